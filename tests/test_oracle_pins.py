@@ -1,0 +1,340 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's general formula: each check is a closed
+form of a special case, an invariant of the method, the paper's own matrix
+recast (Sec. II-C, Eq. 9) evaluated through a library matmul, or a library
+routine (numpy std / mean) applied to the oracle's output.
+"""
+import numpy as np
+import pytest
+
+from paper_1507_07039_amd import inputs as I
+
+RNG = np.random.default_rng(12345)
+
+
+# ---------------------------------------------------------------- Eq. 1 ----
+
+def test_T_self_is_norm(oracle):
+    # T(x, x) = |x|^2 / sqrt(2|x|^2 - |x|^2) = |x|
+    for n in (1, 3, 17, 400):
+        x = RNG.normal(size=n)
+        assert oracle.T(x, x) == pytest.approx(np.linalg.norm(x), rel=1e-14)
+
+
+def test_T_antiparallel_is_minus_norm(oracle):
+    x = RNG.normal(size=33)
+    assert oracle.T(x, -x) == pytest.approx(-np.linalg.norm(x), rel=1e-14)
+
+
+def test_T_orthogonal_is_zero(oracle):
+    x = np.array([1.0, 2.0, 0.0, 0.0, -3.0])
+    y = np.array([0.0, 0.0, 5.0, -1.0, 0.0])
+    assert oracle.T(x, y) == 0.0
+    # orthogonal with overlapping support
+    assert oracle.T([1.0, 1.0], [1.0, -1.0]) == 0.0
+
+
+@pytest.mark.parametrize("c", [2.0, -0.5, 0.25, -3.0, 1.0])
+def test_T_scaled_copy_closed_form(oracle, c):
+    # T(x, c x) = c |x|^2 / sqrt(|x|^2 (1 + c^2 - |c|)) = c |x| / sqrt(1 + c^2 - |c|)
+    x = RNG.normal(size=50)
+    want = c * np.linalg.norm(x) / np.sqrt(1.0 + c * c - abs(c))
+    assert oracle.T(x, c * x) == pytest.approx(want, rel=1e-13)
+
+
+def test_T_zero_vectors(oracle):
+    z = np.zeros(7)
+    assert oracle.T(z, z) == 0.0
+    assert oracle.T(z, RNG.normal(size=7)) == 0.0
+
+
+def test_T_symmetry_and_bounds(oracle):
+    for _ in range(50):
+        n = int(RNG.integers(1, 40))
+        x, y = RNG.normal(size=n), RNG.normal(size=n) * RNG.uniform(0.01, 100)
+        t1, t2 = oracle.T(x, y), oracle.T(y, x)
+        assert t1 == t2  # exact: same summation order, commutative products
+        d = float(np.dot(x, y))
+        assert abs(t1) <= np.sqrt(abs(d)) * (1 + 1e-12)  # den >= |x.y|
+        assert np.sign(t1) == np.sign(d) or d == 0.0
+        # sum of squares minus |x.y| is bounded below by half the sum
+        den = x @ x + y @ y - abs(d)
+        assert den >= 0.5 * (x @ x + y @ y) * (1 - 1e-12)
+
+
+# ------------------------------------------------ Eq. 8 versus Eq. 9 ------
+
+def recast(X, Y):
+    """Eq. 9 (matrix recast): (XY) / sqrt(rowsq(X) 1^T + 1 colsq(Y) - |XY|)."""
+    A = X @ Y
+    B = np.sum(Y ** 2, axis=0)[None, :]
+    Cm = np.sum(X ** 2, axis=1)[:, None]
+    return A / np.sqrt(B + Cm - np.abs(A))
+
+
+@pytest.mark.parametrize("M,K,N", [(1, 1, 1), (3, 5, 7), (40, 400, 40), (40, 40, 400),
+                                   (17, 1, 9), (64, 33, 2), (5, 8, 8), (8, 8, 8)])
+def test_elementwise_matches_matrix_recast(oracle, M, K, N):
+    X = RNG.normal(size=(M, K))
+    Y = RNG.normal(size=(K, N)) * 3.0
+    got = oracle.tanimoto(X, Y)
+    want = recast(X, Y)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-13)
+
+
+def test_entries_match_full_matrix(oracle):
+    X = RNG.normal(size=(23, 31))
+    Y = RNG.normal(size=(31, 45))
+    full = oracle.tanimoto(X, Y)
+    r = RNG.integers(0, 23, size=200)
+    c = RNG.integers(0, 45, size=200)
+    assert np.array_equal(oracle.tanimoto_entries(X, Y, r, c), full[r, c])
+
+
+# ----------------------------------------------------------- Z-score ------
+
+def test_normalize_moments(oracle):
+    M = RNG.exponential(size=(30, 70)) * 5 + 2
+    Z = oracle.normalize(M)
+    assert Z.mean() == pytest.approx(0.0, abs=1e-13)
+    assert Z.std() == pytest.approx(1.0, rel=1e-13)  # numpy std is population std
+    # affine invariance: z-score of a M + b is z-score of M (a > 0)
+    np.testing.assert_allclose(oracle.normalize(3.5 * M - 7.0), Z, atol=1e-12)
+
+
+def test_normalize_identity_closed_form(oracle):
+    for n in (2, 5, 40):
+        Z = oracle.normalize(np.eye(n))
+        mu = 1.0 / n
+        sd = np.sqrt(mu - mu * mu)
+        np.testing.assert_allclose(np.diag(Z), (1 - mu) / sd, rtol=1e-14)
+        off = Z[~np.eye(n, dtype=bool)]
+        np.testing.assert_allclose(off, -mu / sd, rtol=1e-14)
+
+
+def test_normalize_errors(oracle):
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.normalize(np.full((4, 4), 3.0))
+    assert e.value.code == oracle.ERR_DEGENERATE
+    bad = np.ones((3, 3))
+    bad[1, 2] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.normalize(bad)
+    assert e.value.code == oracle.ERR_NONFINITE
+
+
+# --------------------------------------- one iteration: closed forms -----
+
+def test_step_scaled_identity_closed_form(oracle):
+    """P = lam I and C = mu I reduce Eq. 3 and Eq. 4 to closed forms.
+
+    R_ij = T(lam e_i, W_.j) = lam W_ij / sqrt(lam^2 + |W_.j|^2 - lam |W_ij|)
+    A_ij = T(W_i., mu e_j)  = mu W_ij / sqrt(|W_i.|^2 + mu^2 - mu |W_ij|)
+    The first uses column norms of W and the second row norms, so a swapped
+    or transposed operand changes the result.
+    """
+    Ne, Na, lam, mu, a = 5, 9, 3.0, 0.5, 0.1
+    W = RNG.normal(size=(Ne, Na))
+    P, C = lam * np.eye(Ne), mu * np.eye(Na)
+    Wn, Pn, Cn, h, conv = oracle.step(W, P, C, 1, oracle.Options(alpha=a, tol=0.0))
+    col = np.sum(W ** 2, axis=0)[None, :]
+    row = np.sum(W ** 2, axis=1)[:, None]
+    R = lam * W / np.sqrt(lam ** 2 + col - lam * np.abs(W))
+    A = mu * W / np.sqrt(row + mu ** 2 - mu * np.abs(W))
+    Wexp = (1 - a) * W + a / 2 * (A + R)
+    np.testing.assert_allclose(Wn, Wexp, rtol=1e-14, atol=1e-15)
+    assert h == pytest.approx(np.mean(np.abs(Wexp - W)), rel=1e-13)  # Eq. 7
+    assert not conv
+
+
+def test_step_h_undamped_variant(oracle):
+    Ne, Na, a = 4, 6, 0.25
+    W = RNG.normal(size=(Ne, Na))
+    Wn, _, _, h_d, _ = oracle.step(W, np.eye(Ne), np.eye(Na), 1, oracle.Options(alpha=a))
+    _, _, _, h_u, _ = oracle.step(W, np.eye(Ne), np.eye(Na), 1,
+                                  oracle.Options(alpha=a, h_undamped=True))
+    # damped difference is alpha times the undamped one: W' - W = alpha (pred - W)
+    assert h_d == pytest.approx(a * h_u, rel=1e-12)
+
+
+def _offdiag(S):
+    n = S.shape[0]
+    return S[~np.eye(n, dtype=bool)].reshape(n, n - 1)
+
+
+@pytest.mark.parametrize("kw", [{}, {"diag_alpha": False}, {"n_own": True}, {"sigma_from_T": True}])
+def test_step_pc_update_against_recast(oracle, kw):
+    """Eq. 5 off-diagonals against the matrix recast of the NEW W, and Eq. 6
+    diagonals against numpy's population std of the updated off-diagonals."""
+    Ne, Na, a, t = 6, 11, 0.1, 3
+    W = RNG.normal(size=(Ne, Na))
+    P = I.random_symmetric(1, Ne)
+    C = I.random_symmetric(2, Na)
+    opts = oracle.Options(alpha=a, tol=0.0, **kw)
+    Wn, Pn, Cn, h, conv = oracle.step(W, P, C, t, opts)
+    TP = recast(Wn, Wn.T)   # T(W_i., W_m.)
+    TC = recast(Wn.T, Wn)   # T(W_.k, W_.j)
+    offP = ~np.eye(Ne, dtype=bool)
+    offC = ~np.eye(Na, dtype=bool)
+    np.testing.assert_allclose(Pn[offP], ((1 - a) * P + a * TP)[offP], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(Cn[offC], ((1 - a) * C + a * TC)[offC], rtol=1e-12, atol=1e-13)
+    sP = np.std(_offdiag(TP if kw.get("sigma_from_T") else Pn), axis=1)
+    sC = np.std(_offdiag(TC if kw.get("sigma_from_T") else Cn), axis=1)
+    mP = Ne if kw.get("n_own") else Na   # Eq. 6 as printed: N_a for P, N_e for C
+    mC = Na if kw.get("n_own") else Ne
+    g = np.exp(2 * a * t)
+    fa = a if kw.get("diag_alpha", True) else 1.0
+    np.testing.assert_allclose(np.diag(Pn), (1 - a) * np.diag(P) + fa * mP * sP * g, rtol=1e-12)
+    np.testing.assert_allclose(np.diag(Cn), (1 - a) * np.diag(C) + fa * mC * sC * g, rtol=1e-12)
+
+
+def test_step_uses_previous_iterate_for_R_and_A(oracle):
+    """Eq. 2-4: the new W depends on (W, P, C) of the previous iterate only,
+    compared with the recast of both similarities."""
+    Ne, Na, a = 7, 13, 0.3
+    W = RNG.normal(size=(Ne, Na))
+    P = I.random_symmetric(3, Ne)
+    C = I.random_symmetric(4, Na)
+    Wn, *_ = oracle.step(W, P, C, 1, oracle.Options(alpha=a, tol=0.0))
+    np.testing.assert_allclose(Wn, (1 - a) * W + a / 2 * (recast(P, W) + recast(W, C)),
+                               rtol=1e-12, atol=1e-13)
+
+
+def test_scalar_network(oracle):
+    """N_e = N_a = 1: every similarity is a scalar closed form and the
+    off-diagonal sets are empty (sigma = 0), so P and C only decay."""
+    w, p, c, a = 0.7, -1.3, 2.1, 0.2
+    Wn, Pn, Cn, h, conv = oracle.step([[w]], [[p]], [[c]], 5, oracle.Options(alpha=a, tol=0.0))
+    R = p * w / np.sqrt(p * p + w * w - abs(p * w))
+    A = w * c / np.sqrt(w * w + c * c - abs(w * c))
+    assert Wn[0, 0] == pytest.approx((1 - a) * w + a / 2 * (A + R), rel=1e-15)
+    assert Pn[0, 0] == pytest.approx((1 - a) * p, rel=1e-15)
+    assert Cn[0, 0] == pytest.approx((1 - a) * c, rel=1e-15)
+
+
+def test_single_tf_row(oracle):
+    """N_e = 1: C's off-diagonal similarities are scalar T(w_k, w_j)."""
+    Na, a = 5, 0.1
+    w = RNG.normal(size=(1, Na))
+    C = I.random_symmetric(5, Na)
+    Wn, Pn, Cn, h, _ = oracle.step(w, [[1.5]], C, 2, oracle.Options(alpha=a, tol=0.0))
+    x = Wn[0]
+    TC = np.outer(x, x) / np.sqrt(x[:, None] ** 2 + x[None, :] ** 2 - np.abs(np.outer(x, x)))
+    off = ~np.eye(Na, dtype=bool)
+    np.testing.assert_allclose(Cn[off], ((1 - a) * C + a * TC)[off], rtol=1e-13)
+    assert Pn[0, 0] == pytest.approx((1 - a) * 1.5, rel=1e-15)
+
+
+# ------------------------------------------------------------ invariants --
+
+def _cfg1():
+    W0, P0, C0 = I.workload_priors(I.SMALL)
+    W0, P0, C0 = (np.float64(x) for x in I.to_f32(W0, P0, C0))
+    return W0, P0, C0
+
+
+def test_symmetry_preserved_exactly(oracle):
+    W0, P0, C0 = _cfg1()
+    W, P, C = oracle.normalize(W0), oracle.normalize(P0), oracle.normalize(C0)
+    assert np.array_equal(P, P.T) and np.array_equal(C, C.T)
+    for t in range(1, 6):
+        W, P, C, h, _ = oracle.step(W, P, C, t, oracle.Options(tol=0.0))
+        assert np.array_equal(P, P.T)
+        assert np.array_equal(C, C.T)
+        assert h >= 0.0
+
+
+def test_transpose_duality(oracle):
+    """run(W^T, P:=C, C:=P) is run(W, P, C) transposed with P and C swapped:
+    Eq. 3 and Eq. 4 exchange roles, and so do the two halves of Eq. 5-6."""
+    Ne, Na = 6, 15
+    W = oracle.normalize(RNG.normal(size=(Ne, Na)))
+    P = oracle.normalize(I.random_symmetric(7, Ne))
+    C = oracle.normalize(I.random_symmetric(8, Na))
+    o = oracle.Options(max_iter=12, tol=0.0)
+    a = oracle.run(W, P, C, o)
+    b = oracle.run(W.T, C, P, o)
+    np.testing.assert_allclose(b.W, a.W.T, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(b.P, a.C, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(b.C, a.P, rtol=1e-12, atol=1e-12)
+
+
+def test_permutation_equivariance(oracle):
+    """Relabelling TFs and genes (the C-code's label randomisation, Sec. II-D)
+    permutes every output the same way."""
+    Ne, Na = 8, 21
+    W = oracle.normalize(RNG.normal(size=(Ne, Na)))
+    P = oracle.normalize(I.random_symmetric(9, Ne))
+    C = oracle.normalize(I.random_symmetric(10, Na))
+    pe, pa = RNG.permutation(Ne), RNG.permutation(Na)
+    o = oracle.Options(max_iter=10, tol=0.0)
+    a = oracle.run(W, P, C, o)
+    b = oracle.run(W[pe][:, pa], P[pe][:, pe], C[pa][:, pa], o)
+    np.testing.assert_allclose(b.W, a.W[pe][:, pa], rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(b.P, a.P[pe][:, pe], rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(b.C, a.C[pa][:, pa], rtol=1e-11, atol=1e-11)
+
+
+def test_zero_regulatory_network_is_fixed(oracle):
+    """W = 0: every R and A numerator is 0, so W stays 0, h = 0 and the run
+    stops at t = 1 with P and C untouched (Eq. 7 stop rule)."""
+    P = oracle.normalize(I.random_symmetric(11, 5))
+    C = oracle.normalize(I.random_symmetric(12, 9))
+    r = oracle.run(np.zeros((5, 9)), P, C)
+    assert r.iters == 1 and r.h == 0.0 and r.status == oracle.OK
+    assert np.array_equal(r.W, np.zeros((5, 9)))
+    assert np.array_equal(r.P, P) and np.array_equal(r.C, C)
+
+
+def test_converged_state_stays_converged(oracle):
+    W0, P0, C0 = _cfg1()
+    W, P, C = oracle.normalize(W0), oracle.normalize(P0), oracle.normalize(C0)
+    o = oracle.Options(update_last=True)
+    r = oracle.run(W, P, C, o)
+    assert r.status == oracle.OK
+    _, _, _, h, conv = oracle.step(r.W, r.P, r.C, r.iters + 1, o)
+    assert conv and h < r.h
+
+
+def test_restart_equals_straight_run(oracle):
+    """State (W, P, C, t) is the whole state: stopping after k iterations and
+    resuming from t = k gives the same result bit for bit."""
+    W0, P0, C0 = _cfg1()
+    W, P, C = oracle.normalize(W0), oracle.normalize(P0), oracle.normalize(C0)
+    full = oracle.run(W, P, C)
+    part = oracle.run(W, P, C, oracle.Options(max_iter=10))
+    assert part.status == oracle.NOT_CONVERGED and part.iters == 10
+    rest = oracle.run(part.W, part.P, part.C, t0=10)
+    assert rest.iters == full.iters
+    assert np.array_equal(rest.W, full.W) and np.array_equal(rest.C, full.C)
+
+
+def test_iteration_count_near_paper(oracle):
+    """Sec. II-B: with alpha = 0.1 the procedure takes approximately 40
+    iterations (soft pin)."""
+    W0, P0, C0 = _cfg1()
+    r = oracle.run(oracle.normalize(W0), oracle.normalize(P0), oracle.normalize(C0))
+    assert r.status == oracle.OK
+    assert 20 <= r.iters <= 60
+    assert np.all(np.isfinite(r.W))
+    assert r.h_trace[-1] < 1e-3 <= r.h_trace[-2]
+
+
+def test_step_w_entries_match_full_step(oracle):
+    W0, P0, C0 = _cfg1()
+    W, P, C = oracle.normalize(W0), oracle.normalize(P0), oracle.normalize(C0)
+    Wn, *_ = oracle.step(W, P, C, 1)
+    r = RNG.integers(0, W.shape[0], size=300)
+    c = RNG.integers(0, W.shape[1], size=300)
+    np.testing.assert_array_equal(oracle.step_w_entries(W, P, C, 0.1, r, c), Wn[r, c])
+
+
+def test_bad_arguments(oracle):
+    with pytest.raises(ValueError):
+        oracle.step(np.zeros((2, 3)), np.eye(3), np.eye(3), 1)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.step(np.ones((2, 3)), np.eye(2), np.eye(3), 0)
+    assert e.value.code == oracle.ERR_ARG
+    with pytest.raises(oracle.OracleError):
+        oracle.run(np.ones((2, 3)), np.eye(2), np.eye(3), oracle.Options(alpha=0.0))
