@@ -1,0 +1,145 @@
+/*
+ * panda.h -- C ABI of libpanda.so, the MI355X (gfx950) implementation of the
+ * PANDA message-passing iteration in matrix form (Glass, Quackenbush & Kepner,
+ * arXiv 1507.07039).
+ *
+ * Problem (Sec. II-A, II-B).  Three networks: the regulatory network W
+ * (N_e x N_a, transcription factors x genes), the cooperativity network P
+ * (N_e x N_e, symmetric) and the co-regulatory network C (N_a x N_a,
+ * symmetric).  Each iteration t = 1, 2, ... computes
+ *     R = T(P, W), A = T(W, C)                              (Eq. 3, Eq. 4)
+ *     W <- (1 - alpha) W + alpha/2 (A + R)                  (Eq. 2)
+ *     h = mean |W(t) - W(t-1)|, stop when h < tol           (Eq. 7)
+ *     P_im <- (1 - alpha) P_im + alpha T(W_i., W_m.), i != m (Eq. 5)
+ *     C_kj <- (1 - alpha) C_kj + alpha T(W_.k, W_.j), k != j (Eq. 5)
+ *     P_ii, C_jj from the off-diagonal spread of their row   (Eq. 6)
+ * where T(X, Y)_ij = X_i.Y_.j / sqrt(|X_i.|^2 + |Y_.j|^2 - |X_i.Y_.j|)
+ * is the similarity of Eq. 1 in the matrix form of Sec. II-C (Eq. 9).
+ *
+ * Conventions for every entry point:
+ *   - Matrix pointers are DEVICE pointers to row-major, contiguous FP32
+ *     arrays, owned by the caller.  The library never frees them.
+ *   - Work is enqueued on the given HIP stream (NULL = the default stream).
+ *     Calls that return a value computed on the device (h, t, status of a
+ *     normalisation) synchronise that stream before returning.
+ *   - Arguments are validated on the host before any device work; a failed
+ *     validation returns PANDA_ERR_ARG and enqueues nothing.
+ *   - Errors are returned as panda_status; no exception or abort crosses the
+ *     ABI.  panda_last_error() gives a thread-local message for the last
+ *     failure on the calling thread.
+ *   - The workspace is caller-owned device memory of at least the size the
+ *     matching *_workspace_bytes() call returns, aligned to 256 bytes.  The
+ *     library allocates no device memory of its own; a context allocates one
+ *     small pinned host buffer for reading the convergence state.
+ */
+#ifndef PANDA_H
+#define PANDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PANDA_OK = 0,              /* converged (h < tol) or call succeeded         */
+  PANDA_NOT_CONVERGED = 1,   /* max_iter reached; outputs hold the last state */
+  PANDA_ERR_ARG = -1,        /* invalid argument; nothing was enqueued         */
+  PANDA_ERR_DEGENERATE = -2, /* z-score of a constant network (std = 0)        */
+  PANDA_ERR_NONFINITE = -3,  /* NaN or Inf in an input network                 */
+  PANDA_ERR_HIP = -4,        /* a HIP runtime call failed                      */
+  PANDA_ERR_WORKSPACE = -5   /* workspace missing, too small or misaligned     */
+} panda_status;
+
+/* Arithmetic of the similarity products. */
+enum { PANDA_PREC_FP32 = 0 /* FP32 MFMA, FP32 accumulate */ };
+
+/* Run parameters and the readings of the paper where it is ambiguous.
+ * panda_default_options() fills the defaults given in brackets. */
+typedef struct {
+  double alpha;         /* [0.1]  update rate of Eq. 2, 5 and 6, 0 < alpha <= 1   */
+  double tol;           /* [1e-3] stop when h < tol (Sec. II-B)                   */
+  int32_t max_iter;     /* [200]  iteration cap                                   */
+  int32_t diag_alpha;   /* [1]    Eq. 6 increment multiplied by alpha; 0: literal */
+  int32_t sigma_from_T; /* [0]    sigma of Eq. 6 from the damped off-diagonal row;
+                                  1: from the fresh similarity row               */
+  int32_t n_own;        /* [0]    Eq. 6 multiplier N_a for P, N_e for C as printed;
+                                  1: the network's own dimension                 */
+  int32_t h_undamped;   /* [0]    h of Eq. 7 from W(t) - W(t-1); 1: mean |(A+R)/2 - W| */
+  int32_t update_last;  /* [0]    skip the P/C update on the converging iteration */
+  int32_t poll_every;   /* [1]    panda_run reads h back every poll_every iterations */
+  int32_t precision;    /* [PANDA_PREC_FP32]                                      */
+} panda_options;
+
+typedef struct panda_ctx panda_ctx;
+
+/* Fill *opt with the defaults listed above. */
+void panda_default_options(panda_options* opt);
+
+/* Z-score normalisation of one network in place (Sec. II-A; NormalizeNetwork
+ * in Sec. II-C): mean and population standard deviation over all rows*cols
+ * entries, then M <- (M - mean) / std.  Reductions in FP64, two passes.
+ * Needs panda_normalize_workspace_bytes() bytes of workspace (a few KB).
+ * Synchronises the stream.  Returns PANDA_ERR_NONFINITE (M untouched) if an
+ * entry is NaN/Inf, PANDA_ERR_DEGENERATE (M untouched) if the standard
+ * deviation is 0. */
+size_t panda_normalize_workspace_bytes(void);
+panda_status panda_normalize(float* M, int64_t rows, int64_t cols, void* workspace,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Similarity matrix of Eq. 1 in the matrix form of Sec. II-C (the paper's
+ * Tfunction): Out[i][j] = T(row i of X, column j of Y) for X (M x K) and
+ * Y (K x N); Out is M x N.  FP32 MFMA products, FP64 norms and denominator,
+ * T := 0 where the denominator is 0 (both vectors zero).  M, K, N >= 1.
+ * Needs panda_tanimoto_workspace_bytes(M, K, N) bytes of workspace. */
+size_t panda_tanimoto_workspace_bytes(int64_t M, int64_t K, int64_t N);
+panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K, int64_t N,
+                            float* Out, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace for a context or panda_run on an N_e x N_a problem. */
+size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt);
+
+/* Create a context holding the message-passing state (W, P, C, t) inside the
+ * workspace (Sec. II-B, PANDA()).  opt NULL = defaults.  Ne, Na >= 1. */
+panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, void* workspace,
+                              size_t ws_bytes, hipStream_t stream, panda_ctx** out);
+
+/* Load the state: W (Ne x Na), P (Ne x Ne), C (Na x Na), already normalised,
+ * and the number t of iterations already done (0 for a fresh start; the
+ * diagonal rule of Eq. 6 depends on t).  P or C NULL means the identity
+ * network, z-scored like any other (Sec. II-A; fails with
+ * PANDA_ERR_DEGENERATE for a 1 x 1 identity). */
+panda_status panda_ctx_load(panda_ctx* ctx, const float* W, const float* P, const float* C,
+                            int32_t t);
+
+/* One message-passing iteration (Eq. 2-7).  Synchronises the stream and
+ * returns h and the iteration number t.  Once h < tol the state is frozen:
+ * further calls change nothing and return PANDA_OK with the same h and t. */
+panda_status panda_iterate(panda_ctx* ctx, double* h, int32_t* t);
+
+/* Copy the current state out (any pointer may be NULL to skip it). */
+panda_status panda_ctx_store(panda_ctx* ctx, float* W, float* P, float* C, double* h, int32_t* t);
+
+void panda_ctx_destroy(panda_ctx* ctx);
+
+/* The whole message-passing procedure (PANDA() of Sec. II-C): from the
+ * normalised priors (W0, P0, C0; P0/C0 NULL = identity) iterate until h < tol
+ * or max_iter iterations, then write the final networks to W, P, C (may alias
+ * the inputs).  alpha, tol and max_iter override the same fields of opt.
+ * Returns PANDA_OK (converged) or PANDA_NOT_CONVERGED; *iters = final t,
+ * *h = final h.  Blocks only to read h back every poll_every iterations. */
+panda_status panda_run(const float* W0, const float* P0, const float* C0, int64_t Ne, int64_t Na,
+                       double alpha, double tol, int32_t max_iter, float* W, float* P, float* C,
+                       void* workspace, size_t ws_bytes, const panda_options* opt,
+                       int32_t* iters, double* h, hipStream_t stream);
+
+const char* panda_status_string(panda_status s);
+const char* panda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PANDA_H */

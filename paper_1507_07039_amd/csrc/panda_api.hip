@@ -1,0 +1,434 @@
+// Host side of libpanda.so: argument checks, workspace layout, the
+// iteration sequence of Sec. II-B and the C ABI declared in include/panda.h.
+#include "panda.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "panda_internal.h"
+
+using namespace panda;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+panda_status fail(panda_status st, const char* fmt, const char* what = "") {
+  snprintf(g_err, sizeof g_err, fmt, what);
+  return st;
+}
+
+panda_status hip_fail(hipError_t e, const char* where) {
+  snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+  return PANDA_ERR_HIP;
+}
+
+#define HIP_TRY(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+constexpr size_t kZsScratch = kZsBlocks + 8;  // doubles
+
+Rule rule_of(const panda_options& o) {
+  Rule r;
+  r.alpha = o.alpha;
+  r.tol = o.tol;
+  r.diag_alpha = o.diag_alpha;
+  r.sigma_from_T = o.sigma_from_T;
+  r.n_own = o.n_own;
+  r.h_undamped = o.h_undamped;
+  r.update_last = o.update_last;
+  return r;
+}
+
+panda_status check_options(const panda_options& o) {
+  if (!(o.alpha > 0.0) || !(o.alpha <= 1.0)) return fail(PANDA_ERR_ARG, "alpha must be in (0, 1]%s");
+  if (!(o.tol >= 0.0) || !isfinite(o.tol)) return fail(PANDA_ERR_ARG, "tol must be finite and >= 0%s");
+  if (o.max_iter < 1) return fail(PANDA_ERR_ARG, "max_iter must be >= 1%s");
+  if (o.poll_every < 1) return fail(PANDA_ERR_ARG, "poll_every must be >= 1%s");
+  if (o.precision != PANDA_PREC_FP32) return fail(PANDA_ERR_ARG, "unknown precision%s");
+  return PANDA_OK;
+}
+
+// Dimensions that keep every index and the tiled grids within range.
+bool dims_ok(int64_t Ne, int64_t Na) {
+  return Ne >= 1 && Na >= 1 && Ne <= (1 << 16) && Na <= (1 << 18);
+}
+
+}  // namespace
+
+struct panda_ctx {
+  int64_t Ne, Na, Nep, Nap;
+  panda_options opt;
+  Rule rule;
+  hipStream_t stream;
+  float* W[2];
+  float* R;
+  float* P;
+  float* C;
+  float* Tside;
+  float* ppart;
+  double* pnrm;
+  double* hpart;
+  double2* cstat;
+  double* zs;
+  DevState* st;
+  DevState* host;  // pinned
+  int splits;
+  int64_t nh;
+  int32_t t0;
+  int64_t executed;  // iterations known to have run since load
+  int64_t enqueued;  // iterations enqueued since load
+  bool loaded;
+};
+
+namespace {
+
+// Workspace layout shared by the size query and the context.
+size_t layout(int64_t Ne, int64_t Na, panda_ctx* c, char* base) {
+  const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
+  Carver cv{base};
+  const size_t nw = (size_t)Nep * (size_t)Nap;
+  float* w0 = cv.take<float>(nw);
+  float* w1 = cv.take<float>(nw);
+  float* r = cv.take<float>(nw);
+  float* p = cv.take<float>((size_t)Nep * Nep);
+  float* cc = cv.take<float>((size_t)Nap * Nap);
+  float* ts = cv.take<float>((size_t)Nep * Nep);
+  const int splits = coop_splits(Nep, Nap);
+  float* pp = cv.take<float>((size_t)splits * Nep * Nep);
+  double* pn = cv.take<double>((size_t)splits * Nep);
+  const int64_t nh = avail_wupdate_blocks(Nep, Nap);
+  double* hp = cv.take<double>((size_t)nh);
+  double2* cs = cv.take<double2>((size_t)coreg_slots(Nap) * Nap);
+  double* zs = cv.take<double>(kZsScratch);
+  DevState* st = cv.take<DevState>(1);
+  if (c) {
+    c->Nep = Nep;
+    c->Nap = Nap;
+    c->W[0] = w0;
+    c->W[1] = w1;
+    c->R = r;
+    c->P = p;
+    c->C = cc;
+    c->Tside = ts;
+    c->ppart = pp;
+    c->pnrm = pn;
+    c->splits = splits;
+    c->hpart = hp;
+    c->nh = nh;
+    c->cstat = cs;
+    c->zs = zs;
+    c->st = st;
+  }
+  return cv.off;
+}
+
+// z-score of a strided matrix using `scratch`; synchronises the stream.
+panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, double* scratch,
+                    hipStream_t s) {
+  HIP_TRY(launch_zscore_stats(M, rows, cols, ld, scratch, s));
+  double tail[3];
+  HIP_TRY(hipMemcpyAsync(tail, scratch + kZsBlocks, sizeof tail, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (tail[2] != 0.0) return fail(PANDA_ERR_NONFINITE, "network contains NaN or Inf%s");
+  if (!(tail[1] > 0.0)) return fail(PANDA_ERR_DEGENERATE, "network is constant (std = 0)%s");
+  HIP_TRY(launch_zscore_apply(M, rows, cols, ld, scratch, s));
+  return PANDA_OK;
+}
+
+// Enqueue one iteration: R, A + W update, h, P update, C update, diagonals.
+panda_status enqueue_iteration(panda_ctx* c) {
+  const int64_t k = c->executed + (c->enqueued - c->executed);
+  float* Wold = c->W[k & 1];
+  float* Wnew = c->W[(k + 1) & 1];
+  hipStream_t s = c->stream;
+  const int32_t* active = &c->st->active;
+  const int32_t* run_pc = &c->st->run_pc;
+  // Eq. 3: R = T(P, W), K = N_e
+  HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
+                                c->R, c->Nap, active, s));
+  // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
+  HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
+                               c->rule, c->hpart, active, s));
+  HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
+  // Eq. 5, P: T(W_i., W_m.) of the new W
+  HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, c->pnrm, run_pc,
+                              s));
+  HIP_TRY(launch_coop_finalize(c->ppart, c->pnrm, c->splits, c->P, c->Nep, c->Ne, c->rule,
+                               c->rule.sigma_from_T ? c->Tside : nullptr, run_pc, s));
+  // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
+  HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->rule,
+                              c->cstat, run_pc, s));
+  // Eq. 6
+  HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->C,
+                           c->Nap, c->Na, c->cstat, coreg_slots(c->Nap), c->rule, c->st, s));
+  c->enqueued += 1;
+  return PANDA_OK;
+}
+
+// Read the device state back (synchronises the stream).
+panda_status read_state(panda_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->executed = c->host->t - c->t0;
+  return PANDA_OK;
+}
+
+panda_status copy_in(float* dst, int64_t ldd, const float* src, int64_t rows, int64_t cols,
+                     hipStream_t s) {
+  HIP_TRY(hipMemcpy2DAsync(dst, (size_t)ldd * 4, src, (size_t)cols * 4, (size_t)cols * 4,
+                           (size_t)rows, hipMemcpyDeviceToDevice, s));
+  return PANDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void panda_default_options(panda_options* o) {
+  if (!o) return;
+  o->alpha = 0.1;
+  o->tol = 1e-3;
+  o->max_iter = 200;
+  o->diag_alpha = 1;
+  o->sigma_from_T = 0;
+  o->n_own = 0;
+  o->h_undamped = 0;
+  o->update_last = 0;
+  o->poll_every = 1;
+  o->precision = PANDA_PREC_FP32;
+}
+
+const char* panda_status_string(panda_status s) {
+  switch (s) {
+    case PANDA_OK: return "ok";
+    case PANDA_NOT_CONVERGED: return "not converged";
+    case PANDA_ERR_ARG: return "invalid argument";
+    case PANDA_ERR_DEGENERATE: return "degenerate network (std = 0)";
+    case PANDA_ERR_NONFINITE: return "non-finite input";
+    case PANDA_ERR_HIP: return "HIP runtime error";
+    case PANDA_ERR_WORKSPACE: return "workspace too small or misaligned";
+  }
+  return "unknown status";
+}
+
+const char* panda_last_error(void) { return g_err; }
+
+size_t panda_normalize_workspace_bytes(void) { return align_up(kZsScratch * sizeof(double)); }
+
+panda_status panda_normalize(float* M, int64_t rows, int64_t cols, void* workspace,
+                             size_t ws_bytes, hipStream_t stream) {
+  if (!M || rows < 1 || cols < 1) return fail(PANDA_ERR_ARG, "normalize: bad matrix%s");
+  if (!workspace || ws_bytes < panda_normalize_workspace_bytes() ||
+      (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(PANDA_ERR_WORKSPACE, "normalize: workspace too small or misaligned%s");
+  return zscore(M, rows, cols, cols, static_cast<double*>(workspace), stream);
+}
+
+size_t panda_tanimoto_workspace_bytes(int64_t M, int64_t K, int64_t N) {
+  if (M < 1 || K < 1 || N < 1) return 0;
+  const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kBK), Np = round_up(N, kPadA);
+  return align_up((size_t)Mp * Kp * 4) + align_up((size_t)Kp * Np * 4) +
+         align_up((size_t)Mp * Np * 4);
+}
+
+panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K, int64_t N,
+                            float* Out, void* workspace, size_t ws_bytes, hipStream_t s) {
+  if (!X || !Y || !Out || M < 1 || K < 1 || N < 1 || M > (1 << 20) || N > (1 << 20) ||
+      K > (1 << 20))
+    return fail(PANDA_ERR_ARG, "tanimoto: bad arguments%s");
+  const size_t need = panda_tanimoto_workspace_bytes(M, K, N);
+  if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(PANDA_ERR_WORKSPACE, "tanimoto: workspace too small or misaligned%s");
+  const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kBK), Np = round_up(N, kPadA);
+  Carver cv{static_cast<char*>(workspace)};
+  float* Xp = cv.take<float>((size_t)Mp * Kp);
+  float* Yp = cv.take<float>((size_t)Kp * Np);
+  float* Op = cv.take<float>((size_t)Mp * Np);
+  HIP_TRY(hipMemsetAsync(Xp, 0, (size_t)Mp * Kp * 4, s));
+  HIP_TRY(hipMemsetAsync(Yp, 0, (size_t)Kp * Np * 4, s));
+  panda_status st = copy_in(Xp, Kp, X, M, K, s);
+  if (st != PANDA_OK) return st;
+  st = copy_in(Yp, Np, Y, K, N, s);
+  if (st != PANDA_OK) return st;
+  HIP_TRY(launch_tanimoto_store(Xp, Kp, Yp, Np, Mp, Np, Kp, M, N, Op, Np, nullptr, s));
+  HIP_TRY(hipMemcpy2DAsync(Out, (size_t)N * 4, Op, (size_t)Np * 4, (size_t)N * 4, (size_t)M,
+                           hipMemcpyDeviceToDevice, s));
+  return PANDA_OK;
+}
+
+size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt) {
+  (void)opt;
+  if (!dims_ok(Ne, Na)) return 0;
+  return layout(Ne, Na, nullptr, nullptr);
+}
+
+panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, void* workspace,
+                              size_t ws_bytes, hipStream_t stream, panda_ctx** out) {
+  if (!out) return fail(PANDA_ERR_ARG, "ctx_create: out is NULL%s");
+  *out = nullptr;
+  if (!dims_ok(Ne, Na)) return fail(PANDA_ERR_ARG, "ctx_create: bad dimensions%s");
+  panda_options o;
+  if (opt)
+    o = *opt;
+  else
+    panda_default_options(&o);
+  panda_status st = check_options(o);
+  if (st != PANDA_OK) return st;
+  if (!workspace || ws_bytes < panda_workspace_bytes(Ne, Na, &o) ||
+      (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(PANDA_ERR_WORKSPACE, "ctx_create: workspace too small or misaligned%s");
+  panda_ctx* c = new (std::nothrow) panda_ctx();
+  if (!c) return fail(PANDA_ERR_ARG, "ctx_create: out of host memory%s");
+  c->Ne = Ne;
+  c->Na = Na;
+  c->opt = o;
+  c->rule = rule_of(o);
+  c->stream = stream;
+  layout(Ne, Na, c, static_cast<char*>(workspace));
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(DevState),
+                               hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  c->loaded = false;
+  *out = c;
+  return PANDA_OK;
+}
+
+void panda_ctx_destroy(panda_ctx* c) {
+  if (!c) return;
+  if (c->host) (void)hipHostFree(c->host);
+  delete c;
+}
+
+panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const float* C,
+                            int32_t t) {
+  if (!c || !W || t < 0) return fail(PANDA_ERR_ARG, "ctx_load: bad arguments%s");
+  hipStream_t s = c->stream;
+  const int64_t Ne = c->Ne, Na = c->Na, Nep = c->Nep, Nap = c->Nap;
+  HIP_TRY(hipMemsetAsync(c->W[0], 0, (size_t)Nep * Nap * 4, s));
+  HIP_TRY(hipMemsetAsync(c->W[1], 0, (size_t)Nep * Nap * 4, s));
+  HIP_TRY(hipMemsetAsync(c->P, 0, (size_t)Nep * Nep * 4, s));
+  HIP_TRY(hipMemsetAsync(c->C, 0, (size_t)Nap * Nap * 4, s));
+  HIP_TRY(hipMemsetAsync(c->Tside, 0, (size_t)Nep * Nep * 4, s));
+  panda_status st = copy_in(c->W[0], Nap, W, Ne, Na, s);
+  if (st != PANDA_OK) return st;
+  if (P) {
+    st = copy_in(c->P, Nep, P, Ne, Ne, s);
+  } else {
+    HIP_TRY(launch_fill_identity(c->P, Ne, Nep, s));
+    st = zscore(c->P, Ne, Ne, Nep, c->zs, s);
+  }
+  if (st != PANDA_OK) return st;
+  if (C) {
+    st = copy_in(c->C, Nap, C, Na, Na, s);
+  } else {
+    HIP_TRY(launch_fill_identity(c->C, Na, Nap, s));
+    st = zscore(c->C, Na, Na, Nap, c->zs, s);
+  }
+  if (st != PANDA_OK) return st;
+  HIP_TRY(launch_state_init(c->st, t, s));
+  c->t0 = t;
+  c->executed = 0;
+  c->enqueued = 0;
+  c->host->h = 0.0;
+  c->host->t = t;
+  c->host->active = 1;
+  c->host->conv = 0;
+  c->loaded = true;
+  return PANDA_OK;
+}
+
+panda_status panda_iterate(panda_ctx* c, double* h, int32_t* t) {
+  if (!c || !c->loaded) return fail(PANDA_ERR_ARG, "iterate: context not loaded%s");
+  if (c->host->active) {
+    panda_status st = enqueue_iteration(c);
+    if (st != PANDA_OK) return st;
+  }
+  panda_status st = read_state(c);
+  if (st != PANDA_OK) return st;
+  c->enqueued = c->executed;
+  if (h) *h = c->host->h;
+  if (t) *t = c->host->t;
+  return PANDA_OK;
+}
+
+panda_status panda_ctx_store(panda_ctx* c, float* W, float* P, float* C, double* h, int32_t* t) {
+  if (!c || !c->loaded) return fail(PANDA_ERR_ARG, "ctx_store: context not loaded%s");
+  panda_status st = read_state(c);
+  if (st != PANDA_OK) return st;
+  hipStream_t s = c->stream;
+  const float* Wc = c->W[c->executed & 1];
+  if (W)
+    HIP_TRY(hipMemcpy2DAsync(W, (size_t)c->Na * 4, Wc, (size_t)c->Nap * 4, (size_t)c->Na * 4,
+                             (size_t)c->Ne, hipMemcpyDeviceToDevice, s));
+  if (P)
+    HIP_TRY(hipMemcpy2DAsync(P, (size_t)c->Ne * 4, c->P, (size_t)c->Nep * 4, (size_t)c->Ne * 4,
+                             (size_t)c->Ne, hipMemcpyDeviceToDevice, s));
+  if (C)
+    HIP_TRY(hipMemcpy2DAsync(C, (size_t)c->Na * 4, c->C, (size_t)c->Nap * 4, (size_t)c->Na * 4,
+                             (size_t)c->Na, hipMemcpyDeviceToDevice, s));
+  if (h) *h = c->host->h;
+  if (t) *t = c->host->t;
+  return PANDA_OK;
+}
+
+panda_status panda_run(const float* W0, const float* P0, const float* C0, int64_t Ne, int64_t Na,
+                       double alpha, double tol, int32_t max_iter, float* W, float* P, float* C,
+                       void* workspace, size_t ws_bytes, const panda_options* opt,
+                       int32_t* iters, double* h, hipStream_t stream) {
+  if (!W0 || !W || !P || !C) return fail(PANDA_ERR_ARG, "run: NULL matrix pointer%s");
+  panda_options o;
+  if (opt)
+    o = *opt;
+  else
+    panda_default_options(&o);
+  o.alpha = alpha;
+  o.tol = tol;
+  o.max_iter = max_iter;
+  panda_ctx* c = nullptr;
+  panda_status st = panda_ctx_create(Ne, Na, &o, workspace, ws_bytes, stream, &c);
+  if (st != PANDA_OK) return st;
+  st = panda_ctx_load(c, W0, P0, C0, 0);
+  if (st == PANDA_OK) {
+    // Enqueue ahead and read h back every poll_every iterations; iterations
+    // enqueued past convergence are no-ops on the device.
+    while (st == PANDA_OK && c->enqueued < o.max_iter) {
+      st = enqueue_iteration(c);
+      if (st != PANDA_OK) break;
+      if (c->enqueued % o.poll_every == 0 || c->enqueued == o.max_iter) {
+        st = read_state(c);
+        if (st != PANDA_OK || !c->host->active) break;
+      }
+    }
+  }
+  if (st == PANDA_OK) st = panda_ctx_store(c, W, P, C, h, iters);
+  if (st == PANDA_OK && c->host->active) st = PANDA_NOT_CONVERGED;
+  panda_ctx_destroy(c);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+// Element-wise and reduction kernels of the PANDA iteration: the h of Eq. 7,
+// the second half of the P update (Eq. 5), the diagonal rule of Eq. 6 and the
+// z-score normalisation of Sec. II-A.  All reductions are FP64 and run in a
+// fixed order, so results do not depend on scheduling.
+#include "panda_internal.h"
+
+namespace panda {
+namespace {
+
+constexpr int kRT = 256;  // threads per block for the kernels in this file
+
+// Sum of one double per thread over a 256-thread block, fixed order.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// h = (1 / count) * sum of the per-tile partials (Eq. 7); advance t and set
+// the gates of the rest of this iteration and of the next one.
+__global__ __launch_bounds__(kRT) void k_finish_h(const double* __restrict__ hpart, int64_t n,
+                                                  int64_t count, DevState* st, double tol,
+                                                  int32_t update_last) {
+  __shared__ double red[4];
+  if (st->active == 0) {  // converged earlier: this iteration is a no-op
+    if (threadIdx.x == 0) st->run_pc = 0;
+    return;
+  }
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRT) s += hpart[i];
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double h = tot / (double)count;
+    st->h = h;
+    st->t = st->t + 1;
+    const int conv = h < tol;
+    st->conv = conv;
+    st->run_pc = (!conv || update_last) ? 1 : 0;
+    if (conv) st->active = 0;
+  }
+}
+
+// P update, second half (Eq. 5): for every i < j < Ne sum the split-K
+// partial products and norms, form T(W_i., W_j.) and write the damped value
+// at (i, j) and (j, i).
+__global__ __launch_bounds__(kRT) void k_coop_finalize(
+    const float* __restrict__ part, const double* __restrict__ pnrm, int splits, int64_t Nep,
+    float* __restrict__ P, int64_t ldp, int64_t Ne, double alpha, float* __restrict__ Tside,
+    const int32_t* gate) {
+  if (*gate == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x;
+  if (e >= Ne * Ne) return;
+  const int64_t i = e / Ne, j = e % Ne;
+  if (i >= j) return;
+  double dot = 0.0, ni = 0.0, nj = 0.0;
+  for (int s = 0; s < splits; ++s) {
+    dot += (double)part[(int64_t)s * Nep * Nep + i * Nep + j];
+    ni += pnrm[(int64_t)s * Nep + i];
+    nj += pnrm[(int64_t)s * Nep + j];
+  }
+  const double den = ni + nj - fabs(dot);
+  const double tv = den > 0.0 ? dot / sqrt(den) : 0.0;
+  const float v = (float)((1.0 - alpha) * (double)P[i * ldp + j] + alpha * tv);
+  P[i * ldp + j] = v;
+  P[j * ldp + i] = v;
+  if (Tside) {
+    Tside[i * ldp + j] = (float)tv;
+    Tside[j * ldp + i] = (float)tv;
+  }
+}
+
+// Eq. 6 for both networks.  Blocks [0, Ne): row i of P, population std of
+// its off-diagonal entries by two passes over the row.  Remaining blocks:
+// one thread per row of C, from the per-slot (sum, sum of squares) written
+// by the C update.  New diagonal = (1 - alpha) old + f * mult * sigma *
+// exp(2 alpha t), f = alpha (default reading) or 1 (literal Eq. 6).
+__global__ __launch_bounds__(kRT) void k_diagonals(
+    float* __restrict__ P, int64_t ldp, int64_t Ne, const float* __restrict__ Tside,
+    float* __restrict__ C, int64_t ldc, int64_t Na, const double2* __restrict__ cstat,
+    int64_t nslots, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st) {
+  __shared__ double red[4];
+  if (st->run_pc == 0) return;
+  const double g = exp(2.0 * alpha * (double)st->t);
+  const double f = diag_alpha ? alpha : 1.0;
+  if ((int64_t)blockIdx.x < Ne) {
+    const int64_t i = blockIdx.x;
+    const float* row = (Tside ? Tside : P) + i * ldp;
+    double s = 0.0;
+    for (int64_t m = threadIdx.x; m < Ne; m += kRT)
+      if (m != i) s += row[m];
+    const double n = (double)(Ne - 1);
+    const double mean = Ne > 1 ? block_sum(s, red) / n : 0.0;
+    double q = 0.0;
+    for (int64_t m = threadIdx.x; m < Ne; m += kRT)
+      if (m != i) q += ((double)row[m] - mean) * ((double)row[m] - mean);
+    const double var = Ne > 1 ? block_sum(q, red) / n : 0.0;
+    if (threadIdx.x == 0) {
+      const double mult = n_own ? (double)Ne : (double)Na;
+      const double d = (double)P[i * ldp + i];
+      P[i * ldp + i] = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
+    }
+    return;
+  }
+  const int64_t r = ((int64_t)blockIdx.x - Ne) * kRT + threadIdx.x;
+  if (r >= Na) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t sl = 0; sl < nslots; ++sl) {  // slot stride = ldc (both are the padded N_a)
+    const double2 v = cstat[sl * ldc + r];
+    s1 += v.x;
+    s2 += v.y;
+  }
+  double var = 0.0;
+  if (Na > 1) {
+    const double n = (double)(Na - 1), mean = s1 / n;
+    var = s2 / n - mean * mean;
+    if (var < 0.0) var = 0.0;
+  }
+  const double mult = n_own ? (double)Na : (double)Ne;
+  const double d = (double)C[r * ldc + r];
+  C[r * ldc + r] = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
+}
+
+// ---- z-score --------------------------------------------------------------
+// scratch layout: [0, kZsBlocks) block partials, then
+// [kZsBlocks + 0] mean, [+1] std, [+2] 1.0 if any entry is NaN or Inf.
+__global__ __launch_bounds__(kRT) void k_zs_sum(const float* __restrict__ M, int64_t rows,
+                                                int64_t cols, int64_t ld, double* scratch,
+                                                int pass) {
+  __shared__ double red[4];
+  const int64_t n = rows * cols;
+  const double mean = pass ? scratch[kZsBlocks] : 0.0;
+  double s = 0.0, bad = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kRT) {
+    const double x = (double)M[(e / cols) * ld + e % cols];
+    if (!isfinite(x)) bad += 1.0;
+    s += pass ? (x - mean) * (x - mean) : x;
+  }
+  const double tot = block_sum(s, red);
+  double nb = 0.0;
+  if (!pass) nb = block_sum(bad, red);
+  if (threadIdx.x == 0) {
+    scratch[blockIdx.x] = tot;
+    if (!pass && nb > 0.0) scratch[kZsBlocks + 2] = 1.0;  // every writer stores the same 1.0
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_zs_finish(double* scratch, int64_t n, int pass) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kZsBlocks; i += kRT) s += scratch[i];
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    if (!pass) {
+      scratch[kZsBlocks] = tot / (double)n;
+    } else {
+      scratch[kZsBlocks + 1] = sqrt(tot / (double)n);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_zs_clear(double* scratch) {
+  for (int i = threadIdx.x; i < kZsBlocks + 8; i += kRT) scratch[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kRT) void k_zs_apply(float* __restrict__ M, int64_t rows,
+                                                  int64_t cols, int64_t ld,
+                                                  const double* __restrict__ scratch) {
+  const double mean = scratch[kZsBlocks], sd = scratch[kZsBlocks + 1];
+  const int64_t n = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kRT) {
+    float* p = M + (e / cols) * ld + e % cols;
+    *p = (float)(((double)*p - mean) / sd);
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_fill_identity(float* __restrict__ M, int64_t n,
+                                                       int64_t ld) {
+  const int64_t tot = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * kRT) {
+    const int64_t i = e / n, j = e % n;
+    M[i * ld + j] = (i == j) ? 1.0f : 0.0f;
+  }
+}
+
+__global__ void k_state_init(DevState* st, int32_t t0) {
+  if (threadIdx.x == 0) {
+    st->h = 0.0;
+    st->t = t0;
+    st->active = 1;
+    st->run_pc = 0;
+    st->conv = 0;
+    st->pad[0] = st->pad[1] = 0;
+  }
+}
+
+unsigned grid_for(int64_t n, int64_t cap) {
+  int64_t b = (n + kRT - 1) / kRT;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevState* st, Rule rule,
+                           hipStream_t s) {
+  k_finish_h<<<1, kRT, 0, s>>>(hpart, n, count, st, rule.tol, rule.update_last);
+  return hipGetLastError();
+}
+
+hipError_t launch_coop_finalize(const float* part, const double* pnrm, int splits, float* P,
+                                int64_t ldp, int64_t Ne, Rule rule, float* Tside,
+                                const int32_t* gate, hipStream_t s) {
+  const int64_t n = Ne * Ne;
+  k_coop_finalize<<<dim3((unsigned)((n + kRT - 1) / kRT)), kRT, 0, s>>>(
+      part, pnrm, splits, ldp, P, ldp, Ne, rule.alpha, Tside, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, float* C,
+                            int64_t ldc, int64_t Na, const double2* cstat, int64_t nslots,
+                            Rule rule, const DevState* st, hipStream_t s) {
+  const int64_t nb = Ne + (Na + kRT - 1) / kRT;
+  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, C, ldc, Na, cstat, nslots,
+                                                 rule.alpha, rule.diag_alpha, rule.n_own, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_zscore_stats(const float* M, int64_t rows, int64_t cols, int64_t ld,
+                               double* scratch, hipStream_t s) {
+  const int64_t n = rows * cols;
+  k_zs_clear<<<1, kRT, 0, s>>>(scratch);
+  k_zs_sum<<<kZsBlocks, kRT, 0, s>>>(M, rows, cols, ld, scratch, 0);
+  k_zs_finish<<<1, kRT, 0, s>>>(scratch, n, 0);
+  k_zs_sum<<<kZsBlocks, kRT, 0, s>>>(M, rows, cols, ld, scratch, 1);
+  k_zs_finish<<<1, kRT, 0, s>>>(scratch, n, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_zscore_apply(float* M, int64_t rows, int64_t cols, int64_t ld,
+                               const double* scratch, hipStream_t s) {
+  k_zs_apply<<<grid_for(rows * cols, 4096), kRT, 0, s>>>(M, rows, cols, ld, scratch);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_identity(float* M, int64_t n, int64_t ld, hipStream_t s) {
+  k_fill_identity<<<grid_for(n * n, 4096), kRT, 0, s>>>(M, n, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(DevState* st, int32_t t0, hipStream_t s) {
+  k_state_init<<<1, 64, 0, s>>>(st, t0);
+  return hipGetLastError();
+}
+
+}  // namespace panda

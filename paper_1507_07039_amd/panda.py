@@ -1,0 +1,245 @@
+"""Thin Python binding of libpanda.so (argument marshalling only).
+
+Every step of the message-passing path runs in the HIP kernels of the
+library; this module checks tensor placement, passes device pointers and the
+current HIP stream, and turns status codes into exceptions.  PyTorch is used
+only to own device memory and streams.  There is no CPU fallback: if the
+library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpanda.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_DEGENERATE, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5
+
+# Every extern "C" entry point declared in include/panda.h.
+EXPORTS = (
+    "panda_default_options", "panda_normalize_workspace_bytes", "panda_normalize",
+    "panda_tanimoto_workspace_bytes", "panda_tanimoto", "panda_workspace_bytes",
+    "panda_ctx_create", "panda_ctx_load", "panda_iterate", "panda_ctx_store",
+    "panda_ctx_destroy", "panda_run", "panda_status_string", "panda_last_error",
+)
+
+
+class PandaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"panda status {code}: {msg}")
+        self.code = code
+
+
+class Options(ct.Structure):
+    """Mirror of panda_options (include/panda.h)."""
+    _fields_ = [("alpha", ct.c_double), ("tol", ct.c_double), ("max_iter", ct.c_int32),
+                ("diag_alpha", ct.c_int32), ("sigma_from_T", ct.c_int32),
+                ("n_own", ct.c_int32), ("h_undamped", ct.c_int32),
+                ("update_last", ct.c_int32), ("poll_every", ct.c_int32),
+                ("precision", ct.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpanda.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1507_07039_amd/build.py")
+    lib = ct.CDLL(path)
+    vp, sz, i64, i32, dbl = ct.c_void_p, ct.c_size_t, ct.c_int64, ct.c_int32, ct.c_double
+    op = ct.POINTER(Options)
+    sig = {
+        "panda_default_options": (None, [op]),
+        "panda_normalize_workspace_bytes": (sz, []),
+        "panda_normalize": (ct.c_int, [vp, i64, i64, vp, sz, vp]),
+        "panda_tanimoto_workspace_bytes": (sz, [i64, i64, i64]),
+        "panda_tanimoto": (ct.c_int, [vp, vp, i64, i64, i64, vp, vp, sz, vp]),
+        "panda_workspace_bytes": (sz, [i64, i64, op]),
+        "panda_ctx_create": (ct.c_int, [i64, i64, op, vp, sz, vp, ct.POINTER(vp)]),
+        "panda_ctx_load": (ct.c_int, [vp, vp, vp, vp, i32]),
+        "panda_iterate": (ct.c_int, [vp, ct.POINTER(dbl), ct.POINTER(i32)]),
+        "panda_ctx_store": (ct.c_int, [vp, vp, vp, vp, ct.POINTER(dbl), ct.POINTER(i32)]),
+        "panda_ctx_destroy": (None, [vp]),
+        "panda_run": (ct.c_int, [vp, vp, vp, i64, i64, dbl, dbl, i32, vp, vp, vp, vp, sz, op,
+                                 ct.POINTER(i32), ct.POINTER(dbl), vp]),
+        "panda_status_string": (ct.c_char_p, [ct.c_int]),
+        "panda_last_error": (ct.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load_library().panda_default_options(ct.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _check(code: int, allow=(OK,)) -> int:
+    if code not in allow:
+        lib = load_library()
+        raise PandaError(code, lib.panda_last_error().decode())
+    return code
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libpanda needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _dev(t, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _stream():
+    return ct.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def workspace(nbytes: int):
+    """Caller-owned device workspace (256-byte aligned by the caching allocator)."""
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+def normalize(M) -> None:
+    """Z-score the network M in place (panda_normalize)."""
+    lib = load_library()
+    rows, cols = M.shape
+    ws = workspace(lib.panda_normalize_workspace_bytes())
+    _check(lib.panda_normalize(_dev(M, "M"), rows, cols, ws.data_ptr(), ws.numel(), _stream()))
+
+
+def tanimoto(X, Y):
+    """Out = T(X, Y) (panda_tanimoto, the paper's Tfunction)."""
+    torch = _torch()
+    lib = load_library()
+    M, K = X.shape
+    K2, N = Y.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    out = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    ws = workspace(lib.panda_tanimoto_workspace_bytes(M, K, N))
+    _check(lib.panda_tanimoto(_dev(X, "X"), _dev(Y, "Y"), M, K, N, out.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream()))
+    return out
+
+
+def workspace_bytes(Ne: int, Na: int, opts: Options | None = None) -> int:
+    o = opts or default_options()
+    return load_library().panda_workspace_bytes(Ne, Na, ct.byref(o))
+
+
+class Context:
+    """Message-passing state (W, P, C, t) held in a caller-owned workspace."""
+
+    def __init__(self, Ne: int, Na: int, opts: Options | None = None, ws=None):
+        self.lib = load_library()
+        self.Ne, self.Na = int(Ne), int(Na)
+        self.opts = opts or default_options()
+        need = workspace_bytes(Ne, Na, self.opts)
+        if need == 0:
+            raise PandaError(ERR_ARG, "bad dimensions")
+        self.ws = ws if ws is not None else workspace(need)
+        h = ct.c_void_p()
+        _check(self.lib.panda_ctx_create(self.Ne, self.Na, ct.byref(self.opts), self.ws.data_ptr(),
+                                         self.ws.numel(), _stream(), ct.byref(h)))
+        self.h = h
+
+    def load(self, W, P=None, C=None, t: int = 0):
+        pw = _dev(W, "W", (self.Ne, self.Na))
+        pp = None if P is None else _dev(P, "P", (self.Ne, self.Ne))
+        pc = None if C is None else _dev(C, "C", (self.Na, self.Na))
+        _check(self.lib.panda_ctx_load(self.h, pw, pp, pc, int(t)))
+
+    def iterate(self):
+        """One iteration; returns (h, t)."""
+        hv, tv = ct.c_double(), ct.c_int32()
+        _check(self.lib.panda_iterate(self.h, ct.byref(hv), ct.byref(tv)))
+        return hv.value, tv.value
+
+    def store(self, W=None, P=None, C=None):
+        """Copy the state into the given tensors; returns (h, t)."""
+        hv, tv = ct.c_double(), ct.c_int32()
+        pw = None if W is None else _dev(W, "W", (self.Ne, self.Na))
+        pp = None if P is None else _dev(P, "P", (self.Ne, self.Ne))
+        pc = None if C is None else _dev(C, "C", (self.Na, self.Na))
+        _check(self.lib.panda_ctx_store(self.h, pw, pp, pc, ct.byref(hv), ct.byref(tv)))
+        return hv.value, tv.value
+
+    def state(self):
+        torch = _torch()
+        W = torch.empty((self.Ne, self.Na), dtype=torch.float32, device="cuda")
+        P = torch.empty((self.Ne, self.Ne), dtype=torch.float32, device="cuda")
+        C = torch.empty((self.Na, self.Na), dtype=torch.float32, device="cuda")
+        h, t = self.store(W, P, C)
+        return W, P, C, h, t
+
+    def close(self):
+        if self.h:
+            self.lib.panda_ctx_destroy(self.h)
+            self.h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class RunResult:
+    W: object
+    P: object
+    C: object
+    iters: int
+    h: float
+    status: int
+
+
+def run(W0, P0=None, C0=None, alpha: float = 0.1, tol: float = 1e-3, max_iter: int = 200,
+        opts: Options | None = None, ws=None, out=None) -> RunResult:
+    """panda_run: message passing from normalised priors (P0/C0 None = identity)."""
+    torch = _torch()
+    lib = load_library()
+    Ne, Na = W0.shape
+    o = opts or default_options()
+    if out is None:
+        out = (torch.empty((Ne, Na), dtype=torch.float32, device="cuda"),
+               torch.empty((Ne, Ne), dtype=torch.float32, device="cuda"),
+               torch.empty((Na, Na), dtype=torch.float32, device="cuda"))
+    W, P, C = out
+    if ws is None:
+        ws = workspace(workspace_bytes(Ne, Na, o))
+    it, hv = ct.c_int32(), ct.c_double()
+    code = lib.panda_run(_dev(W0, "W0", (Ne, Na)),
+                         None if P0 is None else _dev(P0, "P0", (Ne, Ne)),
+                         None if C0 is None else _dev(C0, "C0", (Na, Na)),
+                         Ne, Na, alpha, tol, max_iter,
+                         _dev(W, "W"), _dev(P, "P"), _dev(C, "C"), ws.data_ptr(), ws.numel(),
+                         ct.byref(o), ct.byref(it), ct.byref(hv), _stream())
+    _check(code, allow=(OK, NOT_CONVERGED))
+    return RunResult(W, P, C, it.value, hv.value, code)

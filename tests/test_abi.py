@@ -1,0 +1,99 @@
+"""The C ABI of libpanda.so: it loads, exports every declared entry point and
+rejects bad arguments on the host before touching the device (no GPU)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_1507_07039_amd import panda
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "panda.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(panda_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(panda.LIB_PATH):
+        pytest.fail("libpanda.so is not built (run __graft_entry__.build())")
+    return panda.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    assert set(names) == set(panda.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_options_struct_layout(lib):
+    o = panda.default_options()
+    assert ct.sizeof(panda.Options) == 8 + 8 + 8 * 4
+    assert o.alpha == 0.1 and o.tol == 1e-3 and o.max_iter == 200
+    assert (o.diag_alpha, o.sigma_from_T, o.n_own, o.h_undamped, o.update_last) == (1, 0, 0, 0, 0)
+    assert o.poll_every == 1 and o.precision == 0
+
+
+def test_status_strings(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert lib.panda_status_string(code)
+    assert lib.panda_status_string(42) == b"unknown status"
+
+
+def test_workspace_sizes(lib):
+    o = panda.default_options()
+    assert lib.panda_workspace_bytes(0, 10, ct.byref(o)) == 0
+    assert lib.panda_workspace_bytes(10, 0, ct.byref(o)) == 0
+    small = lib.panda_workspace_bytes(40, 400, ct.byref(o))
+    big = lib.panda_workspace_bytes(700, 18000, ct.byref(o))
+    # C (padded to 256) dominates: 18176^2 floats
+    assert big >= 18176 * 18176 * 4 and big < 1.25 * 18176 * 18176 * 4
+    assert 0 < small < big
+    assert lib.panda_tanimoto_workspace_bytes(0, 1, 1) == 0
+    assert lib.panda_tanimoto_workspace_bytes(3, 5, 7) > 0
+    assert lib.panda_normalize_workspace_bytes() >= 8 * 1024
+
+
+def test_host_validation_rejects_before_device_work(lib):
+    o = panda.default_options()
+    out = ct.c_void_p()
+    fake = ct.c_void_p(256)  # never dereferenced: validation fails first
+    # bad dimensions
+    assert lib.panda_ctx_create(0, 5, ct.byref(o), fake, 1 << 30, None, ct.byref(out)) == panda.ERR_ARG
+    # bad options
+    for field, val in (("alpha", 0.0), ("alpha", 1.5), ("tol", -1.0), ("max_iter", 0),
+                       ("poll_every", 0), ("precision", 7)):
+        b = panda.default_options(**{field: val})
+        assert lib.panda_ctx_create(4, 5, ct.byref(b), fake, 1 << 30, None, ct.byref(out)) == panda.ERR_ARG, field
+        assert lib.panda_last_error()
+    # workspace too small / missing / misaligned
+    assert lib.panda_ctx_create(4, 5, ct.byref(o), None, 1 << 30, None, ct.byref(out)) == panda.ERR_WORKSPACE
+    assert lib.panda_ctx_create(4, 5, ct.byref(o), fake, 16, None, ct.byref(out)) == panda.ERR_WORKSPACE
+    assert lib.panda_ctx_create(4, 5, ct.byref(o), ct.c_void_p(260), 1 << 30, None, ct.byref(out)) == panda.ERR_WORKSPACE
+    # NULL matrices
+    assert lib.panda_tanimoto(None, fake, 2, 2, 2, fake, fake, 1 << 20, None) == panda.ERR_ARG
+    assert lib.panda_normalize(None, 2, 2, fake, 1 << 20, None) == panda.ERR_ARG
+    assert lib.panda_normalize(fake, 2, 2, fake, 8, None) == panda.ERR_WORKSPACE
+    it, h = ct.c_int32(), ct.c_double()
+    assert lib.panda_run(None, None, None, 4, 5, 0.1, 1e-3, 10, fake, fake, fake, fake, 1 << 30,
+                         ct.byref(o), ct.byref(it), ct.byref(h), None) == panda.ERR_ARG
+    assert lib.panda_iterate(None, ct.byref(h), ct.byref(it)) == panda.ERR_ARG
+    lib.panda_ctx_destroy(None)  # no-op
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The library sources and the binding never import, load or link the oracle."""
+    pkg = os.path.join(ROOT, "paper_1507_07039_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                for pat in (r"^\s*(from|import)\s+oracle", r"liboracle", r"panda_oracle"):
+                    assert not re.search(pat, txt, flags=re.M), (pat, os.path.join(dirpath, f))

@@ -1,0 +1,230 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Both sides start from the same arrays: the seeded raw priors are z-scored by
+the oracle in FP64 and rounded to FP32; the GPU receives the FP32 values and
+the oracle the same values widened to FP64, so input rounding is not counted.
+
+Tolerances.  W: max-abs 1e-4 (the plain FP32 target).  Single similarity
+matrices: a first-order bound of FP32 accumulation over K terms,
+|dT| <= 2 K u sum_k |x_k y_k| / sqrt(den) + 4 u |T| with u = 2^-24.
+P and C off-diagonals: max-abs 1e-4.  Diagonals of P and C grow like
+exp(2 alpha t), so they are compared relative to their size (1e-5).
+"""
+import numpy as np
+import pytest
+
+from paper_1507_07039_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def pd(torch):
+    from paper_1507_07039_amd import panda
+    panda.load_library()
+    return panda
+
+
+def cuda(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def prep(oracle, W0, P0, C0):
+    """Oracle z-score in FP64, then FP32 rounding: the shared start."""
+    return tuple(np.float64(np.float32(oracle.normalize(M))) for M in (W0, P0, C0))
+
+
+def t_bound(X, Y, T):
+    K = X.shape[1]
+    absdot = np.abs(X) @ np.abs(Y)
+    den = (X ** 2).sum(1)[:, None] + (Y ** 2).sum(0)[None, :] - np.abs(X @ Y)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        b = np.where(den > 0, 2 * K * U * absdot / np.sqrt(np.maximum(den, 1e-300)), 0.0)
+    return b + 4 * U * np.abs(T) + 1e-30
+
+
+# ------------------------------------------------------------- Tfunction ---
+
+@pytest.mark.parametrize("M,K,N", [(1, 1, 1), (3, 5, 7), (64, 16, 256), (65, 17, 257),
+                                   (70, 333, 300), (130, 700, 513), (40, 400, 400)])
+def test_tanimoto_matches_oracle(torch, pd, oracle, M, K, N):
+    X = np.float64(np.float32(I.random_dense(M * 7 + K, (M, K))))
+    Y = np.float64(np.float32(I.random_dense(N * 5 + K, (K, N), -2.0, 2.0)))
+    got = host(pd.tanimoto(cuda(torch, X), cuda(torch, Y)))
+    want = oracle.tanimoto(X, Y)
+    err = np.abs(got - want)
+    bound = t_bound(X, Y, want)
+    assert np.all(err <= bound), (err.max(), (err / bound).max())
+
+
+def test_tanimoto_zero_vectors(torch, pd, oracle):
+    X = np.zeros((5, 9))
+    X[2] = 1.0
+    Y = np.zeros((9, 4))
+    Y[:, 1] = -1.0
+    got = host(pd.tanimoto(cuda(torch, X), cuda(torch, Y)))
+    np.testing.assert_array_equal(got, oracle.tanimoto(X, Y))
+
+
+# ------------------------------------------------------------- z-score -----
+
+def test_normalize_matches_oracle(torch, pd, oracle):
+    W0, P0, C0 = I.workload_priors(I.SMALL)
+    for M in (W0, P0, C0, I.random_dense(3, (17, 33), 5.0, 9.0)):
+        M32 = np.float64(np.float32(M))
+        t = cuda(torch, M32)
+        pd.normalize(t)
+        want = oracle.normalize(M32)
+        assert np.abs(host(t) - want).max() <= 2e-7 * max(1.0, np.abs(want).max())
+
+
+def test_normalize_errors(torch, pd):
+    t = torch.full((8, 8), 3.0, device="cuda")
+    with pytest.raises(pd.PandaError) as e:
+        pd.normalize(t)
+    assert e.value.code == pd.ERR_DEGENERATE
+    assert torch.all(t == 3.0)
+    t[3, 4] = float("nan")
+    with pytest.raises(pd.PandaError) as e:
+        pd.normalize(t)
+    assert e.value.code == pd.ERR_NONFINITE
+
+
+# ------------------------------------------------------------ iterations ---
+
+def compare_state(W, P, C, Wo, Po, Co, what=""):
+    eW = np.abs(W - Wo).max()
+    off_p = ~np.eye(P.shape[0], dtype=bool)
+    off_c = ~np.eye(C.shape[0], dtype=bool)
+    eP = np.abs(P - Po)[off_p].max() if P.shape[0] > 1 else 0.0
+    eC = np.abs(C - Co)[off_c].max() if C.shape[0] > 1 else 0.0
+    dP = np.abs(np.diag(P) - np.diag(Po)) / np.maximum(1.0, np.abs(np.diag(Po)))
+    dC = np.abs(np.diag(C) - np.diag(Co)) / np.maximum(1.0, np.abs(np.diag(Co)))
+    assert eW <= 1e-4, (what, "W", eW)
+    assert eP <= 1e-4, (what, "P", eP)
+    assert eC <= 1e-4, (what, "C", eC)
+    assert dP.max() <= 1e-5, (what, "diag P", dP.max())
+    assert dC.max() <= 1e-5, (what, "diag C", dC.max())
+    assert np.array_equal(P, P.T) and np.array_equal(C, C.T), what
+
+
+def run_matched(torch, pd, oracle, W, P, C, opts_kw=None, steps=None, pass_identity=False):
+    """Step GPU and oracle side by side; compare after every iteration."""
+    opts_kw = opts_kw or {}
+    o = oracle.Options(**opts_kw)
+    po = pd.default_options(**{k: int(v) if isinstance(v, bool) else v for k, v in opts_kw.items()})
+    Ne, Na = W.shape
+    ctx = pd.Context(Ne, Na, po)
+    if pass_identity:
+        ctx.load(cuda(torch, W))
+    else:
+        ctx.load(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    Wo, Po, Co = W.copy(), P.copy(), C.copy()
+    t = 0
+    n = steps or o.max_iter
+    conv = False
+    while t < n and not conv:
+        t += 1
+        Wo, Po, Co, ho, conv = oracle.step(Wo, Po, Co, t, o)
+        hg, tg = ctx.iterate()
+        assert tg == t
+        assert abs(hg - ho) <= 1e-6 * max(ho, 1e-3), (t, hg, ho)
+        Wg, Pg, Cg, _, _ = ctx.state()
+        compare_state(host(Wg), host(Pg), host(Cg), Wo, Po, Co, what=f"t={t}")
+    return t, ctx
+
+
+def test_small_workload_matched_iterations(torch, pd, oracle):
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    t, ctx = run_matched(torch, pd, oracle, W, P, C)
+    assert 20 <= t <= 60
+    # converged state is frozen
+    h1, t1 = ctx.iterate()
+    assert t1 == t
+
+
+@pytest.mark.parametrize("kw", [{"diag_alpha": False}, {"sigma_from_T": True}, {"n_own": True},
+                                {"h_undamped": True}, {"update_last": True},
+                                {"alpha": 0.3, "tol": 1e-4}])
+def test_readings_flags(torch, pd, oracle, kw):
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    run_matched(torch, pd, oracle, W, P, C, opts_kw=kw, steps=12)
+
+
+@pytest.mark.parametrize("Ne,Na", [(1, 1), (1, 7), (3, 1), (2, 5), (65, 300), (70, 257)])
+def test_ragged_shapes(torch, pd, oracle, Ne, Na):
+    rng = np.random.default_rng(Ne * 1000 + Na)
+    W = np.float64(np.float32(rng.normal(size=(Ne, Na))))
+    P = np.float64(np.float32(I.random_symmetric(Ne + 1, Ne)))
+    C = np.float64(np.float32(I.random_symmetric(Na + 2, Na)))
+    run_matched(torch, pd, oracle, W, P, C, steps=6)
+
+
+def test_identity_defaults(torch, pd, oracle):
+    """NULL P0 / C0 mean identity networks, z-scored like any other."""
+    W0, _, _ = I.workload_priors(I.SMALL)
+    W = np.float64(np.float32(oracle.normalize(W0)))
+    Ne, Na = W.shape
+    P = oracle.normalize(np.eye(Ne))
+    C = oracle.normalize(np.eye(Na))
+    # the GPU builds and z-scores the identities itself: compare loosely at t=0
+    run_matched(torch, pd, oracle, W, P, C, steps=5, pass_identity=True)
+
+
+def test_run_entry_point(torch, pd, oracle):
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    ref = oracle.run(W, P, C)
+    res = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    assert res.status == pd.OK
+    assert res.iters == ref.iters
+    assert abs(res.h - ref.h) <= 1e-6 * ref.h
+    compare_state(host(res.W), host(res.P), host(res.C), ref.W, ref.P, ref.C, "run")
+    # max_iter exhaustion returns NOT_CONVERGED with the state of that step
+    short = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C), max_iter=5)
+    assert short.status == pd.NOT_CONVERGED and short.iters == 5
+    ref5 = oracle.run(W, P, C, oracle.Options(max_iter=5))
+    compare_state(host(short.W), host(short.P), host(short.C), ref5.W, ref5.P, ref5.C, "max_iter")
+
+
+def test_run_poll_every_and_determinism(torch, pd, oracle):
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    a = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    b = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C), opts=pd.default_options(poll_every=7))
+    assert a.iters == b.iters and a.h == b.h
+    assert torch.equal(a.W, b.W) and torch.equal(a.P, b.P) and torch.equal(a.C, b.C)
+
+
+def test_resume_equals_straight_run(torch, pd, oracle):
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    straight = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    ctx = pd.Context(*W.shape)
+    ctx.load(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    for _ in range(9):
+        ctx.iterate()
+    Wk, Pk, Ck, hk, tk = ctx.state()
+    assert tk == 9
+    ctx2 = pd.Context(*W.shape)
+    ctx2.load(Wk, Pk, Ck, t=tk)
+    t = tk
+    while True:
+        h, t2 = ctx2.iterate()
+        if t2 == t:
+            break
+        t = t2
+    Wr, Pr, Cr, hr, tr = ctx2.state()
+    assert tr == straight.iters
+    assert torch.equal(Wr, straight.W) and torch.equal(Cr, straight.C) and torch.equal(Pr, straight.P)
