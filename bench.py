@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the PANDA message-passing iteration on one MI355X.
+
+Workload: synthetic priors shaped like the paper's realistic networks
+(T = 700 transcription factors x G = 18000 genes, Sec. II-F), drawn by
+paper_1507_07039_amd.inputs and z-scored on the GPU by the library.
+
+Printed (one JSON line):
+  value        seconds per message-passing iteration (median over the timed
+               steps; a step is one full iteration: R, A + W, h, P, C, diagonals)
+  time_to_converge_s / iters_to_converge   panda_run from the priors to h < tol
+  roofline     the dominant kernel (A = T(W, C) fused with the W update):
+               algorithmic FLOPs 2 T G^2 per launch over its event-timed
+               average duration, against the FP32 matrix-core peak
+  cpu_baseline the FP64 oracle on a bounded sample of the same iteration,
+               scaled to seconds per iteration
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1507_07039_amd import inputs as I  # noqa: E402
+
+METRIC = "s/iteration & time-to-converge at T=700,G=18k: plain FP32 vs chosen form"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def gpu_inputs(w: I.Workload, torch, panda):
+    W0, P0, C0 = I.workload_priors(w)
+    dev = [torch.from_numpy(np.ascontiguousarray(M, dtype=np.float32)).cuda() for M in (W0, P0, C0)]
+    del W0, P0, C0
+    for M in dev:
+        panda.normalize(M)
+    torch.cuda.synchronize()
+    return dev
+
+
+def time_iterations(torch, panda, W, P, C, steps: int, warmup: int):
+    Ne, Na = W.shape
+    opts = panda.default_options(tol=0.0, max_iter=1 << 30)  # never stops inside the timing
+    ctx = panda.Context(Ne, Na, opts)
+    ctx.load(W, P, C)
+    for _ in range(warmup):
+        ctx.iterate()
+    ctx.set_timing(True)
+    per = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        ctx.iterate()  # returns after h is read back, i.e. after the iteration ran
+        per.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    phases = ctx.phase_times()
+    ctx.close()
+    return per, total, phases
+
+
+def time_to_converge(torch, panda, W, P, C, runs: int):
+    Ne, Na = W.shape
+    ws = panda.workspace(panda.workspace_bytes(Ne, Na))
+    out = (torch.empty_like(W), torch.empty_like(P), torch.empty_like(C))
+    times, res = [], None
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = panda.run(W, P, C, ws=ws, out=out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return times, res
+
+
+def cpu_baseline(w: I.Workload, budget_s: float = 4.0):
+    """FP64 oracle on sampled entries of each phase of one iteration."""
+    from oracle import oracle as O
+    W0, P0, C0 = I.workload_priors(w)
+    W, P, C = O.normalize(W0), O.normalize(P0), O.normalize(C0)
+    del W0, P0, C0
+    Ne, Na = W.shape
+    Wt = np.ascontiguousarray(W.T)
+    rng = np.random.default_rng(0)
+
+    def timed(fn, total, n0):
+        n = n0
+        while True:
+            r = rng.integers(0, 1 << 62, size=n)
+            t0 = time.perf_counter()
+            fn(r, n)
+            dt = time.perf_counter() - t0
+            if dt >= budget_s or n >= total:
+                return dt / n, n
+            n = min(total, n * 4)
+
+    per_w, nw = timed(lambda r, n: O.step_w_entries(W, P, C, 0.1, r % Ne, (r >> 20) % Na), Ne * Na, 2000)
+    per_p, npp = timed(lambda r, n: O.tanimoto_entries(W, Wt, r % Ne, (r >> 20) % Ne), Ne * Ne, 2000)
+    per_c, nc = timed(lambda r, n: O.tanimoto_entries(Wt, W, r % Na, (r >> 20) % Na), Na * Na, 20000)
+    s_iter = per_w * Ne * Na + per_p * Ne * Ne + per_c * Na * Na
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": s_iter, "unit": "s/iteration", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 element-wise oracle, {nw} W entries (R+A+update), {npp} P entries, "
+                       f"{nc} C entries of one iteration at T={Ne} G={Na}, time per entry scaled "
+                       f"to the full {Ne}x{Na}, {Ne}x{Ne} and {Na}x{Na} matrices")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="human", choices=["human", "small", "large"])
+    ap.add_argument("--converge-runs", type=int, default=3)
+    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              "described in the design notes but not built", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1507_07039_amd import panda
+    panda.load_library()
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    w = {"human": I.HUMAN, "small": I.SMALL, "large": I.LARGE}[args.workload]
+    log(f"workload {w.name}: generating priors")
+    W, P, C = gpu_inputs(w, torch, panda)
+    Ne, Na = W.shape
+    log("timing iterations")
+    per, total, phases = time_iterations(torch, panda, W, P, C, args.steps, args.warmup)
+    s_iter = statistics.median(per)
+    ms = {k: (v[0] / v[1] if v[1] else None) for k, v in phases.items()}
+    flops = {"R": 2.0 * Ne * Ne * Na, "A+W": 2.0 * Ne * Na * Na, "P-partial": 2.0 * Ne * Ne * Na,
+             "C": 1.0 * Ne * Na * Na}
+    rates = {k: flops[k] / (ms[k] * 1e-3) / 1e12 for k in flops if ms.get(k)}
+    aw_ms = ms["A+W"]
+    achieved = flops["A+W"] / (aw_ms * 1e-3) / 1e12
+    result = {
+        "metric": METRIC, "value": s_iter, "unit": "s/iteration", "higher_is_better": False,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": s_iter * 1e3,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "T": Ne, "G": Na, "alpha": 0.1, "tol": 1e-3,
+                   "form": "plain-fp32", "parallelism": "single-gpu"},
+        "s_per_iteration_p10_p90": [float(np.percentile(per, 10)), float(np.percentile(per, 90))],
+        "phase_ms": ms, "phase_tflops": rates,
+        "roofline": {"bound": "mfma", "kernel": "k_avail_wupdate", "achieved": achieved,
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None},
+    }
+    if not args.no_converge:
+        log("time to converge")
+        times, res = time_to_converge(torch, panda, W, P, C, args.converge_runs)
+        result["time_to_converge_s"] = statistics.median(times)
+        result["iters_to_converge"] = res.iters
+        result["h_final"] = res.h
+        result["converged"] = res.status == panda.OK
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = n * 4
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -136,6 +136,25 @@ panda_status panda_run(const float* W0, const float* P0, const float* C0, int64_
                        void* workspace, size_t ws_bytes, const panda_options* opt,
                        int32_t* iters, double* h, hipStream_t stream);
 
+/* Per-phase timing of a context (the paper times the message-passing
+ * procedure alone, Sec. II-D; this splits that time by step).  When enabled,
+ * each phase of each iteration is bracketed by HIP events on the context's
+ * stream; elapsed times are summed whenever the state is read back.  Phases
+ * are indexed by the enum below.  phase_times fills total_ms[PANDA_NPHASE]
+ * and count[PANDA_NPHASE] (iterations timed); either may be NULL. */
+enum {
+  PANDA_PHASE_R = 0,      /* R = T(P, W)                          (Eq. 3)       */
+  PANDA_PHASE_AW = 1,     /* A = T(W, C), W update, h partials    (Eq. 4, 2, 7) */
+  PANDA_PHASE_H = 2,      /* h and the convergence test           (Eq. 7)       */
+  PANDA_PHASE_PPART = 3,  /* W W^T split-K partial products       (Eq. 5, P)    */
+  PANDA_PHASE_PFIN = 4,   /* P off-diagonal update                (Eq. 5, P)    */
+  PANDA_PHASE_C = 5,      /* C off-diagonal update, row sums      (Eq. 5, C)    */
+  PANDA_PHASE_DIAG = 6,   /* diagonals of P and C                 (Eq. 6)       */
+  PANDA_NPHASE = 7
+};
+panda_status panda_ctx_set_timing(panda_ctx* ctx, int32_t enable);
+panda_status panda_ctx_phase_times(panda_ctx* ctx, double* total_ms, int64_t* count);
+
 const char* panda_status_string(panda_status s);
 const char* panda_last_error(void);
 

@@ -48,6 +48,7 @@ struct Carver {
 };
 
 constexpr size_t kZsScratch = kZsBlocks + 8;  // doubles
+constexpr int kMaxPending = 16;               // timed iterations between read-backs
 
 Rule rule_of(const panda_options& o) {
   Rule r;
@@ -100,6 +101,12 @@ struct panda_ctx {
   int64_t executed;  // iterations known to have run since load
   int64_t enqueued;  // iterations enqueued since load
   bool loaded;
+  // phase timing
+  bool timing;
+  int npend;
+  hipEvent_t ev[16][PANDA_NPHASE + 1];
+  double tot_ms[PANDA_NPHASE];
+  int64_t cnt[PANDA_NPHASE];
 };
 
 namespace {
@@ -157,33 +164,24 @@ panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, double* sc
   return PANDA_OK;
 }
 
-// Enqueue one iteration: R, A + W update, h, P update, C update, diagonals.
-panda_status enqueue_iteration(panda_ctx* c) {
-  const int64_t k = c->executed + (c->enqueued - c->executed);
-  float* Wold = c->W[k & 1];
-  float* Wnew = c->W[(k + 1) & 1];
-  hipStream_t s = c->stream;
-  const int32_t* active = &c->st->active;
-  const int32_t* run_pc = &c->st->run_pc;
-  // Eq. 3: R = T(P, W), K = N_e
-  HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
-                                c->R, c->Nap, active, s));
-  // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
-  HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
-                               c->rule, c->hpart, active, s));
-  HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
-  // Eq. 5, P: T(W_i., W_m.) of the new W
-  HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, c->pnrm, run_pc,
-                              s));
-  HIP_TRY(launch_coop_finalize(c->ppart, c->pnrm, c->splits, c->P, c->Nep, c->Ne, c->rule,
-                               c->rule.sigma_from_T ? c->Tside : nullptr, run_pc, s));
-  // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
-  HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->rule,
-                              c->cstat, run_pc, s));
-  // Eq. 6
-  HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->C,
-                           c->Nap, c->Na, c->cstat, coreg_slots(c->Nap), c->rule, c->st, s));
-  c->enqueued += 1;
+// Phase boundary marker: records event `p` of the current pending
+// iteration when timing is on.
+panda_status mark(panda_ctx* c, int p) {
+  if (!c->timing) return PANDA_OK;
+  HIP_TRY(hipEventRecord(c->ev[c->npend][p], c->stream));
+  return PANDA_OK;
+}
+
+// Sum the elapsed times of the pending timed iterations (stream synced).
+panda_status collect_times(panda_ctx* c) {
+  for (int i = 0; i < c->npend; ++i)
+    for (int p = 0; p < PANDA_NPHASE; ++p) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, c->ev[i][p], c->ev[i][p + 1]));
+      c->tot_ms[p] += ms;
+      c->cnt[p] += 1;
+    }
+  c->npend = 0;
   return PANDA_OK;
 }
 
@@ -192,6 +190,55 @@ panda_status read_state(panda_ctx* c) {
   HIP_TRY(hipMemcpyAsync(c->host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->executed = c->host->t - c->t0;
+  return collect_times(c);
+}
+
+#define PANDA_TRY(call)                      \
+  do {                                       \
+    panda_status s_ = (call);                \
+    if (s_ != PANDA_OK) return s_;           \
+  } while (0)
+
+// Enqueue one iteration: R, A + W update, h, P update, C update, diagonals.
+// Iteration k (counted from the load) reads W[k % 2] and writes W[(k+1) % 2];
+// iterations past convergence are skipped on the device, so the executed
+// ones are always a prefix of the enqueued ones.
+panda_status enqueue_iteration(panda_ctx* c) {
+  if (c->timing && c->npend == kMaxPending) PANDA_TRY(read_state(c));
+  const int64_t k = c->enqueued;
+  float* Wold = c->W[k & 1];
+  float* Wnew = c->W[(k + 1) & 1];
+  hipStream_t s = c->stream;
+  const int32_t* active = &c->st->active;
+  const int32_t* run_pc = &c->st->run_pc;
+  PANDA_TRY(mark(c, PANDA_PHASE_R));
+  // Eq. 3: R = T(P, W), K = N_e
+  HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
+                                c->R, c->Nap, active, s));
+  PANDA_TRY(mark(c, PANDA_PHASE_AW));
+  // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
+  HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
+                               c->rule, c->hpart, active, s));
+  PANDA_TRY(mark(c, PANDA_PHASE_H));
+  HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
+  PANDA_TRY(mark(c, PANDA_PHASE_PPART));
+  // Eq. 5, P: T(W_i., W_m.) of the new W
+  HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, c->pnrm, run_pc,
+                              s));
+  PANDA_TRY(mark(c, PANDA_PHASE_PFIN));
+  HIP_TRY(launch_coop_finalize(c->ppart, c->pnrm, c->splits, c->P, c->Nep, c->Ne, c->rule,
+                               c->rule.sigma_from_T ? c->Tside : nullptr, run_pc, s));
+  PANDA_TRY(mark(c, PANDA_PHASE_C));
+  // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
+  HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->rule,
+                              c->cstat, run_pc, s));
+  PANDA_TRY(mark(c, PANDA_PHASE_DIAG));
+  // Eq. 6
+  HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->C,
+                           c->Nap, c->Na, c->cstat, coreg_slots(c->Nap), c->rule, c->st, s));
+  PANDA_TRY(mark(c, PANDA_NPHASE));
+  if (c->timing) c->npend += 1;
+  c->enqueued += 1;
   return PANDA_OK;
 }
 
@@ -218,6 +265,39 @@ void panda_default_options(panda_options* o) {
   o->update_last = 0;
   o->poll_every = 1;
   o->precision = PANDA_PREC_FP32;
+}
+
+panda_status panda_ctx_set_timing(panda_ctx* c, int32_t enable) {
+  if (!c) return fail(PANDA_ERR_ARG, "set_timing: NULL context%s");
+  if (enable && !c->ev[0][0]) {
+    for (int i = 0; i < kMaxPending; ++i)
+      for (int p = 0; p <= PANDA_NPHASE; ++p) HIP_TRY(hipEventCreate(&c->ev[i][p]));
+  }
+  if (!enable && c->timing) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    panda_status st = collect_times(c);
+    if (st != PANDA_OK) return st;
+  }
+  c->timing = enable != 0;
+  for (int p = 0; p < PANDA_NPHASE; ++p) {
+    c->tot_ms[p] = 0.0;
+    c->cnt[p] = 0;
+  }
+  return PANDA_OK;
+}
+
+panda_status panda_ctx_phase_times(panda_ctx* c, double* total_ms, int64_t* count) {
+  if (!c) return fail(PANDA_ERR_ARG, "phase_times: NULL context%s");
+  if (c->timing && c->npend) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    panda_status st = collect_times(c);
+    if (st != PANDA_OK) return st;
+  }
+  for (int p = 0; p < PANDA_NPHASE; ++p) {
+    if (total_ms) total_ms[p] = c->tot_ms[p];
+    if (count) count[p] = c->cnt[p];
+  }
+  return PANDA_OK;
 }
 
 const char* panda_status_string(panda_status s) {
@@ -321,6 +401,9 @@ panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, 
 void panda_ctx_destroy(panda_ctx* c) {
   if (!c) return;
   if (c->host) (void)hipHostFree(c->host);
+  if (c->ev[0][0])
+    for (int i = 0; i < kMaxPending; ++i)
+      for (int p = 0; p <= PANDA_NPHASE; ++p) (void)hipEventDestroy(c->ev[i][p]);
   delete c;
 }
 

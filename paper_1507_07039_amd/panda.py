@@ -23,8 +23,11 @@ EXPORTS = (
     "panda_default_options", "panda_normalize_workspace_bytes", "panda_normalize",
     "panda_tanimoto_workspace_bytes", "panda_tanimoto", "panda_workspace_bytes",
     "panda_ctx_create", "panda_ctx_load", "panda_iterate", "panda_ctx_store",
-    "panda_ctx_destroy", "panda_run", "panda_status_string", "panda_last_error",
+    "panda_ctx_destroy", "panda_run", "panda_ctx_set_timing", "panda_ctx_phase_times",
+    "panda_status_string", "panda_last_error",
 )
+
+PHASES = ("R", "A+W", "h", "P-partial", "P-final", "C", "diag")
 
 
 class PandaError(RuntimeError):
@@ -69,6 +72,8 @@ def load_library(path: str = LIB_PATH):
         "panda_ctx_destroy": (None, [vp]),
         "panda_run": (ct.c_int, [vp, vp, vp, i64, i64, dbl, dbl, i32, vp, vp, vp, vp, sz, op,
                                  ct.POINTER(i32), ct.POINTER(dbl), vp]),
+        "panda_ctx_set_timing": (ct.c_int, [vp, i32]),
+        "panda_ctx_phase_times": (ct.c_int, [vp, ct.POINTER(dbl), ct.POINTER(i64)]),
         "panda_status_string": (ct.c_char_p, [ct.c_int]),
         "panda_last_error": (ct.c_char_p, []),
     }
@@ -189,6 +194,17 @@ class Context:
         pc = None if C is None else _dev(C, "C", (self.Na, self.Na))
         _check(self.lib.panda_ctx_store(self.h, pw, pp, pc, ct.byref(hv), ct.byref(tv)))
         return hv.value, tv.value
+
+    def set_timing(self, enable: bool = True):
+        _check(self.lib.panda_ctx_set_timing(self.h, int(enable)))
+
+    def phase_times(self):
+        """{phase: (total ms, iterations timed)} since timing was enabled."""
+        n = len(PHASES)
+        ms = (ct.c_double * n)()
+        cnt = (ct.c_int64 * n)()
+        _check(self.lib.panda_ctx_phase_times(self.h, ms, cnt))
+        return {PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
 
     def state(self):
         torch = _torch()

@@ -62,7 +62,7 @@ def main(which: str):
     nsamp = 2048 if which == "human" else 256
     t0 = time.time()
     Wf, Pf, Cf = normalized_f32(w)
-    W, P, C = (np.float64(x) for x in (Wf, Pf, Cf))
+    W, P, C = (x.astype(np.float64) for x in (Wf, Pf, Cf))
     opts = O.Options()
     Ne, Na = W.shape
     rw, cw = sample_idx(1, Ne, Na, nsamp)

@@ -1,0 +1,120 @@
+"""Parity at the realistic size T = 700 x G = 18000, in the launch
+configuration the benchmark times.
+
+The full oracle iteration at this size takes minutes, so:
+  - the first iteration is checked on sampled entries that the oracle
+    computes one by one from the shared inputs;
+  - symmetry and finiteness are checked on the whole state;
+  - the whole trajectory is compared with the oracle's stored run
+    (tests/golden/oracle_panda-T700-G18000.json, written by
+    tests/golden/make_golden.py from the oracle alone) when present.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1507_07039_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "oracle_panda-T700-G18000.json")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def pd(torch):
+    from paper_1507_07039_amd import panda
+    panda.load_library()
+    return panda
+
+
+@pytest.fixture(scope="module")
+def human(oracle):
+    W0, P0, C0 = I.workload_priors(I.HUMAN)
+    f32 = [np.ascontiguousarray(oracle.normalize(M).astype(np.float32)) for M in (W0, P0, C0)]
+    del W0, P0, C0
+    h = hashlib.sha256()
+    for a in f32:
+        h.update(a.tobytes())
+    return f32, h.hexdigest()
+
+
+def test_first_iteration_sampled(torch, pd, oracle, human):
+    (W, P, C), _ = human
+    Ne, Na = W.shape
+    ctx = pd.Context(Ne, Na)
+    ctx.load(*[torch.from_numpy(a).cuda() for a in (W, P, C)])
+    h, t = ctx.iterate()
+    assert t == 1
+    Wg = ctx.state()[0].cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(7)
+    r = rng.integers(0, Ne, size=4096)
+    c = rng.integers(0, Na, size=4096)
+    want = oracle.step_w_entries(W.astype(np.float64), P.astype(np.float64),
+                                 C.astype(np.float64), 0.1, r, c)
+    err = np.abs(Wg[r, c] - want)
+    assert err.max() <= 1e-4, err.max()
+    ctx.close()
+
+
+def test_state_symmetric_and_finite(torch, pd, human):
+    (W, P, C), _ = human
+    Ne, Na = W.shape
+    ctx = pd.Context(Ne, Na)
+    ctx.load(*[torch.from_numpy(a).cuda() for a in (W, P, C)])
+    for _ in range(3):
+        ctx.iterate()
+    Wg, Pg, Cg, h, t = ctx.state()
+    assert t == 3 and np.isfinite(h) and h > 0
+    assert torch.isfinite(Wg).all() and torch.isfinite(Pg).all() and torch.isfinite(Cg).all()
+    assert torch.equal(Pg, Pg.T)
+    assert torch.equal(Cg, Cg.T)
+    ctx.close()
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle trajectory not generated")
+def test_trajectory_matches_stored_oracle_run(torch, pd, human):
+    (W, P, C), digest = human
+    g = json.load(open(GOLDEN))
+    if g["inputs_sha256_f32"] != digest:
+        print("note: regenerated inputs differ in their last bits from the stored run's")
+    Ne, Na = W.shape
+    ctx = pd.Context(Ne, Na)
+    ctx.load(*[torch.from_numpy(a).cuda() for a in (W, P, C)])
+    idx = g["idx"]
+    for t_exp, h_exp in enumerate(g["h_trace"], start=1):
+        h, t = ctx.iterate()
+        assert t == t_exp
+        assert abs(h - h_exp) <= 1e-4 * h_exp, (t, h, h_exp)
+        snap = g["snapshots"].get(str(t))
+        if snap is None:
+            continue
+        Wg, Pg, Cg, _, _ = ctx.state()
+        Wg = Wg.cpu().numpy().astype(np.float64)
+        Pg = Pg.cpu().numpy().astype(np.float64)
+        Cg = Cg.cpu().numpy().astype(np.float64)
+        eW = np.abs(Wg[idx["W"][0], idx["W"][1]] - np.array(snap["W"])).max()
+        eP = np.abs(Pg[idx["P"][0], idx["P"][1]] - np.array(snap["P"])).max()
+        eC = np.abs(Cg[idx["C"][0], idx["C"][1]] - np.array(snap["C"])).max()
+        pd_ = np.array(snap["Pdiag"])
+        cd_ = np.array(snap["Cdiag"])
+        dP = (np.abs(Pg[idx["Pdiag"], idx["Pdiag"]] - pd_) / np.maximum(1, np.abs(pd_))).max()
+        dC = (np.abs(Cg[idx["Cdiag"], idx["Cdiag"]] - cd_) / np.maximum(1, np.abs(cd_))).max()
+        print(f"t={t} W {eW:.2e} P {eP:.2e} C {eC:.2e} diagP {dP:.2e} diagC {dC:.2e}")
+        assert eW <= 1e-4 and eP <= 1e-4 and eC <= 1e-4, (t, eW, eP, eC)
+        assert dP <= 1e-5 and dC <= 1e-5, (t, dP, dC)
+    assert g["converged"]
+    h, t = ctx.iterate()  # frozen after convergence
+    assert t == g["iters"]
+    ctx.close()

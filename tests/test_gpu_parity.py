@@ -35,6 +35,11 @@ def pd(torch):
     return panda
 
 
+def f32r(a):
+    """Round to FP32 and widen back to FP64 (keeps the array shape)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
 def cuda(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
@@ -45,7 +50,7 @@ def host(t):
 
 def prep(oracle, W0, P0, C0):
     """Oracle z-score in FP64, then FP32 rounding: the shared start."""
-    return tuple(np.float64(np.float32(oracle.normalize(M))) for M in (W0, P0, C0))
+    return tuple(f32r(oracle.normalize(M)) for M in (W0, P0, C0))
 
 
 def t_bound(X, Y, T):
@@ -62,8 +67,8 @@ def t_bound(X, Y, T):
 @pytest.mark.parametrize("M,K,N", [(1, 1, 1), (3, 5, 7), (64, 16, 256), (65, 17, 257),
                                    (70, 333, 300), (130, 700, 513), (40, 400, 400)])
 def test_tanimoto_matches_oracle(torch, pd, oracle, M, K, N):
-    X = np.float64(np.float32(I.random_dense(M * 7 + K, (M, K))))
-    Y = np.float64(np.float32(I.random_dense(N * 5 + K, (K, N), -2.0, 2.0)))
+    X = f32r(I.random_dense(M * 7 + K, (M, K)))
+    Y = f32r(I.random_dense(N * 5 + K, (K, N), -2.0, 2.0))
     got = host(pd.tanimoto(cuda(torch, X), cuda(torch, Y)))
     want = oracle.tanimoto(X, Y)
     err = np.abs(got - want)
@@ -85,7 +90,7 @@ def test_tanimoto_zero_vectors(torch, pd, oracle):
 def test_normalize_matches_oracle(torch, pd, oracle):
     W0, P0, C0 = I.workload_priors(I.SMALL)
     for M in (W0, P0, C0, I.random_dense(3, (17, 33), 5.0, 9.0)):
-        M32 = np.float64(np.float32(M))
+        M32 = f32r(M)
         t = cuda(torch, M32)
         pd.normalize(t)
         want = oracle.normalize(M32)
@@ -168,20 +173,27 @@ def test_readings_flags(torch, pd, oracle, kw):
 @pytest.mark.parametrize("Ne,Na", [(1, 1), (1, 7), (3, 1), (2, 5), (65, 300), (70, 257)])
 def test_ragged_shapes(torch, pd, oracle, Ne, Na):
     rng = np.random.default_rng(Ne * 1000 + Na)
-    W = np.float64(np.float32(rng.normal(size=(Ne, Na))))
-    P = np.float64(np.float32(I.random_symmetric(Ne + 1, Ne)))
-    C = np.float64(np.float32(I.random_symmetric(Na + 2, Na)))
+    W = f32r(rng.normal(size=(Ne, Na)))
+    P = f32r(I.random_symmetric(Ne + 1, Ne))
+    C = f32r(I.random_symmetric(Na + 2, Na))
     run_matched(torch, pd, oracle, W, P, C, steps=6)
 
 
 def test_identity_defaults(torch, pd, oracle):
     """NULL P0 / C0 mean identity networks, z-scored like any other."""
     W0, _, _ = I.workload_priors(I.SMALL)
-    W = np.float64(np.float32(oracle.normalize(W0)))
+    W = f32r(oracle.normalize(W0))
     Ne, Na = W.shape
-    P = oracle.normalize(np.eye(Ne))
-    C = oracle.normalize(np.eye(Na))
-    # the GPU builds and z-scores the identities itself: compare loosely at t=0
+    # the GPU builds the identities and z-scores them in FP64 before storing
+    # FP32; the oracle gets the same FP32-rounded values
+    P = f32r(oracle.normalize(np.eye(Ne)))
+    C = f32r(oracle.normalize(np.eye(Na)))
+    ctx = pd.Context(Ne, Na)
+    ctx.load(cuda(torch, W))
+    _, Pg, Cg, _, t0 = ctx.state()
+    assert t0 == 0
+    assert np.abs(host(Pg) - P).max() <= 2e-7 * np.abs(P).max()
+    assert np.abs(host(Cg) - C).max() <= 2e-7 * np.abs(C).max()
     run_matched(torch, pd, oracle, W, P, C, steps=5, pass_identity=True)
 
 

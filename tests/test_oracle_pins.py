@@ -230,7 +230,7 @@ def test_single_tf_row(oracle):
 
 def _cfg1():
     W0, P0, C0 = I.workload_priors(I.SMALL)
-    W0, P0, C0 = (np.float64(x) for x in I.to_f32(W0, P0, C0))
+    W0, P0, C0 = (x.astype(np.float64) for x in I.to_f32(W0, P0, C0))
     return W0, P0, C0
 
 
