@@ -88,10 +88,16 @@ struct panda_ctx {
   float* P;
   float* C;
   float* Tside;
-  float* ppart;
-  double* pnrm;
+  float* ppart;   // split-K partial products of W W^T
+  float* skpart;  // stream-K partial tiles
+  double* nP;     // |P_i.|^2
+  double* nC;     // |C_.j|^2
+  double* nWr;    // |W_i.|^2
+  double* nWc;    // |W_.j|^2
+  double* colscr; // column-norm scratch
   double* hpart;
   double2* cstat;
+  double* csq;
   double* zs;
   DevState* st;
   DevState* host;  // pinned
@@ -124,10 +130,16 @@ size_t layout(int64_t Ne, int64_t Na, panda_ctx* c, char* base) {
   float* ts = cv.take<float>((size_t)Nep * Nep);
   const int splits = coop_splits(Nep, Nap);
   float* pp = cv.take<float>((size_t)splits * Nep * Nep);
-  double* pn = cv.take<double>((size_t)splits * Nep);
-  const int64_t nh = avail_wupdate_blocks(Nep, Nap);
+  float* sk = cv.take<float>(rect_partial_floats());
+  double* np_ = cv.take<double>((size_t)Nep);
+  double* nc = cv.take<double>((size_t)Nap);
+  double* nwr = cv.take<double>((size_t)Nep);
+  double* nwc = cv.take<double>((size_t)Nap);
+  double* scr = cv.take<double>((size_t)kColChunks * (size_t)Nap);
+  const int64_t nh = rect_tiles(Nep, Nap);
   double* hp = cv.take<double>((size_t)nh);
   double2* cs = cv.take<double2>((size_t)coreg_slots(Nap) * Nap);
+  double* cq = cv.take<double>((size_t)coreg_slots(Nap) * Nap);
   double* zs = cv.take<double>(kZsScratch);
   DevState* st = cv.take<DevState>(1);
   if (c) {
@@ -140,11 +152,17 @@ size_t layout(int64_t Ne, int64_t Na, panda_ctx* c, char* base) {
     c->C = cc;
     c->Tside = ts;
     c->ppart = pp;
-    c->pnrm = pn;
+    c->skpart = sk;
+    c->nP = np_;
+    c->nC = nc;
+    c->nWr = nwr;
+    c->nWc = nwc;
+    c->colscr = scr;
     c->splits = splits;
     c->hpart = hp;
     c->nh = nh;
     c->cstat = cs;
+    c->csq = cq;
     c->zs = zs;
     c->st = st;
   }
@@ -214,28 +232,31 @@ panda_status enqueue_iteration(panda_ctx* c) {
   PANDA_TRY(mark(c, PANDA_PHASE_R));
   // Eq. 3: R = T(P, W), K = N_e
   HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
-                                c->R, c->Nap, active, s));
+                                c->nP, c->nWc, c->R, c->Nap, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_AW));
   // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
   HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
-                               c->rule, c->hpart, active, s));
+                               c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_H));
   HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
+  // squared norms of the rows and columns of the new W
+  HIP_TRY(launch_row_sqnorms(Wnew, c->Ne, c->Na, c->Nap, c->nWr, run_pc, s));
+  HIP_TRY(launch_col_sqnorms(Wnew, c->Ne, c->Na, c->Nap, c->nWc, c->colscr, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_PPART));
   // Eq. 5, P: T(W_i., W_m.) of the new W
-  HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, c->pnrm, run_pc,
-                              s));
+  HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_PFIN));
-  HIP_TRY(launch_coop_finalize(c->ppart, c->pnrm, c->splits, c->P, c->Nep, c->Ne, c->rule,
+  HIP_TRY(launch_coop_finalize(c->ppart, c->splits, c->Nep, c->nWr, c->P, c->Nep, c->Ne, c->rule,
                                c->rule.sigma_from_T ? c->Tside : nullptr, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_C));
   // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
-  HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->rule,
-                              c->cstat, run_pc, s));
+  HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc, c->rule,
+                              c->cstat, c->csq, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_DIAG));
-  // Eq. 6
-  HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->C,
-                           c->Nap, c->Na, c->cstat, coreg_slots(c->Nap), c->rule, c->st, s));
+  // Eq. 6, and |P_i.|^2, |C_.j|^2 for the next iteration
+  HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->nP,
+                           c->C, c->Nap, c->Na, c->cstat, c->rule.sigma_from_T ? c->csq : nullptr,
+                           coreg_slots(c->Nap), c->nC, c->rule, c->st, s));
   PANDA_TRY(mark(c, PANDA_NPHASE));
   if (c->timing) c->npend += 1;
   c->enqueued += 1;
@@ -326,11 +347,29 @@ panda_status panda_normalize(float* M, int64_t rows, int64_t cols, void* workspa
   return zscore(M, rows, cols, cols, static_cast<double*>(workspace), stream);
 }
 
+namespace {
+struct TaniLayout {
+  float *Xp, *Yp, *Op, *part;
+  double *nx, *ny, *scr;
+};
+size_t tanimoto_layout(int64_t M, int64_t K, int64_t N, char* base, TaniLayout* L) {
+  const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kPadK), Np = round_up(N, kPadA);
+  Carver cv{base};
+  float* xp = cv.take<float>((size_t)Mp * Kp);
+  float* yp = cv.take<float>((size_t)Kp * Np);
+  float* op = cv.take<float>((size_t)Mp * Np);
+  float* pt = cv.take<float>(rect_partial_floats());
+  double* nx = cv.take<double>((size_t)Mp);
+  double* ny = cv.take<double>((size_t)Np);
+  double* sc = cv.take<double>((size_t)kColChunks * (size_t)Np);
+  if (L) *L = TaniLayout{xp, yp, op, pt, nx, ny, sc};
+  return cv.off;
+}
+}  // namespace
+
 size_t panda_tanimoto_workspace_bytes(int64_t M, int64_t K, int64_t N) {
   if (M < 1 || K < 1 || N < 1) return 0;
-  const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kBK), Np = round_up(N, kPadA);
-  return align_up((size_t)Mp * Kp * 4) + align_up((size_t)Kp * Np * 4) +
-         align_up((size_t)Mp * Np * 4);
+  return tanimoto_layout(M, K, N, nullptr, nullptr);
 }
 
 panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K, int64_t N,
@@ -341,19 +380,20 @@ panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K
   const size_t need = panda_tanimoto_workspace_bytes(M, K, N);
   if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
     return fail(PANDA_ERR_WORKSPACE, "tanimoto: workspace too small or misaligned%s");
-  const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kBK), Np = round_up(N, kPadA);
-  Carver cv{static_cast<char*>(workspace)};
-  float* Xp = cv.take<float>((size_t)Mp * Kp);
-  float* Yp = cv.take<float>((size_t)Kp * Np);
-  float* Op = cv.take<float>((size_t)Mp * Np);
-  HIP_TRY(hipMemsetAsync(Xp, 0, (size_t)Mp * Kp * 4, s));
-  HIP_TRY(hipMemsetAsync(Yp, 0, (size_t)Kp * Np * 4, s));
-  panda_status st = copy_in(Xp, Kp, X, M, K, s);
+  const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kPadK), Np = round_up(N, kPadA);
+  TaniLayout L;
+  tanimoto_layout(M, K, N, static_cast<char*>(workspace), &L);
+  HIP_TRY(hipMemsetAsync(L.Xp, 0, (size_t)Mp * Kp * 4, s));
+  HIP_TRY(hipMemsetAsync(L.Yp, 0, (size_t)Kp * Np * 4, s));
+  panda_status st = copy_in(L.Xp, Kp, X, M, K, s);
   if (st != PANDA_OK) return st;
-  st = copy_in(Yp, Np, Y, K, N, s);
+  st = copy_in(L.Yp, Np, Y, K, N, s);
   if (st != PANDA_OK) return st;
-  HIP_TRY(launch_tanimoto_store(Xp, Kp, Yp, Np, Mp, Np, Kp, M, N, Op, Np, nullptr, s));
-  HIP_TRY(hipMemcpy2DAsync(Out, (size_t)N * 4, Op, (size_t)Np * 4, (size_t)N * 4, (size_t)M,
+  HIP_TRY(launch_row_sqnorms(L.Xp, Mp, Kp, Kp, L.nx, nullptr, s));
+  HIP_TRY(launch_col_sqnorms(L.Yp, Kp, Np, Np, L.ny, L.scr, nullptr, s));
+  HIP_TRY(launch_tanimoto_store(L.Xp, Kp, L.Yp, Np, Mp, Np, Kp, M, N, L.nx, L.ny, L.Op, Np, L.part,
+                                nullptr, s));
+  HIP_TRY(hipMemcpy2DAsync(Out, (size_t)N * 4, L.Op, (size_t)Np * 4, (size_t)N * 4, (size_t)M,
                            hipMemcpyDeviceToDevice, s));
   return PANDA_OK;
 }
@@ -433,6 +473,15 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
     st = zscore(c->C, Na, Na, Nap, c->zs, s);
   }
   if (st != PANDA_OK) return st;
+  // squared norms of the loaded state (later iterations produce their own)
+  HIP_TRY(hipMemsetAsync(c->nP, 0, (size_t)Nep * 8, s));
+  HIP_TRY(hipMemsetAsync(c->nWr, 0, (size_t)Nep * 8, s));
+  HIP_TRY(hipMemsetAsync(c->nC, 0, (size_t)Nap * 8, s));
+  HIP_TRY(hipMemsetAsync(c->nWc, 0, (size_t)Nap * 8, s));
+  HIP_TRY(launch_row_sqnorms(c->P, Ne, Ne, Nep, c->nP, nullptr, s));
+  HIP_TRY(launch_col_sqnorms(c->C, Na, Na, Nap, c->nC, c->colscr, nullptr, s));
+  HIP_TRY(launch_row_sqnorms(c->W[0], Ne, Na, Nap, c->nWr, nullptr, s));
+  HIP_TRY(launch_col_sqnorms(c->W[0], Ne, Na, Nap, c->nWc, c->colscr, nullptr, s));
   HIP_TRY(launch_state_init(c->st, t, s));
   c->t0 = t;
   c->executed = 0;

@@ -29,49 +29,64 @@ struct Rule {
   int32_t update_last;
 };
 
-constexpr int kBK = 16;       // K-step of the GEMM main loop (floats)
-constexpr int kThreads = 256; // threads per GEMM block (4 waves of 64)
+constexpr int kThreads = 256;            // threads per block (4 waves of 64)
+constexpr int64_t kMaxStreamKBlocks = 1024;
+constexpr int kColChunks = 64;           // row chunks of the column-norm kernel
 
-// Padding of the internal state: rows of W / P to 64, genes to 256.
+// Padding of the internal state: TF dimension to 64, gene dimension to 128.
 constexpr int64_t kPadE = 64;
-constexpr int64_t kPadA = 256;
+constexpr int64_t kPadA = 128;
+constexpr int64_t kPadK = 32;            // K of a stand-alone similarity product
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ------------------------------------------------------------ launchers --
-// Similarity matrix T(X, Y) of padded operands: X is Mp x Kp (row-major,
-// k contiguous), Y is Kp x Np (row-major, n contiguous).  Mp % 64 == 0,
-// Np % 256 == 0, Kp % 16 == 0.  Out[i][j] written for i < M, j < N.
+// Rectangular similarity products (stream-K).  X is Mp x Kp (k contiguous),
+// Y is Kp x Np (n contiguous); Mp % 64 == 0, Np % 128 == 0, Kp % 32 == 0.
+// nx / ny are the FP64 squared norms of the rows of X / columns of Y.
+// part: rect_partial_floats() floats of split-tile scratch.
+int64_t rect_tiles(int64_t Mp, int64_t Np);
+size_t rect_partial_floats();
+
+// Out[i][j] = T(X, Y)_ij for i < M, j < N.
 hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, int64_t ldy,
                                  int64_t Mp, int64_t Np, int64_t Kp, int64_t M, int64_t N,
-                                 float* Out, int64_t ldo, const int32_t* gate, hipStream_t s);
+                                 const double* nx, const double* ny, float* Out, int64_t ldo,
+                                 float* part, const int32_t* gate, hipStream_t s);
 
-// A = T(W, C) fused with the W update of Eq. 2 and the h partials of Eq. 7.
+// A = T(W, C) fused with the W update of Eq. 2 and per-tile h partials (Eq. 7).
 hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* R, float* Wnew,
                                 int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
-                                Rule rule, double* hpart, const int32_t* gate, hipStream_t s);
-int64_t avail_wupdate_blocks(int64_t Nep, int64_t Nap);
+                                const double* nWrow, const double* nC, Rule rule, double* hpart,
+                                float* part, const int32_t* gate, hipStream_t s);
 
 // C update (Eq. 5) on the upper tiles of T(W^T, W) with mirror writes and
-// per-row partial sums for the sigma of Eq. 6.
+// per-row partial sums for the sigma of Eq. 6 (and |C_.j|^2).
 hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* C, int64_t ldc,
-                               int64_t Nap, int64_t Na, Rule rule, double2* cstat,
-                               const int32_t* gate, hipStream_t s);
+                               int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
+                               double2* cstat, double* csq, const int32_t* gate, hipStream_t s);
 int64_t coreg_slots(int64_t Nap);
 
 // P update, split over K: partial products of W W^T on upper tiles.
 hipError_t launch_coop_partial(const float* W, int64_t ldw, int64_t Nep, int64_t Nap, int splits,
-                               float* part, double* pnrm, const int32_t* gate, hipStream_t s);
+                               float* part, const int32_t* gate, hipStream_t s);
 int coop_splits(int64_t Nep, int64_t Nap);
 
-// Rest of the iteration: h, P finalisation and both diagonals.
+// Rest of the iteration: h, P finalisation, both diagonals, norm vectors.
 hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevState* st,
                            Rule rule, hipStream_t s);
-hipError_t launch_coop_finalize(const float* part, const double* pnrm, int splits, float* P,
-                                int64_t ldp, int64_t Ne, Rule rule, float* Tside,
+hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, const double* nWrow,
+                                float* P, int64_t ldp, int64_t Ne, Rule rule, float* Tside,
                                 const int32_t* gate, hipStream_t s);
-hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, float* C,
-                            int64_t ldc, int64_t Na, const double2* cstat, int64_t nslots,
-                            Rule rule, const DevState* st, hipStream_t s);
+hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, double* nP,
+                            float* C, int64_t ldc, int64_t Na, const double2* cstat,
+                            const double* csq, int64_t nslots, double* nC, Rule rule,
+                            const DevState* st, hipStream_t s);
+// Squared norms of the rows / columns of a rows x cols matrix with leading
+// dimension ld.  The column version needs kColChunks * cols doubles of scratch.
+hipError_t launch_row_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,
+                              const int32_t* gate, hipStream_t s);
+hipError_t launch_col_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,
+                              double* scratch, const int32_t* gate, hipStream_t s);
 
 // Z-score (Sec. II-A) on a strided matrix; scratch holds kZsBlocks + 8 doubles.
 constexpr int kZsBlocks = 1024;

@@ -1,7 +1,8 @@
 // Element-wise and reduction kernels of the PANDA iteration: the h of Eq. 7,
-// the second half of the P update (Eq. 5), the diagonal rule of Eq. 6 and the
-// z-score normalisation of Sec. II-A.  All reductions are FP64 and run in a
-// fixed order, so results do not depend on scheduling.
+// the second half of the P update (Eq. 5), the diagonal rule of Eq. 6, the
+// squared-norm vectors the similarity epilogues read, and the z-score
+// normalisation of Sec. II-A.  All reductions are FP64 and run in a fixed
+// order, so results do not depend on scheduling.
 #include "panda_internal.h"
 
 namespace panda {
@@ -44,10 +45,10 @@ __global__ __launch_bounds__(kRT) void k_finish_h(const double* __restrict__ hpa
 }
 
 // P update, second half (Eq. 5): for every i < j < Ne sum the split-K
-// partial products and norms, form T(W_i., W_j.) and write the damped value
-// at (i, j) and (j, i).
+// partial products, form T(W_i., W_j.) with the row norms of the new W and
+// write the damped value at (i, j) and (j, i).
 __global__ __launch_bounds__(kRT) void k_coop_finalize(
-    const float* __restrict__ part, const double* __restrict__ pnrm, int splits, int64_t Nep,
+    const float* __restrict__ part, int splits, int64_t Nep, const double* __restrict__ nW,
     float* __restrict__ P, int64_t ldp, int64_t Ne, double alpha, float* __restrict__ Tside,
     const int32_t* gate) {
   if (*gate == 0) return;
@@ -55,13 +56,9 @@ __global__ __launch_bounds__(kRT) void k_coop_finalize(
   if (e >= Ne * Ne) return;
   const int64_t i = e / Ne, j = e % Ne;
   if (i >= j) return;
-  double dot = 0.0, ni = 0.0, nj = 0.0;
-  for (int s = 0; s < splits; ++s) {
-    dot += (double)part[(int64_t)s * Nep * Nep + i * Nep + j];
-    ni += pnrm[(int64_t)s * Nep + i];
-    nj += pnrm[(int64_t)s * Nep + j];
-  }
-  const double den = ni + nj - fabs(dot);
+  double dot = 0.0;
+  for (int s = 0; s < splits; ++s) dot += (double)part[(int64_t)s * Nep * Nep + i * Nep + j];
+  const double den = nW[i] + nW[j] - fabs(dot);
   const double tv = den > 0.0 ? dot / sqrt(den) : 0.0;
   const float v = (float)((1.0 - alpha) * (double)P[i * ldp + j] + alpha * tv);
   P[i * ldp + j] = v;
@@ -72,27 +69,34 @@ __global__ __launch_bounds__(kRT) void k_coop_finalize(
   }
 }
 
-// Eq. 6 for both networks.  Blocks [0, Ne): row i of P, population std of
-// its off-diagonal entries by two passes over the row.  Remaining blocks:
-// one thread per row of C, from the per-slot (sum, sum of squares) written
-// by the C update.  New diagonal = (1 - alpha) old + f * mult * sigma *
-// exp(2 alpha t), f = alpha (default reading) or 1 (literal Eq. 6).
+// Eq. 6 for both networks, and the squared norms |P_i.|^2, |C_.j|^2 that the
+// next iteration's similarities need.  Blocks [0, Ne): row i of P, population
+// std of its off-diagonal entries by two passes over the row.  Remaining
+// blocks: one thread per row of C, from the per-slot (sum, sum of squares)
+// written by the C update.  New diagonal = (1 - alpha) old + f * mult *
+// sigma * exp(2 alpha t), f = alpha (default reading) or 1 (literal Eq. 6).
 __global__ __launch_bounds__(kRT) void k_diagonals(
     float* __restrict__ P, int64_t ldp, int64_t Ne, const float* __restrict__ Tside,
-    float* __restrict__ C, int64_t ldc, int64_t Na, const double2* __restrict__ cstat,
-    int64_t nslots, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st) {
+    double* __restrict__ nP, float* __restrict__ C, int64_t ldc, int64_t Na,
+    const double2* __restrict__ cstat, const double* __restrict__ csq, int64_t nslots,
+    double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st) {
   __shared__ double red[4];
   if (st->run_pc == 0) return;
   const double g = exp(2.0 * alpha * (double)st->t);
   const double f = diag_alpha ? alpha : 1.0;
   if ((int64_t)blockIdx.x < Ne) {
     const int64_t i = blockIdx.x;
-    const float* row = (Tside ? Tside : P) + i * ldp;
-    double s = 0.0;
+    const float* prow = P + i * ldp;
+    const float* row = Tside ? Tside + i * ldp : prow;
+    double s = 0.0, q2 = 0.0;
     for (int64_t m = threadIdx.x; m < Ne; m += kRT)
-      if (m != i) s += row[m];
+      if (m != i) {
+        s += row[m];
+        q2 += (double)prow[m] * (double)prow[m];
+      }
     const double n = (double)(Ne - 1);
     const double mean = Ne > 1 ? block_sum(s, red) / n : 0.0;
+    const double off2 = block_sum(q2, red);
     double q = 0.0;
     for (int64_t m = threadIdx.x; m < Ne; m += kRT)
       if (m != i) q += ((double)row[m] - mean) * ((double)row[m] - mean);
@@ -100,18 +104,22 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     if (threadIdx.x == 0) {
       const double mult = n_own ? (double)Ne : (double)Na;
       const double d = (double)P[i * ldp + i];
-      P[i * ldp + i] = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
+      const float dn = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
+      P[i * ldp + i] = dn;
+      nP[i] = off2 + (double)dn * (double)dn;
     }
     return;
   }
   const int64_t r = ((int64_t)blockIdx.x - Ne) * kRT + threadIdx.x;
   if (r >= Na) return;
-  double s1 = 0.0, s2 = 0.0;
+  double s1 = 0.0, s2 = 0.0, c2 = 0.0;
   for (int64_t sl = 0; sl < nslots; ++sl) {  // slot stride = ldc (both are the padded N_a)
     const double2 v = cstat[sl * ldc + r];
     s1 += v.x;
     s2 += v.y;
+    if (csq) c2 += csq[sl * ldc + r];
   }
+  if (!csq) c2 = s2;
   double var = 0.0;
   if (Na > 1) {
     const double n = (double)(Na - 1), mean = s1 / n;
@@ -120,7 +128,49 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
   }
   const double mult = n_own ? (double)Na : (double)Ne;
   const double d = (double)C[r * ldc + r];
-  C[r * ldc + r] = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
+  const float dn = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
+  C[r * ldc + r] = dn;
+  nC[r] = c2 + (double)dn * (double)dn;
+}
+
+// ---- squared norms --------------------------------------------------------
+__global__ __launch_bounds__(kRT) void k_row_sqnorms(const float* __restrict__ M, int64_t cols,
+                                                     int64_t ld, double* __restrict__ out,
+                                                     const int32_t* gate) {
+  __shared__ double red[4];
+  if (gate && *gate == 0) return;
+  const float* row = M + (int64_t)blockIdx.x * ld;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < cols; j += kRT) s += (double)row[j] * (double)row[j];
+  const double tot = block_sum(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+// Column sums of squares over row chunk blockIdx.y, into scratch[chunk][col].
+__global__ __launch_bounds__(kRT) void k_col_sqnorms_part(const float* __restrict__ M,
+                                                          int64_t rows, int64_t cols, int64_t ld,
+                                                          int64_t chunk, double* __restrict__ scr,
+                                                          const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t j = (int64_t)blockIdx.x * kRT + threadIdx.x;
+  if (j >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
+  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+  double s = 0.0;
+  for (int64_t i = r0; i < r1; ++i) s += (double)M[i * ld + j] * (double)M[i * ld + j];
+  scr[(int64_t)blockIdx.y * cols + j] = s;
+}
+
+__global__ __launch_bounds__(kRT) void k_col_sqnorms_sum(const double* __restrict__ scr,
+                                                         int64_t cols, int nchunks,
+                                                         double* __restrict__ out,
+                                                         const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t j = (int64_t)blockIdx.x * kRT + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += scr[(int64_t)c * cols + j];
+  out[j] = s;
 }
 
 // ---- z-score --------------------------------------------------------------
@@ -211,21 +261,44 @@ hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevSta
   return hipGetLastError();
 }
 
-hipError_t launch_coop_finalize(const float* part, const double* pnrm, int splits, float* P,
-                                int64_t ldp, int64_t Ne, Rule rule, float* Tside,
+hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, const double* nWrow,
+                                float* P, int64_t ldp, int64_t Ne, Rule rule, float* Tside,
                                 const int32_t* gate, hipStream_t s) {
   const int64_t n = Ne * Ne;
   k_coop_finalize<<<dim3((unsigned)((n + kRT - 1) / kRT)), kRT, 0, s>>>(
-      part, pnrm, splits, ldp, P, ldp, Ne, rule.alpha, Tside, gate);
+      part, splits, Nep, nWrow, P, ldp, Ne, rule.alpha, Tside, gate);
   return hipGetLastError();
 }
 
-hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, float* C,
-                            int64_t ldc, int64_t Na, const double2* cstat, int64_t nslots,
-                            Rule rule, const DevState* st, hipStream_t s) {
+hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, double* nP,
+                            float* C, int64_t ldc, int64_t Na, const double2* cstat,
+                            const double* csq, int64_t nslots, double* nC, Rule rule,
+                            const DevState* st, hipStream_t s) {
   const int64_t nb = Ne + (Na + kRT - 1) / kRT;
-  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, C, ldc, Na, cstat, nslots,
-                                                 rule.alpha, rule.diag_alpha, rule.n_own, st);
+  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, nP, C, ldc, Na, cstat, csq,
+                                                 nslots, nC, rule.alpha, rule.diag_alpha,
+                                                 rule.n_own, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,
+                              const int32_t* gate, hipStream_t s) {
+  k_row_sqnorms<<<dim3((unsigned)rows), kRT, 0, s>>>(M, cols, ld, out, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,
+                              double* scratch, const int32_t* gate, hipStream_t s) {
+  int nch = (int)((rows + 63) / 64);  // about 64 rows per chunk
+  if (nch > kColChunks) nch = kColChunks;
+  if (nch < 1) nch = 1;
+  const int64_t chunk = (rows + nch - 1) / nch;
+  const unsigned gx = (unsigned)((cols + kRT - 1) / kRT);
+  k_col_sqnorms_part<<<dim3(gx, (unsigned)nch), kRT, 0, s>>>(M, rows, cols, ld, chunk, scratch,
+                                                             gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_col_sqnorms_sum<<<dim3(gx), kRT, 0, s>>>(scratch, cols, nch, out, gate);
   return hipGetLastError();
 }
 

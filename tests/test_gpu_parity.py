@@ -147,7 +147,9 @@ def run_matched(torch, pd, oracle, W, P, C, opts_kw=None, steps=None, pass_ident
         Wo, Po, Co, ho, conv = oracle.step(Wo, Po, Co, t, o)
         hg, tg = ctx.iterate()
         assert tg == t
-        assert abs(hg - ho) <= 1e-6 * max(ho, 1e-3), (t, hg, ho)
+        # h is a mean of |dW| over FP32 entries: relative 1e-5 (FP32 sums of
+        # many terms with cancellation lose a few more bits than one ulp)
+        assert abs(hg - ho) <= 1e-5 * ho + 1e-9, (t, hg, ho)
         Wg, Pg, Cg, _, _ = ctx.state()
         compare_state(host(Wg), host(Pg), host(Cg), Wo, Po, Co, what=f"t={t}")
     return t, ctx
