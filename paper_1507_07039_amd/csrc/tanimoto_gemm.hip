@@ -30,6 +30,7 @@ namespace panda {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Logical number for block b of an n-block grid: contiguous chunks per XCD.
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
@@ -69,7 +70,7 @@ struct TileLoad {
   static_assert(NV >= 1, "tile too small for one float4 per thread");
   static_assert(KC ? (RP * NV == MN) : (RPP * NV == BK), "loads must cover the tile");
 
-  float4 v[NV];
+  f4 v[NV];
 
   __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int64_t mn0,
                                        int64_t k0, int t) {
@@ -78,14 +79,14 @@ struct TileLoad {
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
         const int mn = t / KQ + i * RP;
-        v[i] = *reinterpret_cast<const float4*>(base + (mn0 + mn) * ld + k0 + kq);
+        v[i] = *reinterpret_cast<const f4*>(base + (mn0 + mn) * ld + k0 + kq);
       }
     } else {
       const int mnq = (t % TPR) * 4;
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
         const int k = t / TPR + i * RPP;
-        v[i] = *reinterpret_cast<const float4*>(base + (k0 + k) * ld + mn0 + mnq);
+        v[i] = *reinterpret_cast<const f4*>(base + (k0 + k) * ld + mn0 + mnq);
       }
     }
   }
@@ -106,7 +107,7 @@ struct TileLoad {
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
         const int k = t / TPR + i * RPP;
-        *reinterpret_cast<float4*>(lds + k * LD + mnq) = v[i];
+        *reinterpret_cast<f4*>(lds + k * LD + mnq) = v[i];
       }
     }
   }
@@ -272,7 +273,7 @@ struct EpiWUpdate {
 };
 
 // ----------------------------------------------------- stream-K kernels --
-using RectGemm = BlockGemm<64, 128, 1, 4, true, false, 32>;
+using RectGemm = BlockGemm<64, 128, 1, 4, true, false, 16>;
 
 // Block L (logical) owns work items [L*total/G, (L+1)*total/G) of the
 // total = tiles * U items (U = K-steps per tile), tile-major, M fastest.
@@ -284,13 +285,12 @@ __device__ __forceinline__ int64_t sk_owner(int64_t i, int64_t total, int64_t G)
   return ((i + 1) * G - 1) / total;
 }
 
-template <class Epi>
+template <class G, class Epi>
 __global__ __launch_bounds__(kThreads) void k_rect_streamk(
     const float* __restrict__ X, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
     int64_t nMT, int64_t nTiles, int64_t U, Epi epi, float* __restrict__ part,
     const int32_t* gate) {
   if (gate && *gate == 0) return;
-  using G = RectGemm;
   __shared__ __align__(16) char smem[G::MAIN_BYTES];
   __shared__ double red[4];
   const int64_t nb = gridDim.x;
@@ -318,12 +318,11 @@ __global__ __launch_bounds__(kThreads) void k_rect_streamk(
 
 // Tiles whose K-steps were split between blocks: sum the partial products in
 // block order (deterministic) and run the same epilogue.
-template <class Epi>
+template <class G, class Epi>
 __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
                                                          int64_t nb, const float* __restrict__ part,
                                                          Epi epi, const int32_t* gate) {
   if (gate && *gate == 0) return;
-  using G = RectGemm;
   __shared__ double red[4];
   const int64_t tile = blockIdx.x;
   const int64_t total = nTiles * U;
@@ -355,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nT
 // sums are taken over the fresh similarities instead, and the sums of
 // squares of the updated entries (for |C_.j|^2) go to csq.
 constexpr int kCB = 128;
-using SymGemm = BlockGemm<kCB, kCB, 2, 2, false, false, 32>;
+using SymGemm = BlockGemm<kCB, kCB, 2, 2, false, false, 16>;
 constexpr int kSymLD = kCB + 1;
 
 template <bool SIGT>
@@ -376,16 +375,20 @@ __global__ __launch_bounds__(kThreads) void k_coreg_update(
   g.run(W, ldw, W, ldw, m0, n0, 0, Nep, smem);
   float* ts = reinterpret_cast<float*>(smem);  // updated values
   float* tt = ts + kCB * kSymLD;               // fresh T (SIGT only)
-  const double keep = 1.0 - alpha;
+  // The denominator here is built from column norms of W alone (no growing
+  // diagonal), so it is formed in FP64 and the rest runs in FP32:
+  // T = acc * rsqrt(den), C <- (1 - alpha) C + alpha T (about 2 ulp).
+  const float keep = (float)(1.0 - alpha), alf = (float)alpha;
   g.for_each([&](int rr, int c, float acc) {
     const int64_t gr = m0 + rr, gc = n0 + c;
     float v = 0.0f, tv = 0.0f;
     if (gr < gc && gc < Na) {
-      const double tsim = tanimoto((double)acc, ncol[gr], ncol[gc]);
+      const float den = (float)(ncol[gr] + ncol[gc] - fabs((double)acc));
+      const float tsim = den > 0.0f ? acc * __frsqrt_rn(den) : 0.0f;
       const int64_t o = gr * ldc + gc;
-      v = (float)(keep * (double)C[o] + alpha * tsim);
+      v = keep * C[o] + alf * tsim;
       C[o] = v;
-      tv = (float)tsim;
+      tv = tsim;
     }
     ts[rr * kSymLD + c] = v;
     if constexpr (SIGT) tt[rr * kSymLD + c] = tv;
@@ -469,40 +472,37 @@ __global__ __launch_bounds__(kThreads) void k_coop_partial(
 }
 
 // ------------------------------------------------------------------------
-// Grid size of the stream-K kernels: as many blocks as run at once, capped.
-int64_t resident_blocks() {
-  static int64_t cached = 0;
-  if (cached) return cached;
+// Blocks of kernel `fn` the whole GPU runs at once (CUs x occupancy).
+int64_t resident_blocks(const void* fn) {
   int dev = 0, cus = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &occ, reinterpret_cast<const void*>(&k_rect_streamk<EpiWUpdate>), kThreads, 0) !=
-          hipSuccess ||
-      occ <= 0)
-    occ = 2;
-  int64_t n = (int64_t)cus * occ;
-  if (n > kMaxStreamKBlocks) n = kMaxStreamKBlocks;
-  cached = n;
-  return n;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, 0) != hipSuccess || occ <= 0)
+    occ = 1;
+  return (int64_t)cus * occ;
 }
 
-template <class Epi>
+// Stream-K launch of a rectangular product; nb_max caps the grid (0: one
+// block per resident slot, at most kMaxStreamKBlocks).
+template <class G, class Epi>
 hipError_t launch_rect(const float* X, int64_t ldx, const float* Y, int64_t ldy, int64_t Mp,
                        int64_t Np, int64_t Kp, Epi epi, float* part, const int32_t* gate,
-                       hipStream_t s) {
-  const int64_t nMT = Mp / RectGemm::BM, nNT = Np / RectGemm::BN;
-  const int64_t nTiles = nMT * nNT, U = Kp / RectGemm::BK;
-  int64_t nb = resident_blocks();
+                       hipStream_t s, int64_t nb_max = 0) {
+  static int64_t resident = 0;
+  if (!resident) resident = resident_blocks(reinterpret_cast<const void*>(&k_rect_streamk<G, Epi>));
+  const int64_t nMT = Mp / G::BM, nNT = Np / G::BN;
+  const int64_t nTiles = nMT * nNT, U = Kp / G::BK;
+  int64_t nb = nb_max > 0 ? nb_max : resident;
+  if (nb > kMaxStreamKBlocks) nb = kMaxStreamKBlocks;
   if (nb > nTiles) nb = nTiles;
-  k_rect_streamk<Epi><<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(X, ldx, Y, ldy, nMT, nTiles,
-                                                                    U, epi, part, gate);
+  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(X, ldx, Y, ldy, nMT, nTiles,
+                                                                       U, epi, part, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_rect_fixup<Epi><<<dim3((unsigned)nTiles), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, part,
-                                                                      epi, gate);
+  k_rect_fixup<G, Epi><<<dim3((unsigned)nTiles), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, part,
+                                                                         epi, gate);
   return hipGetLastError();
 }
 
@@ -520,7 +520,7 @@ hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, in
                                  const double* nx, const double* ny, float* Out, int64_t ldo,
                                  float* part, const int32_t* gate, hipStream_t s) {
   EpiStoreT epi{Out, ldo, M, N, nx, ny};
-  return launch_rect(X, ldx, Y, ldy, Mp, Np, Kp, epi, part, gate, s);
+  return launch_rect<RectGemm>(X, ldx, Y, ldy, Mp, Np, Kp, epi, part, gate, s);
 }
 
 hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* R, float* Wnew,
@@ -528,7 +528,7 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* 
                                 const double* nWrow, const double* nC, Rule rule, double* hpart,
                                 float* part, const int32_t* gate, hipStream_t s) {
   EpiWUpdate epi{Wold, R, Wnew, ld, Ne, Na, nWrow, nC, rule.alpha, rule.h_undamped, hpart, 0.0};
-  return launch_rect(Wold, ld, C, ld, Nep, Nap, Nap, epi, part, gate, s);
+  return launch_rect<RectGemm>(Wold, ld, C, ld, Nep, Nap, Nap, epi, part, gate, s);
 }
 
 int64_t coreg_slots(int64_t Nap) { return Nap / kCB; }
