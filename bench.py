@@ -33,6 +33,7 @@ from paper_1507_07039_amd import inputs as I  # noqa: E402
 
 METRIC = "s/iteration & time-to-converge at T=700,G=18k: plain FP32 vs chosen form"
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
@@ -50,9 +51,10 @@ def gpu_inputs(w: I.Workload, torch, panda):
     return dev
 
 
-def time_iterations(torch, panda, W, P, C, steps: int, warmup: int):
+def time_iterations(torch, panda, W, P, C, steps: int, warmup: int, precision: int = 0):
     Ne, Na = W.shape
-    opts = panda.default_options(tol=0.0, max_iter=1 << 30)  # never stops inside the timing
+    # tol = 0: no iteration inside the timing is skipped by convergence
+    opts = panda.default_options(tol=0.0, max_iter=1 << 30, precision=precision)
     ctx = panda.Context(Ne, Na, opts)
     ctx.load(W, P, C)
     for _ in range(warmup):
@@ -72,15 +74,16 @@ def time_iterations(torch, panda, W, P, C, steps: int, warmup: int):
     return per, total, phases
 
 
-def time_to_converge(torch, panda, W, P, C, runs: int):
+def time_to_converge(torch, panda, W, P, C, runs: int, precision: int = 0):
     Ne, Na = W.shape
-    ws = panda.workspace(panda.workspace_bytes(Ne, Na))
+    opts = panda.default_options(precision=precision)
+    ws = panda.workspace(panda.workspace_bytes(Ne, Na, opts))
     out = (torch.empty_like(W), torch.empty_like(P), torch.empty_like(C))
     times, res = [], None
     for _ in range(runs):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = panda.run(W, P, C, ws=ws, out=out)
+        res = panda.run(W, P, C, opts=opts, ws=ws, out=out)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     return times, res
@@ -127,6 +130,7 @@ def main():
     ap.add_argument("--converge-runs", type=int, default=3)
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-only", action="store_true", help="skip the split-BF16 form")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -145,15 +149,20 @@ def main():
     log(f"workload {w.name}: generating priors")
     W, P, C = gpu_inputs(w, torch, panda)
     Ne, Na = W.shape
-    log("timing iterations")
-    per, total, phases = time_iterations(torch, panda, W, P, C, args.steps, args.warmup)
-    s_iter = statistics.median(per)
-    ms = {k: (v[0] / v[1] if v[1] else None) for k, v in phases.items()}
-    flops = {"R": 2.0 * Ne * Ne * Na, "A+W": 2.0 * Ne * Na * Na, "P-partial": 2.0 * Ne * Ne * Na,
+    flops = {"R": 2.0 * Ne * Ne * Na, "A+W": 2.0 * Ne * Na * Na, "P-partial": 1.0 * Ne * Ne * Na,
              "C": 1.0 * Ne * Na * Na}
-    rates = {k: flops[k] / (ms[k] * 1e-3) / 1e12 for k in flops if ms.get(k)}
-    aw_ms = ms["A+W"]
-    achieved = flops["A+W"] / (aw_ms * 1e-3) / 1e12
+
+    def measure(precision):
+        per, total, phases = time_iterations(torch, panda, W, P, C, args.steps, args.warmup,
+                                             precision)
+        ms = {k: (v[0] / v[1] if v[1] else None) for k, v in phases.items()}
+        rates = {k: flops[k] / (ms[k] * 1e-3) / 1e12 for k in flops if ms.get(k)}
+        return per, ms, rates
+
+    log("timing iterations (plain FP32)")
+    per, ms, rates = measure(0)
+    s_iter = statistics.median(per)
+    achieved = rates["A+W"]
     result = {
         "metric": METRIC, "value": s_iter, "unit": "s/iteration", "higher_is_better": False,
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": s_iter * 1e3,
@@ -162,17 +171,41 @@ def main():
                    "form": "plain-fp32", "parallelism": "single-gpu"},
         "s_per_iteration_p10_p90": [float(np.percentile(per, 10)), float(np.percentile(per, 90))],
         "phase_ms": ms, "phase_tflops": rates,
-        "roofline": {"bound": "mfma", "kernel": "k_avail_wupdate", "achieved": achieved,
-                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "kernel": "k_rect_streamk<RectF32, EpiWUpdate> (A+W)",
+                     "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None},
     }
+    if not args.plain_only:
+        log("timing iterations (split-BF16 form)")
+        per3, ms3, rates3 = measure(1)
+        # executed bf16 flops: three products per FP32-equivalent product
+        bf_rate = 3.0 * rates3["A+W"]
+        result["chosen_form"] = {
+            "form": "bf16x3", "s_per_iteration": statistics.median(per3),
+            "speedup_per_iteration": s_iter / statistics.median(per3),
+            "phase_ms": ms3, "phase_tflops_fp32_equivalent": rates3,
+            "roofline": {"bound": "mfma", "kernel": "k_rect_streamk<RectB3, EpiWUpdate> (A+W)",
+                         "achieved": bf_rate, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": bf_rate / PEAK_BF16_MFMA_TFLOPS, "traffic": None},
+        }
     if not args.no_converge:
-        log("time to converge")
+        log("time to converge (plain FP32)")
         times, res = time_to_converge(torch, panda, W, P, C, args.converge_runs)
         result["time_to_converge_s"] = statistics.median(times)
         result["iters_to_converge"] = res.iters
         result["h_final"] = res.h
         result["converged"] = res.status == panda.OK
+        if not args.plain_only:
+            Wp = res.W.clone()
+            log("time to converge (split-BF16 form)")
+            times3, res3 = time_to_converge(torch, panda, W, P, C, args.converge_runs, 1)
+            cf = result["chosen_form"]
+            cf["time_to_converge_s"] = statistics.median(times3)
+            cf["iters_to_converge"] = res3.iters
+            cf["converged"] = res3.status == panda.OK
+            cf["speedup_time_to_converge"] = result["time_to_converge_s"] / cf["time_to_converge_s"]
+            cf["max_abs_dW_vs_plain"] = (res3.W - Wp).abs().max().item()
+            cf["max_abs_W_plain"] = Wp.abs().max().item()
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -54,8 +54,16 @@ typedef enum {
   PANDA_ERR_WORKSPACE = -5   /* workspace missing, too small or misaligned     */
 } panda_status;
 
-/* Arithmetic of the similarity products. */
-enum { PANDA_PREC_FP32 = 0 /* FP32 MFMA, FP32 accumulate */ };
+/* Arithmetic of the similarity products (norms, denominators, h and the
+ * diagonal rule are FP64 in both forms; the state W, P, C is FP32):
+ *   PANDA_PREC_FP32    FP32 matrix-core products, FP32 accumulation.
+ *   PANDA_PREC_BF16X3  every operand split as x = hi + lo (bf16, round to
+ *                      nearest even) and each product formed as
+ *                      hi*hi + hi*lo + lo*hi on bf16 matrix cores with FP32
+ *                      accumulation; the diagonals of P and C are kept out
+ *                      of the split operands and their terms added in FP64.
+ *                      Needs about twice the workspace of C. */
+enum { PANDA_PREC_FP32 = 0, PANDA_PREC_BF16X3 = 1 };
 
 /* Run parameters and the readings of the paper where it is ambiguous.
  * panda_default_options() fills the defaults given in brackets. */

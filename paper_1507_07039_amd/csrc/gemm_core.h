@@ -1,0 +1,514 @@
+// Device building blocks of the similarity GEMMs: operand tile loaders, the
+// block-level MFMA main loops (FP32 and split-BF16), and the stream-K driver
+// shared by every rectangular product.
+//
+// Every similarity of the method is T(X, Y)_ij = (XY)_ij / sqrt(|X_i.|^2 +
+// |Y_.j|^2 - |(XY)_ij|) (Eq. 1), which Sec. II-C recasts as one matrix product
+// followed by an element-wise step on row and column norms (Eq. 9).  The
+// product runs on matrix cores; the element-wise step (and whatever update
+// rule consumes the similarity) is the epilogue of the same kernel.
+//
+// Operands are zero-padded to tile multiples by the host, so main loops have
+// no bounds checks; zero rows and columns add nothing to products.  The
+// stream-K driver gives every block of a grid as large as the GPU runs at
+// once an equal share of all (tile, K-step) items; tiles finished inside one
+// block get their epilogue at once, tiles shared by two blocks are summed in
+// block order by a fix-up kernel (deterministic, no block waits for another).
+// Logical block numbers are assigned XCD by XCD (the hardware hands block b
+// to XCD b % 8), so the tiles one XCD works on are contiguous and share
+// operand strips in its L2.
+#pragma once
+
+#include "panda_internal.h"
+
+namespace panda {
+namespace gemm {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Logical number for block b of an n-block grid: contiguous chunks per XCD.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+  const int64_t xcd = b & 7, slot = b >> 3;
+  const int64_t q = n >> 3, r = n & 7;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+// (I, J) with I <= J for upper-triangular tile number u = J(J+1)/2 + I.
+__device__ __forceinline__ void tri_tile(int64_t u, int64_t& I, int64_t& J) {
+  int64_t j = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+  while (j * (j + 1) / 2 > u) --j;
+  while ((j + 1) * (j + 2) / 2 <= u) ++j;
+  J = j;
+  I = u - j * (j + 1) / 2;
+}
+
+// Eq. 1 from the product and the two squared norms (FP64); T := 0 when the
+// denominator vanishes (both vectors zero).
+__device__ __forceinline__ double tanimoto(double dot, double xx, double yy) {
+  const double den = xx + yy - fabs(dot);
+  return den > 0.0 ? dot / sqrt(den) : 0.0;
+}
+
+// Deterministic sum of one double per thread over the 256-thread block.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// bf16 of x rounded to nearest even, as raw bits.
+__device__ __forceinline__ bf16_t to_bf16(float x) {
+  return __builtin_bit_cast(bf16_t, (__bf16)x);
+}
+__device__ __forceinline__ float from_bf16(bf16_t b) {
+  return (float)__builtin_bit_cast(__bf16, b);
+}
+// x = hi + lo + O(2^-17 |x|): hi = bf16(x), lo = bf16(x - hi).
+__device__ __forceinline__ void split_bf16(float x, bf16_t& hi, bf16_t& lo) {
+  hi = to_bf16(x);
+  lo = to_bf16(x - from_bf16(hi));
+}
+
+// ======================================================== FP32 main loop ==
+// One operand's MN x BK tile: global -> registers -> LDS.  KC: the operand
+// is contiguous along k in global memory (element (mn, k) at base[mn*ld+k]);
+// otherwise along mn (element at base[k*ld + mn]).  The LDS copy is always
+// [k][mn] with row length LD, the layout the MFMA operand reads want (32
+// consecutive mn per half-wave).  LD is padded so that the transposing
+// stores of the KC case hit every bank equally often.
+template <int MN, bool KC, int BK>
+struct TileLoad {
+  static constexpr int NV = MN * BK / 4 / kThreads;  // float4 per thread
+  static constexpr int KQ = BK / 4;                  // KC: threads per mn-row
+  static constexpr int RP = kThreads / KQ;           // KC: mn-rows per pass
+  static constexpr int TPR = MN / 4;                 // !KC: threads per k-row
+  static constexpr int RPP = kThreads / TPR;         // !KC: k-rows per pass
+  static constexpr int LD = KC ? MN + (BK == 32 ? 2 : 4) : MN + 4;
+  static_assert(NV >= 1, "tile too small for one float4 per thread");
+  static_assert(KC ? (RP * NV == MN) : (RPP * NV == BK), "loads must cover the tile");
+
+  f4 v[NV];
+
+  __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int64_t mn0,
+                                       int64_t k0, int t) {
+    if constexpr (KC) {
+      const int kq = (t % KQ) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int mn = t / KQ + i * RP;
+        v[i] = *reinterpret_cast<const f4*>(base + (mn0 + mn) * ld + k0 + kq);
+      }
+    } else {
+      const int mnq = (t % TPR) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int k = t / TPR + i * RPP;
+        v[i] = *reinterpret_cast<const f4*>(base + (k0 + k) * ld + mn0 + mnq);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(float* lds, int t) const {
+    if constexpr (KC) {
+      const int kq = (t % KQ) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int mn = t / KQ + i * RP;
+        lds[(kq + 0) * LD + mn] = v[i].x;
+        lds[(kq + 1) * LD + mn] = v[i].y;
+        lds[(kq + 2) * LD + mn] = v[i].z;
+        lds[(kq + 3) * LD + mn] = v[i].w;
+      }
+    } else {
+      const int mnq = (t % TPR) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int k = t / TPR + i * RPP;
+        *reinterpret_cast<f4*>(lds + k * LD + mnq) = v[i];
+      }
+    }
+  }
+};
+
+// FP32 operands: X element (m, k) = XK ? X[m*ldx + k] : X[k*ldx + m];
+// Y element (k, n) = YK ? Y[n*ldy + k] : Y[k*ldy + n].
+struct OpsF32 {
+  const float* X;
+  int64_t ldx;
+  const float* Y;
+  int64_t ldy;
+};
+
+// Block-level FP32 GEMM over k in [kbeg, kend) for a BM x BN tile with WM x WN
+// waves; each wave owns a (BM/WM) x (BN/WN) sub-tile of 32 x 32 MFMA blocks
+// (v_mfma_f32_32x32x2f32).
+template <int BM_, int BN_, int WM, int WN, bool XK, bool YK, int BK_>
+struct BlockGemm {
+  using Ops = OpsF32;
+  static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static_assert(WM * WN == 4, "four waves per block");
+  static constexpr int TM = BM / WM / 32;
+  static constexpr int TN = BN / WN / 32;
+  static_assert(TM >= 1 && TN >= 1, "wave tile below one MFMA block");
+  using LX = TileLoad<BM, XK, BK>;
+  using LY = TileLoad<BN, YK, BK>;
+  static constexpr int XS = BK * LX::LD;
+  static constexpr int YS = BK * LY::LD;
+  static constexpr int MAIN_BYTES = 2 * (XS + YS) * 4;
+
+  floatx16 acc[TM][TN];
+  int lane, wm, wn;
+
+  __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
+                                      int64_t kend, char* smem) {
+    const int t = threadIdx.x;
+    lane = t & 63;
+    const int w = t >> 6;
+    wm = w % WM;
+    wn = w / WM;
+    float* xs = reinterpret_cast<float*>(smem);
+    float* ys = xs + 2 * XS;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    LX lx;
+    LY ly;
+    const int64_t nk = (kend - kbeg) / BK;
+    if (nk > 0) {
+      lx.load(o.X, o.ldx, m0, kbeg, t);
+      ly.load(o.Y, o.ldy, n0, kbeg, t);
+      lx.store(xs, t);
+      ly.store(ys, t);
+    }
+    __syncthreads();
+    const int mrow = wm * (BM / WM) + (lane & 31);
+    const int ncol = wn * (BN / WN) + (lane & 31);
+    const int khalf = lane >> 5;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int cur = (int)(kt & 1);
+      const bool more = kt + 1 < nk;
+      if (more) {
+        lx.load(o.X, o.ldx, m0, kbeg + (kt + 1) * BK, t);
+        ly.load(o.Y, o.ldy, n0, kbeg + (kt + 1) * BK, t);
+      }
+      const float* xc = xs + cur * XS;
+      const float* yc = ys + cur * YS;
+#pragma unroll
+      for (int kk = 0; kk < BK / 2; ++kk) {
+        const int kr = 2 * kk + khalf;
+        float a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = xc[kr * LX::LD + mrow + i * 32];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = yc[kr * LY::LD + ncol + j * 32];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_iglp_opt(0);  // interleave LDS reads with the MFMAs
+      }
+      if (more) {
+        lx.store(xs + (cur ^ 1) * XS, t);
+        ly.store(ys + (cur ^ 1) * YS, t);
+      }
+      __syncthreads();
+    }
+  }
+
+  // Local (row, col) in the block tile of accumulator register r of MFMA
+  // block (i, j): the 32x32 result layout puts column lane%32 in each lane
+  // and rows 8*(r/4) + 4*(lane/32) + r%4.
+  __device__ __forceinline__ int row_of(int i, int r) const {
+    return wm * (BM / WM) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  }
+  __device__ __forceinline__ int col_of(int j) const {
+    return wn * (BN / WN) + j * 32 + (lane & 31);
+  }
+  template <class F>
+  __device__ __forceinline__ void for_each(F&& f) const {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int c = col_of(j);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) f(row_of(i, r), c, acc[i][j][r]);
+      }
+  }
+};
+
+// ================================================== split-BF16 main loop ==
+// Both operands are stored K-contiguous as two bf16 planes (hi, lo) with
+// x = hi + lo: X_hi/X_lo[m][k] and Yt_hi/Yt_lo[n][k] (Yt = Y transposed).
+// Each product is hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16 with an
+// FP32 accumulator; the dropped lo*lo term and the rounding of lo bound the
+// relative error of each product term by about 2^-16.
+struct OpsB3 {
+  const bf16_t* Xh;
+  const bf16_t* Xl;
+  int64_t ldx;
+  const bf16_t* Yh;
+  const bf16_t* Yl;
+  int64_t ldy;
+};
+
+// MN x 32 tile of one K-contiguous operand, both planes.  LDS rows are 64 B
+// (4 chunks of 8 bf16) with the chunk index XOR-swizzled by (row / 4) % 4,
+// so the 16 rows one ds_read_b128 group touches land in distinct banks.
+template <int MN>
+struct TileLoadB3 {
+  static constexpr int BK = 32;
+  static constexpr int CPR = BK / 8;        // 16-byte chunks per row and plane
+  static constexpr int RP = kThreads / CPR;  // rows per pass
+  static constexpr int NV = MN / RP;         // chunks per thread and plane
+  static constexpr int PLANE = MN * BK;      // bf16 per plane in LDS
+  static_assert(NV >= 1 && RP * NV == MN, "loads must cover the tile");
+
+  u4 h[NV], l[NV];
+
+  __device__ __forceinline__ static int swz(int row, int chunk) {
+    return row * BK + ((chunk ^ ((row >> 2) & 3)) << 3);
+  }
+  __device__ __forceinline__ void load(const bf16_t* __restrict__ H, const bf16_t* __restrict__ L,
+                                       int64_t ld, int64_t mn0, int64_t k0, int t) {
+    const int c = (t % CPR) * 8;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int r = t / CPR + i * RP;
+      h[i] = *reinterpret_cast<const u4*>(H + (mn0 + r) * ld + k0 + c);
+      l[i] = *reinterpret_cast<const u4*>(L + (mn0 + r) * ld + k0 + c);
+    }
+  }
+  __device__ __forceinline__ void store(bf16_t* lds, int t) const {
+    const int c = t % CPR;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int r = t / CPR + i * RP;
+      *reinterpret_cast<u4*>(lds + swz(r, c)) = h[i];
+      *reinterpret_cast<u4*>(lds + PLANE + swz(r, c)) = l[i];
+    }
+  }
+};
+
+template <int BM_, int BN_, int WM, int WN>
+struct BlockGemmB3 {
+  using Ops = OpsB3;
+  static constexpr int BM = BM_, BN = BN_, BK = 32;
+  static_assert(WM * WN == 4, "four waves per block");
+  static constexpr int TM = BM / WM / 32;
+  static constexpr int TN = BN / WN / 32;
+  static_assert(TM >= 1 && TN >= 1, "wave tile below one MFMA block");
+  using LX = TileLoadB3<BM>;
+  using LY = TileLoadB3<BN>;
+  static constexpr int XS = 2 * LX::PLANE;  // bf16 per stage
+  static constexpr int YS = 2 * LY::PLANE;
+  static constexpr int MAIN_BYTES = 2 * (XS + YS) * 2;
+
+  floatx16 acc[TM][TN];
+  int lane, wm, wn;
+
+  __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
+                                      int64_t kend, char* smem) {
+    const int t = threadIdx.x;
+    lane = t & 63;
+    const int w = t >> 6;
+    wm = w % WM;
+    wn = w / WM;
+    bf16_t* xs = reinterpret_cast<bf16_t*>(smem);
+    bf16_t* ys = xs + 2 * XS;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    LX lx;
+    LY ly;
+    const int64_t nk = (kend - kbeg) / BK;
+    if (nk > 0) {
+      lx.load(o.Xh, o.Xl, o.ldx, m0, kbeg, t);
+      ly.load(o.Yh, o.Yl, o.ldy, n0, kbeg, t);
+      lx.store(xs, t);
+      ly.store(ys, t);
+    }
+    __syncthreads();
+    const int mrow = wm * (BM / WM) + (lane & 31);
+    const int ncol = wn * (BN / WN) + (lane & 31);
+    const int khalf = lane >> 5;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int cur = (int)(kt & 1);
+      const bool more = kt + 1 < nk;
+      if (more) {
+        lx.load(o.Xh, o.Xl, o.ldx, m0, kbeg + (kt + 1) * BK, t);
+        ly.load(o.Yh, o.Yl, o.ldy, n0, kbeg + (kt + 1) * BK, t);
+      }
+      const bf16_t* xc = xs + cur * XS;
+      const bf16_t* yc = ys + cur * YS;
+#pragma unroll
+      for (int ks = 0; ks < BK / 16; ++ks) {
+        const int chunk = 2 * ks + khalf;  // this lane's 8 k-values of the 16-k step
+        bf16x8 xh[TM], xl[TM], yh[TN], yl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int off = LX::swz(mrow + i * 32, chunk);
+          xh[i] = *reinterpret_cast<const bf16x8*>(xc + off);
+          xl[i] = *reinterpret_cast<const bf16x8*>(xc + LX::PLANE + off);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int off = LY::swz(ncol + j * 32, chunk);
+          yh[j] = *reinterpret_cast<const bf16x8*>(yc + off);
+          yl[j] = *reinterpret_cast<const bf16x8*>(yc + LY::PLANE + off);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+      if (more) {
+        lx.store(xs + (cur ^ 1) * XS, t);
+        ly.store(ys + (cur ^ 1) * YS, t);
+      }
+      __syncthreads();
+    }
+  }
+
+  __device__ __forceinline__ int row_of(int i, int r) const {
+    return wm * (BM / WM) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  }
+  __device__ __forceinline__ int col_of(int j) const {
+    return wn * (BN / WN) + j * 32 + (lane & 31);
+  }
+  template <class F>
+  __device__ __forceinline__ void for_each(F&& f) const {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int c = col_of(j);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) f(row_of(i, r), c, acc[i][j][r]);
+      }
+  }
+};
+
+// ============================================================= stream-K ==
+// Block L (logical) owns work items [L*total/G, (L+1)*total/G) of the
+// total = tiles * U items (U = K-steps per tile), tile-major, M fastest.
+__device__ __forceinline__ int64_t sk_begin(int64_t L, int64_t total, int64_t G) {
+  return L * total / G;
+}
+// Logical block whose range holds item i (the largest L with begin <= i).
+__device__ __forceinline__ int64_t sk_owner(int64_t i, int64_t total, int64_t G) {
+  return ((i + 1) * G - 1) / total;
+}
+
+template <class G, class Epi>
+__global__ __launch_bounds__(kThreads) void k_rect_streamk(typename G::Ops ops, int64_t nMT,
+                                                           int64_t nTiles, int64_t U, Epi epi,
+                                                           float* __restrict__ part,
+                                                           const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  __shared__ __align__(16) char smem[G::MAIN_BYTES];
+  __shared__ double red[4];
+  const int64_t nb = gridDim.x;
+  const int64_t L = xcd_tile(blockIdx.x, nb);
+  const int64_t total = nTiles * U;
+  const int64_t b = sk_begin(L, total, nb), e = sk_begin(L + 1, total, nb);
+  G g;
+  int64_t it = b;
+  while (it < e) {
+    const int64_t tile = it / U;
+    const int64_t k0 = it - tile * U;
+    const int64_t k1 = (e - tile * U < U) ? e - tile * U : U;
+    const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
+    g.run(ops, m0, n0, k0 * G::BK, k1 * G::BK, smem);
+    if (k0 == 0 && k1 == U) {
+      g.for_each([&](int r, int c, float v) { epi.element(m0 + r, n0 + c, v); });
+      epi.end_tile(tile, red);
+    } else {
+      float* ps = part + (2 * L + (it == b ? 0 : 1)) * (int64_t)(G::BM * G::BN);
+      g.for_each([&](int r, int c, float v) { ps[r * G::BN + c] = v; });
+    }
+    it = tile * U + k1;
+  }
+}
+
+// Tiles whose K-steps were split between blocks: sum the partial products in
+// block order (deterministic) and run the same epilogue.
+template <class G, class Epi>
+__global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
+                                                         int64_t nb, const float* __restrict__ part,
+                                                         Epi epi, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  __shared__ double red[4];
+  const int64_t tile = blockIdx.x;
+  const int64_t total = nTiles * U;
+  const int64_t lo = sk_owner(tile * U, total, nb), hi = sk_owner((tile + 1) * U - 1, total, nb);
+  if (lo == hi) return;  // finished inside one block
+  const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
+  constexpr int E = G::BM * G::BN;
+  for (int e = threadIdx.x; e < E; e += kThreads) {
+    float s = 0.0f;
+    for (int64_t L = lo; L <= hi; ++L) {
+      const int64_t bL = sk_begin(L, total, nb);
+      if (bL == sk_begin(L + 1, total, nb)) continue;  // empty range
+      const int64_t slot = 2 * L + ((L == lo && bL < tile * U) ? 1 : 0);
+      s += part[slot * E + e];
+    }
+    epi.element(m0 + e / G::BN, n0 + e % G::BN, s);
+  }
+  epi.end_tile(tile, red);
+}
+
+// Blocks of kernel `fn` the whole GPU runs at once (CUs x occupancy).
+inline int64_t resident_blocks(const void* fn) {
+  int dev = 0, cus = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, 0) != hipSuccess || occ <= 0)
+    occ = 1;
+  return (int64_t)cus * occ;
+}
+
+// Stream-K launch of a rectangular product over an Mp x Np output with
+// K = Kp; part holds 2 * kMaxStreamKBlocks tiles.  nb_max caps the grid
+// (0: one block per resident slot).
+template <class G, class Epi>
+hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64_t Kp, Epi epi,
+                       float* part, const int32_t* gate, hipStream_t s, int64_t nb_max = 0) {
+  static int64_t resident = 0;
+  if (!resident) resident = resident_blocks(reinterpret_cast<const void*>(&k_rect_streamk<G, Epi>));
+  const int64_t nMT = Mp / G::BM, nNT = Np / G::BN;
+  const int64_t nTiles = nMT * nNT, U = Kp / G::BK;
+  int64_t nb = nb_max > 0 ? nb_max : resident;
+  if (nb > kMaxStreamKBlocks) nb = kMaxStreamKBlocks;
+  if (nb > nTiles) nb = nTiles;
+  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(ops, nMT, nTiles, U, epi,
+                                                                       part, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_rect_fixup<G, Epi><<<dim3((unsigned)nTiles), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, part,
+                                                                         epi, gate);
+  return hipGetLastError();
+}
+
+}  // namespace gemm
+}  // namespace panda

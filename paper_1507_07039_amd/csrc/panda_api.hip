@@ -67,7 +67,8 @@ panda_status check_options(const panda_options& o) {
   if (!(o.tol >= 0.0) || !isfinite(o.tol)) return fail(PANDA_ERR_ARG, "tol must be finite and >= 0%s");
   if (o.max_iter < 1) return fail(PANDA_ERR_ARG, "max_iter must be >= 1%s");
   if (o.poll_every < 1) return fail(PANDA_ERR_ARG, "poll_every must be >= 1%s");
-  if (o.precision != PANDA_PREC_FP32) return fail(PANDA_ERR_ARG, "unknown precision%s");
+  if (o.precision != PANDA_PREC_FP32 && o.precision != PANDA_PREC_BF16X3)
+    return fail(PANDA_ERR_ARG, "unknown precision%s");
   return PANDA_OK;
 }
 
@@ -100,6 +101,8 @@ struct panda_ctx {
   double* csq;
   double* zs;
   DevState* st;
+  bool b3;  // split-BF16 products
+  bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl, *Ch, *Cl;
   DevState* host;  // pinned
   int splits;
   int64_t nh;
@@ -118,7 +121,7 @@ struct panda_ctx {
 namespace {
 
 // Workspace layout shared by the size query and the context.
-size_t layout(int64_t Ne, int64_t Na, panda_ctx* c, char* base) {
+size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* base) {
   const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
   Carver cv{base};
   const size_t nw = (size_t)Nep * (size_t)Nap;
@@ -142,6 +145,19 @@ size_t layout(int64_t Ne, int64_t Na, panda_ctx* c, char* base) {
   double* cq = cv.take<double>((size_t)coreg_slots(Nap) * Nap);
   double* zs = cv.take<double>(kZsScratch);
   DevState* st = cv.take<DevState>(1);
+  // split-BF16 operand planes
+  const bool b3 = precision == PANDA_PREC_BF16X3;
+  bf16_t* sh[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (b3) {
+    sh[0] = cv.take<bf16_t>(nw);                   // W hi, row-major
+    sh[1] = cv.take<bf16_t>(nw);                   // W lo
+    sh[2] = cv.take<bf16_t>(nw);                   // W^T hi, gene-major
+    sh[3] = cv.take<bf16_t>(nw);                   // W^T lo
+    sh[4] = cv.take<bf16_t>((size_t)Nep * Nep);    // P hi, zero diagonal
+    sh[5] = cv.take<bf16_t>((size_t)Nep * Nep);    // P lo
+    sh[6] = cv.take<bf16_t>((size_t)Nap * Nap);    // C hi, zero diagonal
+    sh[7] = cv.take<bf16_t>((size_t)Nap * Nap);    // C lo
+  }
   if (c) {
     c->Nep = Nep;
     c->Nap = Nap;
@@ -165,6 +181,15 @@ size_t layout(int64_t Ne, int64_t Na, panda_ctx* c, char* base) {
     c->csq = cq;
     c->zs = zs;
     c->st = st;
+    c->b3 = b3;
+    c->Wh = sh[0];
+    c->Wl = sh[1];
+    c->Wth = sh[2];
+    c->Wtl = sh[3];
+    c->Ph = sh[4];
+    c->Pl = sh[5];
+    c->Ch = sh[6];
+    c->Cl = sh[7];
   }
   return cv.off;
 }
@@ -231,27 +256,48 @@ panda_status enqueue_iteration(panda_ctx* c) {
   const int32_t* run_pc = &c->st->run_pc;
   PANDA_TRY(mark(c, PANDA_PHASE_R));
   // Eq. 3: R = T(P, W), K = N_e
-  HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
-                                c->nP, c->nWc, c->R, c->Nap, c->skpart, active, s));
+  if (c->b3)
+    HIP_TRY(launch_resp_b3(c->Ph, c->Pl, c->Nep, c->Wth, c->Wtl, c->Nep, c->Nep, c->Nap, c->Ne,
+                           c->Na, c->P, Wold, c->Nap, c->nP, c->nWc, c->R, c->skpart, active, s));
+  else
+    HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
+                                  c->nP, c->nWc, c->R, c->Nap, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_AW));
   // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
-  HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
-                               c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s));
+  if (c->b3)
+    HIP_TRY(launch_avail_wupdate_b3(c->Wh, c->Wl, c->Ch, c->Cl, Wold, c->C, c->R, Wnew, c->Nap,
+                                    c->Nep, c->Nap, c->Ne, c->Na, c->nWr, c->nC, c->rule,
+                                    c->hpart, c->skpart, active, s));
+  else
+    HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
+                                 c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_H));
   HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
-  // squared norms of the rows and columns of the new W
+  // squared norms (and split planes) of the new W
   HIP_TRY(launch_row_sqnorms(Wnew, c->Ne, c->Na, c->Nap, c->nWr, run_pc, s));
   HIP_TRY(launch_col_sqnorms(Wnew, c->Ne, c->Na, c->Nap, c->nWc, c->colscr, run_pc, s));
+  if (c->b3)
+    HIP_TRY(launch_w_shadows(Wnew, c->Ne, c->Na, c->Nap, c->Wh, c->Wl, c->Wth, c->Wtl, c->Nep,
+                             run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_PPART));
   // Eq. 5, P: T(W_i., W_m.) of the new W
-  HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, run_pc, s));
+  if (c->b3)
+    HIP_TRY(launch_coop_partial_b3(c->Wh, c->Wl, c->Nap, c->Nep, c->Nap, c->splits, c->ppart,
+                                   run_pc, s));
+  else
+    HIP_TRY(launch_coop_partial(Wnew, c->Nap, c->Nep, c->Nap, c->splits, c->ppart, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_PFIN));
   HIP_TRY(launch_coop_finalize(c->ppart, c->splits, c->Nep, c->nWr, c->P, c->Nep, c->Ne, c->rule,
-                               c->rule.sigma_from_T ? c->Tside : nullptr, run_pc, s));
+                               c->rule.sigma_from_T ? c->Tside : nullptr, c->Ph, c->Pl, run_pc,
+                               s));
   PANDA_TRY(mark(c, PANDA_PHASE_C));
   // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
-  HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc, c->rule,
-                              c->cstat, c->csq, run_pc, s));
+  if (c->b3)
+    HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Ch, c->Cl, c->Nap,
+                                   c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, run_pc, s));
+  else
+    HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc,
+                                c->rule, c->cstat, c->csq, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_DIAG));
   // Eq. 6, and |P_i.|^2, |C_.j|^2 for the next iteration
   HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->nP,
@@ -401,7 +447,7 @@ panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K
 size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt) {
   (void)opt;
   if (!dims_ok(Ne, Na)) return 0;
-  return layout(Ne, Na, nullptr, nullptr);
+  return layout(Ne, Na, opt ? opt->precision : PANDA_PREC_FP32, nullptr, nullptr);
 }
 
 panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, void* workspace,
@@ -426,7 +472,7 @@ panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, 
   c->opt = o;
   c->rule = rule_of(o);
   c->stream = stream;
-  layout(Ne, Na, c, static_cast<char*>(workspace));
+  layout(Ne, Na, o.precision, c, static_cast<char*>(workspace));
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(DevState),
                                hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -482,6 +528,21 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
   HIP_TRY(launch_col_sqnorms(c->C, Na, Na, Nap, c->nC, c->colscr, nullptr, s));
   HIP_TRY(launch_row_sqnorms(c->W[0], Ne, Na, Nap, c->nWr, nullptr, s));
   HIP_TRY(launch_col_sqnorms(c->W[0], Ne, Na, Nap, c->nWc, c->colscr, nullptr, s));
+  if (c->b3) {
+    // planes of the loaded state; padding and the P/C diagonals stay zero
+    const size_t nw = (size_t)Nep * Nap;
+    HIP_TRY(hipMemsetAsync(c->Wh, 0, nw * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Wl, 0, nw * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Wth, 0, nw * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Wtl, 0, nw * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Ph, 0, (size_t)Nep * Nep * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Pl, 0, (size_t)Nep * Nep * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Ch, 0, (size_t)Nap * Nap * 2, s));
+    HIP_TRY(hipMemsetAsync(c->Cl, 0, (size_t)Nap * Nap * 2, s));
+    HIP_TRY(launch_w_shadows(c->W[0], Ne, Na, Nap, c->Wh, c->Wl, c->Wth, c->Wtl, Nep, nullptr, s));
+    HIP_TRY(launch_split_offdiag(c->P, Ne, Nep, c->Ph, c->Pl, s));
+    HIP_TRY(launch_split_offdiag(c->C, Na, Nap, c->Ch, c->Cl, s));
+  }
   HIP_TRY(launch_state_init(c->st, t, s));
   c->t0 = t;
   c->executed = 0;

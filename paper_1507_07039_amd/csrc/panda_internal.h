@@ -29,6 +29,8 @@ struct Rule {
   int32_t update_last;
 };
 
+typedef unsigned short bf16_t;           // raw bits of a bfloat16
+
 constexpr int kThreads = 256;            // threads per block (4 waves of 64)
 constexpr int64_t kMaxStreamKBlocks = 1024;
 constexpr int kColChunks = 64;           // row chunks of the column-norm kernel
@@ -71,12 +73,41 @@ hipError_t launch_coop_partial(const float* W, int64_t ldw, int64_t Nep, int64_t
                                float* part, const int32_t* gate, hipStream_t s);
 int coop_splits(int64_t Nep, int64_t Nap);
 
+// Split-BF16 forms of the same products.  Operands are K-contiguous hi/lo
+// planes: P (diagonal zero), W row-major, W^T (gene-major), C (diagonal zero).
+hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const bf16_t* Wth,
+                          const bf16_t* Wtl, int64_t ldwt, int64_t Nep, int64_t Nap, int64_t Ne,
+                          int64_t Na, const float* P, const float* W, int64_t ldw,
+                          const double* nP, const double* nWc, float* R, float* part,
+                          const int32_t* gate, hipStream_t s);
+hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const bf16_t* Ch,
+                                   const bf16_t* Cl, const float* Wold, const float* C,
+                                   const float* R, float* Wnew, int64_t ld, int64_t Nep,
+                                   int64_t Nap, int64_t Ne, int64_t Na, const double* nWrow,
+                                   const double* nC, Rule rule, double* hpart, float* part,
+                                   const int32_t* gate, hipStream_t s);
+hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
+                                  float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
+                                  int64_t Na, const double* nWcol, Rule rule, double2* cstat,
+                                  double* csq, const int32_t* gate, hipStream_t s);
+hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ldw, int64_t Nep,
+                                  int64_t Nap, int splits, float* part, const int32_t* gate,
+                                  hipStream_t s);
+// hi/lo planes of W (Ne x Na, leading dimension ldw) row-major (ld ldw) and
+// transposed (Na x Ne, leading dimension ldt).
+hipError_t launch_w_shadows(const float* W, int64_t Ne, int64_t Na, int64_t ldw, bf16_t* Wh,
+                            bf16_t* Wl, bf16_t* Wth, bf16_t* Wtl, int64_t ldt, const int32_t* gate,
+                            hipStream_t s);
+// hi/lo planes of an n x n matrix with its diagonal left zero.
+hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* Mh, bf16_t* Ml,
+                                hipStream_t s);
+
 // Rest of the iteration: h, P finalisation, both diagonals, norm vectors.
 hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevState* st,
                            Rule rule, hipStream_t s);
 hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, const double* nWrow,
                                 float* P, int64_t ldp, int64_t Ne, Rule rule, float* Tside,
-                                const int32_t* gate, hipStream_t s);
+                                bf16_t* Ph, bf16_t* Pl, const int32_t* gate, hipStream_t s);
 hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, double* nP,
                             float* C, int64_t ldc, int64_t Na, const double2* cstat,
                             const double* csq, int64_t nslots, double* nC, Rule rule,

@@ -47,10 +47,19 @@ __global__ __launch_bounds__(kRT) void k_finish_h(const double* __restrict__ hpa
 // P update, second half (Eq. 5): for every i < j < Ne sum the split-K
 // partial products, form T(W_i., W_j.) with the row norms of the new W and
 // write the damped value at (i, j) and (j, i).
+__device__ __forceinline__ bf16_t to_bf16(float x) {
+  return __builtin_bit_cast(bf16_t, (__bf16)x);
+}
+// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even.
+__device__ __forceinline__ void split_bf16(float x, bf16_t& hi, bf16_t& lo) {
+  hi = to_bf16(x);
+  lo = to_bf16(x - (float)__builtin_bit_cast(__bf16, hi));
+}
+
 __global__ __launch_bounds__(kRT) void k_coop_finalize(
     const float* __restrict__ part, int splits, int64_t Nep, const double* __restrict__ nW,
     float* __restrict__ P, int64_t ldp, int64_t Ne, double alpha, float* __restrict__ Tside,
-    const int32_t* gate) {
+    bf16_t* __restrict__ Ph, bf16_t* __restrict__ Pl, const int32_t* gate) {
   if (*gate == 0) return;
   const int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x;
   if (e >= Ne * Ne) return;
@@ -63,6 +72,12 @@ __global__ __launch_bounds__(kRT) void k_coop_finalize(
   const float v = (float)((1.0 - alpha) * (double)P[i * ldp + j] + alpha * tv);
   P[i * ldp + j] = v;
   P[j * ldp + i] = v;
+  if (Ph) {
+    bf16_t h, l;
+    split_bf16(v, h, l);
+    Ph[i * ldp + j] = Ph[j * ldp + i] = h;
+    Pl[i * ldp + j] = Pl[j * ldp + i] = l;
+  }
   if (Tside) {
     Tside[i * ldp + j] = (float)tv;
     Tside[j * ldp + i] = (float)tv;
@@ -131,6 +146,57 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
   const float dn = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
   C[r * ldc + r] = dn;
   nC[r] = c2 + (double)dn * (double)dn;
+}
+
+// ---- split-BF16 operand planes ----------------------------------------------
+// 64 x 64 tiles of W through LDS: row-major planes written along rows, the
+// transposed planes along genes, both coalesced.  Only the real Ne x Na
+// region is written; the padding of the planes stays zero.
+__global__ __launch_bounds__(kRT) void k_w_shadows(const float* __restrict__ W, int64_t Ne,
+                                                   int64_t Na, int64_t ldw, bf16_t* __restrict__ Wh,
+                                                   bf16_t* __restrict__ Wl,
+                                                   bf16_t* __restrict__ Wth,
+                                                   bf16_t* __restrict__ Wtl, int64_t ldt,
+                                                   const int32_t* gate) {
+  __shared__ float tile[64][65];
+  if (gate && *gate == 0) return;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    float v = 0.0f;
+    if (r < Ne && c < Na) {
+      v = W[r * ldw + c];
+      bf16_t h, l;
+      split_bf16(v, h, l);
+      Wh[r * ldw + c] = h;
+      Wl[r * ldw + c] = l;
+    }
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t c = c0 + cc, r = r0 + tx;
+    if (r < Ne && c < Na) {
+      bf16_t h, l;
+      split_bf16(tile[tx][cc], h, l);
+      Wth[c * ldt + r] = h;
+      Wtl[c * ldt + r] = l;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_split_offdiag(const float* __restrict__ M, int64_t n,
+                                                       int64_t ld, bf16_t* __restrict__ Mh,
+                                                       bf16_t* __restrict__ Ml) {
+  const int64_t tot = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * kRT) {
+    const int64_t i = e / n, j = e % n;
+    bf16_t h = 0, l = 0;
+    if (i != j) split_bf16(M[i * ld + j], h, l);
+    Mh[i * ld + j] = h;
+    Ml[i * ld + j] = l;
+  }
 }
 
 // ---- squared norms --------------------------------------------------------
@@ -263,10 +329,24 @@ hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevSta
 
 hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, const double* nWrow,
                                 float* P, int64_t ldp, int64_t Ne, Rule rule, float* Tside,
-                                const int32_t* gate, hipStream_t s) {
+                                bf16_t* Ph, bf16_t* Pl, const int32_t* gate, hipStream_t s) {
   const int64_t n = Ne * Ne;
   k_coop_finalize<<<dim3((unsigned)((n + kRT - 1) / kRT)), kRT, 0, s>>>(
-      part, splits, Nep, nWrow, P, ldp, Ne, rule.alpha, Tside, gate);
+      part, splits, Nep, nWrow, P, ldp, Ne, rule.alpha, Tside, Ph, Pl, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_shadows(const float* W, int64_t Ne, int64_t Na, int64_t ldw, bf16_t* Wh,
+                            bf16_t* Wl, bf16_t* Wth, bf16_t* Wtl, int64_t ldt, const int32_t* gate,
+                            hipStream_t s) {
+  const dim3 grid((unsigned)((Na + 63) / 64), (unsigned)((Ne + 63) / 64));
+  k_w_shadows<<<grid, kRT, 0, s>>>(W, Ne, Na, ldw, Wh, Wl, Wth, Wtl, ldt, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* Mh, bf16_t* Ml,
+                                hipStream_t s) {
+  k_split_offdiag<<<grid_for(n * n, 8192), kRT, 0, s>>>(M, n, ld, Mh, Ml);
   return hipGetLastError();
 }
 
