@@ -10,13 +10,8 @@
 //
 // Operands are zero-padded to tile multiples by the host, so main loops have
 // no bounds checks; zero rows and columns add nothing to products.  The
-// stream-K driver gives every block of a grid as large as the GPU runs at
-// once an equal share of all (tile, K-step) items; tiles finished inside one
-// block get their epilogue at once, tiles shared by two blocks are summed in
-// block order by a fix-up kernel (deterministic, no block waits for another).
-// Logical block numbers are assigned XCD by XCD (the hardware hands block b
-// to XCD b % 8), so the tiles one XCD works on are contiguous and share
-// operand strips in its L2.
+// rectangular products share one tile schedule (whole tiles in full rounds,
+// the remainder split stream-K style), described at k_rect_streamk.
 #pragma once
 
 #include "panda_internal.h"
@@ -52,14 +47,17 @@ __device__ __forceinline__ double tanimoto(double dot, double xx, double yy) {
   return den > 0.0 ? dot / sqrt(den) : 0.0;
 }
 
-// Deterministic sum of one double per thread over the 256-thread block.
+// Deterministic sum of one double per thread over the block (at most 8
+// waves); red holds one double per wave.
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return ((red[0] + red[1]) + red[2]) + red[3];
+  double s = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
 }
 
 // bf16 of x rounded to nearest even, as raw bits.
@@ -151,7 +149,7 @@ struct OpsF32 {
 template <int BM_, int BN_, int WM, int WN, bool XK, bool YK, int BK_>
 struct BlockGemm {
   using Ops = OpsF32;
-  static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = kThreads;
   static_assert(WM * WN == 4, "four waves per block");
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
@@ -263,25 +261,29 @@ struct OpsB3 {
   int64_t ldy;
 };
 
-// MN x 32 tile of one K-contiguous operand, both planes.  LDS rows are 64 B
-// (4 chunks of 8 bf16) with the chunk index XOR-swizzled by (row / 4) % 4,
-// so the 16 rows one ds_read_b128 group touches land in distinct banks.
-template <int MN>
+// MN x BK tile of one K-contiguous operand, both planes, loaded by NT
+// threads.  LDS rows are BK bf16 (chunks of 8 bf16 = 16 B) with the chunk
+// index XOR-swizzled by the row's bank group, so the 16 rows one
+// ds_read_b128 group touches land in distinct banks.
+template <int MN, int NT, int BK_>
 struct TileLoadB3 {
-  static constexpr int BK = 32;
+  static constexpr int BK = BK_;
   static constexpr int CPR = BK / 8;        // 16-byte chunks per row and plane
-  static constexpr int RP = kThreads / CPR;  // rows per pass
-  static constexpr int NV = MN / RP;         // chunks per thread and plane
-  static constexpr int PLANE = MN * BK;      // bf16 per plane in LDS
-  static_assert(NV >= 1 && RP * NV == MN, "loads must cover the tile");
+  static constexpr int RP = NT / CPR;       // rows per pass
+  static constexpr int NV = MN >= RP ? MN / RP : 1;  // chunks per thread and plane
+  static constexpr bool ALL = MN >= RP;     // every thread loads (else t < MN * CPR)
+  static constexpr int PLANE = MN * BK;     // bf16 per plane in LDS
+  static constexpr int RG = 64 / (BK / 2);  // rows sharing a bank offset
+  static_assert(ALL ? RP * NV == MN : RP % MN == 0, "loads must cover the tile");
 
   u4 h[NV], l[NV];
 
   __device__ __forceinline__ static int swz(int row, int chunk) {
-    return row * BK + ((chunk ^ ((row >> 2) & 3)) << 3);
+    return row * BK + ((chunk ^ ((row / RG) & (CPR - 1))) << 3);
   }
   __device__ __forceinline__ void load(const bf16_t* __restrict__ H, const bf16_t* __restrict__ L,
                                        int64_t ld, int64_t mn0, int64_t k0, int t) {
+    if (!ALL && t >= MN * CPR) return;
     const int c = (t % CPR) * 8;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -291,6 +293,7 @@ struct TileLoadB3 {
     }
   }
   __device__ __forceinline__ void store(bf16_t* lds, int t) const {
+    if (!ALL && t >= MN * CPR) return;
     const int c = t % CPR;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -301,16 +304,19 @@ struct TileLoadB3 {
   }
 };
 
-template <int BM_, int BN_, int WM, int WN>
+// Block-level split-BF16 GEMM, WM x WN waves of (BM/WM) x (BN/WN) each.
+// All fragments of a K-tile are read from LDS before its MFMAs are issued,
+// so the LDS latency is paid once per tile rather than once per 16-k step.
+template <int BM_, int BN_, int WM, int WN, int BK_ = 32>
 struct BlockGemmB3 {
   using Ops = OpsB3;
-  static constexpr int BM = BM_, BN = BN_, BK = 32;
-  static_assert(WM * WN == 4, "four waves per block");
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
+  static constexpr int KS = BK / 16;  // MFMA k-steps per K-tile
   static_assert(TM >= 1 && TN >= 1, "wave tile below one MFMA block");
-  using LX = TileLoadB3<BM>;
-  using LY = TileLoadB3<BN>;
+  using LX = TileLoadB3<BM, NT, BK>;
+  using LY = TileLoadB3<BN, NT, BK>;
   static constexpr int XS = 2 * LX::PLANE;  // bf16 per stage
   static constexpr int YS = 2 * LY::PLANE;
   static constexpr int MAIN_BYTES = 2 * (XS + YS) * 2;
@@ -355,31 +361,33 @@ struct BlockGemmB3 {
       }
       const bf16_t* xc = xs + cur * XS;
       const bf16_t* yc = ys + cur * YS;
+      bf16x8 xh[KS][TM], xl[KS][TM], yh[KS][TN], yl[KS][TN];
 #pragma unroll
-      for (int ks = 0; ks < BK / 16; ++ks) {
+      for (int ks = 0; ks < KS; ++ks) {
         const int chunk = 2 * ks + khalf;  // this lane's 8 k-values of the 16-k step
-        bf16x8 xh[TM], xl[TM], yh[TN], yl[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
           const int off = LX::swz(mrow + i * 32, chunk);
-          xh[i] = *reinterpret_cast<const bf16x8*>(xc + off);
-          xl[i] = *reinterpret_cast<const bf16x8*>(xc + LX::PLANE + off);
+          xh[ks][i] = *reinterpret_cast<const bf16x8*>(xc + off);
+          xl[ks][i] = *reinterpret_cast<const bf16x8*>(xc + LX::PLANE + off);
         }
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int off = LY::swz(ncol + j * 32, chunk);
-          yh[j] = *reinterpret_cast<const bf16x8*>(yc + off);
-          yl[j] = *reinterpret_cast<const bf16x8*>(yc + LY::PLANE + off);
+          yh[ks][j] = *reinterpret_cast<const bf16x8*>(yc + off);
+          yl[ks][j] = *reinterpret_cast<const bf16x8*>(yc + LY::PLANE + off);
         }
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ks][i], yl[ks][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ks][i], yh[ks][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ks][i], yh[ks][j], acc[i][j], 0, 0, 0);
           }
-      }
       if (more) {
         lx.store(xs + (cur ^ 1) * XS, t);
         ly.store(ys + (cur ^ 1) * YS, t);
@@ -407,59 +415,82 @@ struct BlockGemmB3 {
   }
 };
 
-// ============================================================= stream-K ==
-// Block L (logical) owns work items [L*total/G, (L+1)*total/G) of the
-// total = tiles * U items (U = K-steps per tile), tile-major, M fastest.
+// ======================================================= tile schedule ==
+// A grid of nb blocks (as many as the GPU runs at once) covers nTiles output
+// tiles of U K-steps each in two parts:
+//   full rounds: with R = nTiles / nb, block L computes tiles L, L + nb, ...,
+//     L + (R-1) nb whole.  Consecutive tiles (M fastest, sharing a strip of
+//     the Y operand) run on one XCD at the same time, so that strip is
+//     fetched from memory about once per round.
+//   tail: the remaining nTiles - R nb tiles are split stream-K style: block L
+//     owns items [L*total/nb, (L+1)*total/nb) of their total = tail * U
+//     K-steps; tiles finished inside one block get their epilogue at once,
+//     tiles shared by blocks are summed in block order by the fix-up kernel
+//     (deterministic; no block ever waits for another).
+// Logical block numbers are assigned XCD by XCD (the hardware hands block b to
+// XCD b % 8), so one XCD works on contiguous tiles.
 __device__ __forceinline__ int64_t sk_begin(int64_t L, int64_t total, int64_t G) {
   return L * total / G;
 }
-// Logical block whose range holds item i (the largest L with begin <= i).
+// Logical block whose tail range holds item i (the largest L with begin <= i).
 __device__ __forceinline__ int64_t sk_owner(int64_t i, int64_t total, int64_t G) {
   return ((i + 1) * G - 1) / total;
 }
 
 template <class G, class Epi>
-__global__ __launch_bounds__(kThreads) void k_rect_streamk(typename G::Ops ops, int64_t nMT,
-                                                           int64_t nTiles, int64_t U, Epi epi,
-                                                           float* __restrict__ part,
-                                                           const int32_t* gate) {
+__global__ __launch_bounds__(G::NT) void k_rect_streamk(typename G::Ops ops, int64_t nMT,
+                                                        int64_t nTiles, int64_t U, Epi epi,
+                                                        float* __restrict__ part,
+                                                        const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ __align__(16) char smem[G::MAIN_BYTES];
-  __shared__ double red[4];
+  __shared__ double red[8];
   const int64_t nb = gridDim.x;
   const int64_t L = xcd_tile(blockIdx.x, nb);
-  const int64_t total = nTiles * U;
-  const int64_t b = sk_begin(L, total, nb), e = sk_begin(L + 1, total, nb);
+  const int64_t R = nTiles / nb, nFull = R * nb;
   G g;
+  for (int64_t r = 0; r < R; ++r) {
+    const int64_t tile = r * nb + L;
+    const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
+    g.run(ops, m0, n0, 0, U * G::BK, smem);
+    g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
+    epi.end_tile(tile, red);
+  }
+  const int64_t total = (nTiles - nFull) * U;
+  const int64_t b = sk_begin(L, total, nb), e = sk_begin(L + 1, total, nb);
   int64_t it = b;
   while (it < e) {
-    const int64_t tile = it / U;
-    const int64_t k0 = it - tile * U;
-    const int64_t k1 = (e - tile * U < U) ? e - tile * U : U;
+    const int64_t tt = it / U;  // tail tile
+    const int64_t k0 = it - tt * U;
+    const int64_t k1 = (e - tt * U < U) ? e - tt * U : U;
+    const int64_t tile = nFull + tt;
     const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
     g.run(ops, m0, n0, k0 * G::BK, k1 * G::BK, smem);
     if (k0 == 0 && k1 == U) {
-      g.for_each([&](int r, int c, float v) { epi.element(m0 + r, n0 + c, v); });
+      g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
       epi.end_tile(tile, red);
     } else {
       float* ps = part + (2 * L + (it == b ? 0 : 1)) * (int64_t)(G::BM * G::BN);
-      g.for_each([&](int r, int c, float v) { ps[r * G::BN + c] = v; });
+      g.for_each([&](int rr, int c, float v) { ps[rr * G::BN + c] = v; });
     }
-    it = tile * U + k1;
+    it = tt * U + k1;
   }
 }
 
-// Tiles whose K-steps were split between blocks: sum the partial products in
-// block order (deterministic) and run the same epilogue.
+// Tail tiles whose K-steps were split between blocks: sum the partial
+// products in block order (deterministic) and run the same epilogue.
 template <class G, class Epi>
 __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
                                                          int64_t nb, const float* __restrict__ part,
                                                          Epi epi, const int32_t* gate) {
   if (gate && *gate == 0) return;
-  __shared__ double red[4];
-  const int64_t tile = blockIdx.x;
-  const int64_t total = nTiles * U;
-  const int64_t lo = sk_owner(tile * U, total, nb), hi = sk_owner((tile + 1) * U - 1, total, nb);
+  __shared__ double red[8];
+  const int64_t nFull = (nTiles / nb) * nb;
+  const int64_t tile = nFull + blockIdx.x;
+  if (tile >= nTiles) return;
+  const int64_t tt = tile - nFull;
+  const int64_t total = (nTiles - nFull) * U;
+  const int64_t lo = sk_owner(tt * U, total, nb), hi = sk_owner((tt + 1) * U - 1, total, nb);
   if (lo == hi) return;  // finished inside one block
   const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
   constexpr int E = G::BM * G::BN;
@@ -468,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nT
     for (int64_t L = lo; L <= hi; ++L) {
       const int64_t bL = sk_begin(L, total, nb);
       if (bL == sk_begin(L + 1, total, nb)) continue;  // empty range
-      const int64_t slot = 2 * L + ((L == lo && bL < tile * U) ? 1 : 0);
+      const int64_t slot = 2 * L + ((L == lo && bL < tt * U) ? 1 : 0);
       s += part[slot * E + e];
     }
     epi.element(m0 + e / G::BN, n0 + e % G::BN, s);
@@ -476,37 +507,39 @@ __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nT
   epi.end_tile(tile, red);
 }
 
-// Blocks of kernel `fn` the whole GPU runs at once (CUs x occupancy).
-inline int64_t resident_blocks(const void* fn) {
+// Blocks of kernel `fn` (nt threads each) the whole GPU runs at once.
+inline int64_t resident_blocks(const void* fn, int nt = kThreads) {
   int dev = 0, cus = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, 0) != hipSuccess || occ <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, nt, 0) != hipSuccess || occ <= 0)
     occ = 1;
   return (int64_t)cus * occ;
 }
 
-// Stream-K launch of a rectangular product over an Mp x Np output with
-// K = Kp; part holds 2 * kMaxStreamKBlocks tiles.  nb_max caps the grid
-// (0: one block per resident slot).
+// Launch of a rectangular product over an Mp x Np output with K = Kp; part
+// holds 2 * kMaxStreamKBlocks tiles of split-tile scratch.
 template <class G, class Epi>
 hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64_t Kp, Epi epi,
-                       float* part, const int32_t* gate, hipStream_t s, int64_t nb_max = 0) {
+                       float* part, const int32_t* gate, hipStream_t s) {
   static int64_t resident = 0;
-  if (!resident) resident = resident_blocks(reinterpret_cast<const void*>(&k_rect_streamk<G, Epi>));
+  if (!resident)
+    resident = resident_blocks(reinterpret_cast<const void*>(&k_rect_streamk<G, Epi>), G::NT);
   const int64_t nMT = Mp / G::BM, nNT = Np / G::BN;
   const int64_t nTiles = nMT * nNT, U = Kp / G::BK;
-  int64_t nb = nb_max > 0 ? nb_max : resident;
+  int64_t nb = resident;
   if (nb > kMaxStreamKBlocks) nb = kMaxStreamKBlocks;
   if (nb > nTiles) nb = nTiles;
-  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(kThreads), 0, s>>>(ops, nMT, nTiles, U, epi,
-                                                                       part, gate);
+  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(G::NT), 0, s>>>(ops, nMT, nTiles, U, epi,
+                                                                     part, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_rect_fixup<G, Epi><<<dim3((unsigned)nTiles), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, part,
-                                                                         epi, gate);
+  const int64_t tail = nTiles - (nTiles / nb) * nb;
+  if (tail == 0) return hipSuccess;
+  k_rect_fixup<G, Epi><<<dim3((unsigned)tail), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, part,
+                                                                       epi, gate);
   return hipGetLastError();
 }
 
