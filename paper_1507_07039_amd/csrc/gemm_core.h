@@ -422,10 +422,12 @@ struct BlockGemmB3 {
 //     L + (R-1) nb whole.  Consecutive tiles (M fastest, sharing a strip of
 //     the Y operand) run on one XCD at the same time, so that strip is
 //     fetched from memory about once per round.
-//   tail: the remaining nTiles - R nb tiles are split stream-K style: block L
-//     owns items [L*total/nb, (L+1)*total/nb) of their total = tail * U
-//     K-steps; tiles finished inside one block get their epilogue at once,
-//     tiles shared by blocks are summed in block order by the fix-up kernel
+//   tail: the remaining nTiles - R nb tiles are split stream-K style over the
+//     first nbt <= nb blocks (at most kTailSplit blocks per tile, so the
+//     fix-up sums few partials): block L < nbt owns items
+//     [L*total/nbt, (L+1)*total/nbt) of their total = tail * U K-steps;
+//     tiles finished inside one block get their epilogue at once, tiles
+//     shared by blocks are summed in block order by the fix-up kernel
 //     (deterministic; no block ever waits for another).
 // Logical block numbers are assigned XCD by XCD (the hardware hands block b to
 // XCD b % 8), so one XCD works on contiguous tiles.
@@ -437,10 +439,12 @@ __device__ __forceinline__ int64_t sk_owner(int64_t i, int64_t total, int64_t G)
   return ((i + 1) * G - 1) / total;
 }
 
+constexpr int64_t kTailSplit = 4;
+
 template <class G, class Epi>
 __global__ __launch_bounds__(G::NT) void k_rect_streamk(typename G::Ops ops, int64_t nMT,
-                                                        int64_t nTiles, int64_t U, Epi epi,
-                                                        float* __restrict__ part,
+                                                        int64_t nTiles, int64_t U, int64_t nbt,
+                                                        Epi epi, float* __restrict__ part,
                                                         const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ __align__(16) char smem[G::MAIN_BYTES];
@@ -456,8 +460,9 @@ __global__ __launch_bounds__(G::NT) void k_rect_streamk(typename G::Ops ops, int
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
     epi.end_tile(tile, red);
   }
+  if (L >= nbt) return;
   const int64_t total = (nTiles - nFull) * U;
-  const int64_t b = sk_begin(L, total, nb), e = sk_begin(L + 1, total, nb);
+  const int64_t b = sk_begin(L, total, nbt), e = sk_begin(L + 1, total, nbt);
   int64_t it = b;
   while (it < e) {
     const int64_t tt = it / U;  // tail tile
@@ -481,8 +486,9 @@ __global__ __launch_bounds__(G::NT) void k_rect_streamk(typename G::Ops ops, int
 // products in block order (deterministic) and run the same epilogue.
 template <class G, class Epi>
 __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
-                                                         int64_t nb, const float* __restrict__ part,
-                                                         Epi epi, const int32_t* gate) {
+                                                         int64_t nb, int64_t nbt,
+                                                         const float* __restrict__ part, Epi epi,
+                                                         const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ double red[8];
   const int64_t nFull = (nTiles / nb) * nb;
@@ -490,15 +496,15 @@ __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nT
   if (tile >= nTiles) return;
   const int64_t tt = tile - nFull;
   const int64_t total = (nTiles - nFull) * U;
-  const int64_t lo = sk_owner(tt * U, total, nb), hi = sk_owner((tt + 1) * U - 1, total, nb);
+  const int64_t lo = sk_owner(tt * U, total, nbt), hi = sk_owner((tt + 1) * U - 1, total, nbt);
   if (lo == hi) return;  // finished inside one block
   const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
   constexpr int E = G::BM * G::BN;
   for (int e = threadIdx.x; e < E; e += kThreads) {
     float s = 0.0f;
     for (int64_t L = lo; L <= hi; ++L) {
-      const int64_t bL = sk_begin(L, total, nb);
-      if (bL == sk_begin(L + 1, total, nb)) continue;  // empty range
+      const int64_t bL = sk_begin(L, total, nbt);
+      if (bL == sk_begin(L + 1, total, nbt)) continue;  // empty range
       const int64_t slot = 2 * L + ((L == lo && bL < tt * U) ? 1 : 0);
       s += part[slot * E + e];
     }
@@ -532,14 +538,15 @@ hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64
   int64_t nb = resident;
   if (nb > kMaxStreamKBlocks) nb = kMaxStreamKBlocks;
   if (nb > nTiles) nb = nTiles;
-  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(G::NT), 0, s>>>(ops, nMT, nTiles, U, epi,
+  const int64_t tail = nTiles - (nTiles / nb) * nb;
+  const int64_t nbt = tail * kTailSplit < nb ? tail * kTailSplit : nb;
+  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(G::NT), 0, s>>>(ops, nMT, nTiles, U, nbt, epi,
                                                                      part, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t tail = nTiles - (nTiles / nb) * nb;
   if (tail == 0) return hipSuccess;
-  k_rect_fixup<G, Epi><<<dim3((unsigned)tail), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, part,
-                                                                       epi, gate);
+  k_rect_fixup<G, Epi><<<dim3((unsigned)tail), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, nbt,
+                                                                       part, epi, gate);
   return hipGetLastError();
 }
 

@@ -104,43 +104,39 @@ static_assert(CoopF32::BK == CoopB3::BK, "one K split");
 constexpr int kCB = 128;
 constexpr int kSymLD = kCB + 1;
 
-template <class G, bool SIGT>
-__global__ __launch_bounds__(kThreads) void k_coreg_update(
-    typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
-    const double* __restrict__ ncol, double alpha, double2* __restrict__ cstat,
-    double* __restrict__ csq, int64_t ldstat, bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl,
-    const int32_t* gate) {
-  if (gate && *gate == 0) return;
-  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
-  constexpr int TILE_BYTES = kCB * kSymLD * 4 * (SIGT ? 2 : 1);
-  constexpr int SMEM = G::MAIN_BYTES > TILE_BYTES ? G::MAIN_BYTES : TILE_BYTES;
-  __shared__ __align__(16) char smem[SMEM];
-  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
-  int64_t I, J;
-  tri_tile(u, I, J);
+// Fresh similarity of one C-tile entry from its product (FP32 math, see
+// above); 0 outside the strictly-upper real part.
+__device__ __forceinline__ float coreg_sim(float acc, int64_t gr, int64_t gc, int64_t Na,
+                                           const double* __restrict__ ncol) {
+  if (!(gr < gc && gc < Na)) return 0.0f;
+  const float den = (float)(ncol[gr] + ncol[gc] - fabs((double)acc));
+  return den > 0.0f ? acc * __frsqrt_rn(den) : 0.0f;
+}
+
+// Everything of the C update after the similarities of tile (I, J) are
+// known: fe(f) calls f(rr, c, tsim) once for every entry the thread owns.
+template <bool SIGT, class FE>
+__device__ __forceinline__ void coreg_tile_update(FE&& fe, char* smem, int64_t I, int64_t J,
+                                                  float* __restrict__ C, int64_t ldc, int64_t Na,
+                                                  double alpha, double2* __restrict__ cstat,
+                                                  double* __restrict__ csq, int64_t ldstat,
+                                                  bf16_t* __restrict__ Ch,
+                                                  bf16_t* __restrict__ Cl) {
   const int64_t m0 = I * kCB, n0 = J * kCB;
-  G g;
-  g.run(ops, m0, n0, 0, Kp, smem);
   float* ts = reinterpret_cast<float*>(smem);  // updated values
   float* tt = ts + kCB * kSymLD;               // fresh T (SIGT only)
-  // The denominator here is built from column norms of W alone (no growing
-  // diagonal), so it is formed in FP64 and the rest runs in FP32:
-  // T = acc * rsqrt(den), C <- (1 - alpha) C + alpha T (about 2 ulp).
   const float keep = (float)(1.0 - alpha), alf = (float)alpha;
-  g.for_each([&](int rr, int c, float acc) {
+  fe([&](int rr, int c, float tsim) {
     const int64_t gr = m0 + rr, gc = n0 + c;
-    float v = 0.0f, tv = 0.0f;
+    float v = 0.0f;
     if (gr < gc && gc < Na) {
-      const float den = (float)(ncol[gr] + ncol[gc] - fabs((double)acc));
-      const float tsim = den > 0.0f ? acc * __frsqrt_rn(den) : 0.0f;
       const int64_t o = gr * ldc + gc;
       v = keep * C[o] + alf * tsim;
       C[o] = v;
       if (Ch) split_bf16(v, Ch[o], Cl[o]);
-      tv = tsim;
     }
     ts[rr * kSymLD + c] = v;
-    if constexpr (SIGT) tt[rr * kSymLD + c] = tv;
+    if constexpr (SIGT) tt[rr * kSymLD + c] = tsim;
   });
   __syncthreads();
   const int t = threadIdx.x;
@@ -198,6 +194,75 @@ __global__ __launch_bounds__(kThreads) void k_coreg_update(
       if constexpr (SIGT) csq[I * ldstat + n0 + q] = c2;
     }
   }
+}
+
+// Fused form: the product of the tile, then the update in its epilogue.
+template <class G, bool SIGT>
+__global__ __launch_bounds__(kThreads) void k_coreg_update(
+    typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
+    const double* __restrict__ ncol, double alpha, double2* __restrict__ cstat,
+    double* __restrict__ csq, int64_t ldstat, bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl,
+    const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
+  constexpr int TILE_BYTES = kCB * kSymLD * 4 * (SIGT ? 2 : 1);
+  constexpr int SMEM = G::MAIN_BYTES > TILE_BYTES ? G::MAIN_BYTES : TILE_BYTES;
+  __shared__ __align__(16) char smem[SMEM];
+  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
+  int64_t I, J;
+  tri_tile(u, I, J);
+  const int64_t m0 = I * kCB, n0 = J * kCB;
+  G g;
+  g.run(ops, m0, n0, 0, Kp, smem);
+  coreg_tile_update<SIGT>(
+      [&](auto&& f) {
+        g.for_each([&](int rr, int c, float acc) {
+          f(rr, c, coreg_sim(acc, m0 + rr, n0 + c, Na, ncol));
+        });
+      },
+      smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat, Ch, Cl);
+}
+
+// Split form, first half: the similarities of every upper tile into a
+// tile-packed buffer (tile u at T + u * kCB * kCB, row-major in the tile).
+template <class G>
+__global__ __launch_bounds__(kThreads) void k_coreg_sim(typename G::Ops ops, int64_t Kp,
+                                                        int64_t Na, const double* __restrict__ ncol,
+                                                        float* __restrict__ T,
+                                                        const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
+  __shared__ __align__(16) char smem[G::MAIN_BYTES];
+  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
+  int64_t I, J;
+  tri_tile(u, I, J);
+  const int64_t m0 = I * kCB, n0 = J * kCB;
+  G g;
+  g.run(ops, m0, n0, 0, Kp, smem);
+  float* tu = T + u * (int64_t)(kCB * kCB);
+  g.for_each([&](int rr, int c, float acc) {
+    tu[rr * kCB + c] = coreg_sim(acc, m0 + rr, n0 + c, Na, ncol);
+  });
+}
+
+// Split form, second half: the memory-bound update of every upper tile from
+// the stored similarities (same rule and outputs as the fused form).
+template <bool SIGT>
+__global__ __launch_bounds__(kThreads) void k_coreg_apply(
+    const float* __restrict__ T, float* __restrict__ C, int64_t ldc, int64_t Na, double alpha,
+    double2* __restrict__ cstat, double* __restrict__ csq, int64_t ldstat,
+    bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  __shared__ __align__(16) char smem[kCB * kSymLD * 4 * (SIGT ? 2 : 1)];
+  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
+  int64_t I, J;
+  tri_tile(u, I, J);
+  const float* tu = T + u * (int64_t)(kCB * kCB);
+  coreg_tile_update<SIGT>(
+      [&](auto&& f) {
+        for (int e = threadIdx.x; e < kCB * kCB; e += kThreads) f(e / kCB, e % kCB, tu[e]);
+      },
+      smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat, Ch, Cl);
 }
 
 // ------------------------------------------------------------------------
@@ -304,10 +369,28 @@ hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* 
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
                                   float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
                                   int64_t Na, const double* nWcol, Rule rule, double2* cstat,
-                                  double* csq, const int32_t* gate, hipStream_t s) {
-  // X = Yt = W^T stored gene-major: row m of W^T is column m of W.
-  return coreg_launch<SymB3>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol,
-                             rule, cstat, csq, Ch, Cl, gate, s);
+                                  double* csq, float* Tbuf, const int32_t* gate, hipStream_t s) {
+  // X = Yt = W^T stored gene-major: row m of W^T is column m of W.  The split
+  // form runs the bf16 product at full rate and the update at memory rate
+  // instead of alternating the two inside every block.
+  const int64_t nT = Nap / kCB;
+  const unsigned nb = (unsigned)(nT * (nT + 1) / 2);
+  k_coreg_sim<SymB3><<<dim3(nb), dim3(kThreads), 0, s>>>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt},
+                                                         Nep, Na, nWcol, Tbuf, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (rule.sigma_from_T)
+    k_coreg_apply<true><<<dim3(nb), dim3(kThreads), 0, s>>>(Tbuf, C, ldc, Na, rule.alpha, cstat,
+                                                            csq, Nap, Ch, Cl, gate);
+  else
+    k_coreg_apply<false><<<dim3(nb), dim3(kThreads), 0, s>>>(Tbuf, C, ldc, Na, rule.alpha, cstat,
+                                                             csq, Nap, Ch, Cl, gate);
+  return hipGetLastError();
+}
+
+size_t coreg_tbuf_floats(int64_t Nap) {
+  const int64_t nT = Nap / kCB;
+  return (size_t)(nT * (nT + 1) / 2) * kCB * kCB;
 }
 
 int coop_splits(int64_t Nep, int64_t Nap) {

@@ -125,7 +125,11 @@ def test_full_size_first_iteration_sampled(torch, pd, oracle):
 
 def test_full_size_run_against_plain(torch, pd):
     """Whole run at T=700, G=18000: the precision form against the FP32 form
-    on the same (library-normalised) inputs."""
+    on the same (library-normalised) inputs, compared at matched iteration
+    numbers.  W grows to ~2e3 on this workload, so the bound is relative to
+    max|W|: 1e-3 (about 2^-10, the growth of the 2^-16 per-product error
+    through the iteration's sensitivity).  The stopping iteration itself is
+    sensitive (h crosses tol slowly), so it is reported and bounded loosely."""
     W0, P0, C0 = I.workload_priors(I.HUMAN)
     dev = [torch.from_numpy(np.ascontiguousarray(M, dtype=np.float32)).cuda() for M in (W0, P0, C0)]
     del W0, P0, C0
@@ -134,9 +138,22 @@ def test_full_size_run_against_plain(torch, pd):
     plain = pd.run(*dev)
     fast = pd.run(*dev, opts=b3(pd))
     assert plain.status == pd.OK and fast.status == pd.OK
-    dW = (fast.W - plain.W).abs().max().item()
-    scale = plain.W.abs().max().item()
-    print(f"T=700 G=18000: iters plain {plain.iters} bf16x3 {fast.iters}; max|dW| = {dW:.3e} "
-          f"(max|W| = {scale:.3e})")
-    assert abs(fast.iters - plain.iters) <= 2
-    assert torch.equal(fast.P, fast.P.T) and torch.equal(fast.C, fast.C.T)
+    print(f"T=700 G=18000: iterations to converge: plain {plain.iters}, bf16x3 {fast.iters}")
+    assert abs(fast.iters - plain.iters) <= 5
+    Ne, Na = dev[0].shape
+    cp = pd.Context(Ne, Na)
+    cf = pd.Context(Ne, Na, b3(pd))
+    cp.load(*dev)
+    cf.load(*dev)
+    n = min(plain.iters, fast.iters)
+    for t in range(1, n + 1):
+        cp.iterate()
+        cf.iterate()
+        if t in (1, 5, 10, 20, 40) or t == n:
+            Wp, Pp, Cp, _, _ = cp.state()
+            Wf, Pf, Cf, _, _ = cf.state()
+            dW = (Wf - Wp).abs().max().item()
+            sW = Wp.abs().max().item()
+            print(f"  t={t}: max|dW| = {dW:.3e}  max|W| = {sW:.3e}  rel {dW / max(1.0, sW):.2e}")
+            assert dW <= 1e-3 * max(1.0, sW), (t, dW, sW)
+            assert torch.equal(Pf, Pf.T) and torch.equal(Cf, Cf.T)
