@@ -103,7 +103,6 @@ struct panda_ctx {
   DevState* st;
   bool b3;  // split-BF16 products
   bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl, *Ch, *Cl;
-  float* Tbuf;
   DevState* host;  // pinned
   int splits;
   int64_t nh;
@@ -149,9 +148,7 @@ size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* bas
   // split-BF16 operand planes
   const bool b3 = precision == PANDA_PREC_BF16X3;
   bf16_t* sh[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  float* tb = nullptr;
   if (b3) {
-    tb = cv.take<float>(coreg_tbuf_floats(Nap));  // similarities of the upper C tiles
     sh[0] = cv.take<bf16_t>(nw);                   // W hi, row-major
     sh[1] = cv.take<bf16_t>(nw);                   // W lo
     sh[2] = cv.take<bf16_t>(nw);                   // W^T hi, gene-major
@@ -193,7 +190,6 @@ size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* bas
     c->Pl = sh[5];
     c->Ch = sh[6];
     c->Cl = sh[7];
-    c->Tbuf = tb;
   }
   return cv.off;
 }
@@ -298,8 +294,7 @@ panda_status enqueue_iteration(panda_ctx* c) {
   // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
   if (c->b3)
     HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Ch, c->Cl, c->Nap,
-                                   c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, c->Tbuf,
-                                   run_pc, s));
+                                   c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, run_pc, s));
   else
     HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc,
                                 c->rule, c->cstat, c->csq, run_pc, s));

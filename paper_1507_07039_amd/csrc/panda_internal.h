@@ -89,8 +89,7 @@ hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const bf1
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
                                   float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
                                   int64_t Na, const double* nWcol, Rule rule, double2* cstat,
-                                  double* csq, float* Tbuf, const int32_t* gate, hipStream_t s);
-size_t coreg_tbuf_floats(int64_t Nap);  // similarity scratch of the split C update
+                                  double* csq, const int32_t* gate, hipStream_t s);
 hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ldw, int64_t Nep,
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s);

@@ -114,30 +114,46 @@ __device__ __forceinline__ float coreg_sim(float acc, int64_t gr, int64_t gc, in
 }
 
 // Everything of the C update after the similarities of tile (I, J) are
-// known: fe(f) calls f(rr, c, tsim) once for every entry the thread owns.
-template <bool SIGT, class FE>
-__device__ __forceinline__ void coreg_tile_update(FE&& fe, char* smem, int64_t I, int64_t J,
+// known.  Each thread owns kPer entries; fi(f) calls f(q, rr, c) and fv(f)
+// calls f(q, rr, c, tsim) for its q-th entry.  The old values of all owned
+// entries are loaded before any is written (the loads cannot be reordered
+// past stores to the same array, so this keeps them in flight together).
+constexpr int kPer = kCB * kCB / kThreads;
+
+template <bool SIGT, int CHUNK, class FI, class FV>
+__device__ __forceinline__ void coreg_tile_update(FI&& fi, FV&& fv, char* smem, int64_t I, int64_t J,
                                                   float* __restrict__ C, int64_t ldc, int64_t Na,
                                                   double alpha, double2* __restrict__ cstat,
                                                   double* __restrict__ csq, int64_t ldstat,
                                                   bf16_t* __restrict__ Ch,
                                                   bf16_t* __restrict__ Cl) {
+  static_assert(kPer % CHUNK == 0, "whole chunks");
   const int64_t m0 = I * kCB, n0 = J * kCB;
   float* ts = reinterpret_cast<float*>(smem);  // updated values
   float* tt = ts + kCB * kSymLD;               // fresh T (SIGT only)
   const float keep = (float)(1.0 - alpha), alf = (float)alpha;
-  fe([&](int rr, int c, float tsim) {
-    const int64_t gr = m0 + rr, gc = n0 + c;
-    float v = 0.0f;
-    if (gr < gc && gc < Na) {
-      const int64_t o = gr * ldc + gc;
-      v = keep * C[o] + alf * tsim;
-      C[o] = v;
-      if (Ch) split_bf16(v, Ch[o], Cl[o]);
-    }
-    ts[rr * kSymLD + c] = v;
-    if constexpr (SIGT) tt[rr * kSymLD + c] = tsim;
-  });
+#pragma unroll
+  for (int ch = 0; ch < kPer / CHUNK; ++ch) {  // CHUNK old values in flight at a time
+    float cold[CHUNK];
+    fi([&](int q, int rr, int c) {
+      if (q / CHUNK != ch) return;
+      const int64_t gr = m0 + rr, gc = n0 + c;
+      cold[q % CHUNK] = (gr < gc && gc < Na) ? C[gr * ldc + gc] : 0.0f;
+    });
+    fv([&](int q, int rr, int c, float tsim) {
+      if (q / CHUNK != ch) return;
+      const int64_t gr = m0 + rr, gc = n0 + c;
+      float v = 0.0f;
+      if (gr < gc && gc < Na) {
+        const int64_t o = gr * ldc + gc;
+        v = keep * cold[q % CHUNK] + alf * tsim;
+        C[o] = v;
+        if (Ch) split_bf16(v, Ch[o], Cl[o]);
+      }
+      ts[rr * kSymLD + c] = v;
+      if constexpr (SIGT) tt[rr * kSymLD + c] = tsim;
+    });
+  }
   __syncthreads();
   const int t = threadIdx.x;
   // mirror write: C[n0 + q][m0 + p] = ts[p][q] for global m0+p < n0+q
@@ -196,7 +212,7 @@ __device__ __forceinline__ void coreg_tile_update(FE&& fe, char* smem, int64_t I
   }
 }
 
-// Fused form: the product of the tile, then the update in its epilogue.
+// The product of the tile, then the update in its epilogue.
 template <class G, bool SIGT>
 __global__ __launch_bounds__(kThreads) void k_coreg_update(
     typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
@@ -214,53 +230,26 @@ __global__ __launch_bounds__(kThreads) void k_coreg_update(
   const int64_t m0 = I * kCB, n0 = J * kCB;
   G g;
   g.run(ops, m0, n0, 0, Kp, smem);
-  coreg_tile_update<SIGT>(
+  static_assert(G::TM * G::TN * 16 == kPer, "one accumulator per owned entry");
+  coreg_tile_update<SIGT, 16>(
       [&](auto&& f) {
-        g.for_each([&](int rr, int c, float acc) {
-          f(rr, c, coreg_sim(acc, m0 + rr, n0 + c, Na, ncol));
-        });
+#pragma unroll
+        for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < G::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) f((i * G::TN + j) * 16 + r, g.row_of(i, r), g.col_of(j));
       },
-      smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat, Ch, Cl);
-}
-
-// Split form, first half: the similarities of every upper tile into a
-// tile-packed buffer (tile u at T + u * kCB * kCB, row-major in the tile).
-template <class G>
-__global__ __launch_bounds__(kThreads) void k_coreg_sim(typename G::Ops ops, int64_t Kp,
-                                                        int64_t Na, const double* __restrict__ ncol,
-                                                        float* __restrict__ T,
-                                                        const int32_t* gate) {
-  if (gate && *gate == 0) return;
-  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
-  __shared__ __align__(16) char smem[G::MAIN_BYTES];
-  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
-  int64_t I, J;
-  tri_tile(u, I, J);
-  const int64_t m0 = I * kCB, n0 = J * kCB;
-  G g;
-  g.run(ops, m0, n0, 0, Kp, smem);
-  float* tu = T + u * (int64_t)(kCB * kCB);
-  g.for_each([&](int rr, int c, float acc) {
-    tu[rr * kCB + c] = coreg_sim(acc, m0 + rr, n0 + c, Na, ncol);
-  });
-}
-
-// Split form, second half: the memory-bound update of every upper tile from
-// the stored similarities (same rule and outputs as the fused form).
-template <bool SIGT>
-__global__ __launch_bounds__(kThreads) void k_coreg_apply(
-    const float* __restrict__ T, float* __restrict__ C, int64_t ldc, int64_t Na, double alpha,
-    double2* __restrict__ cstat, double* __restrict__ csq, int64_t ldstat,
-    bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl, const int32_t* gate) {
-  if (gate && *gate == 0) return;
-  __shared__ __align__(16) char smem[kCB * kSymLD * 4 * (SIGT ? 2 : 1)];
-  const int64_t u = xcd_tile(blockIdx.x, gridDim.x);
-  int64_t I, J;
-  tri_tile(u, I, J);
-  const float* tu = T + u * (int64_t)(kCB * kCB);
-  coreg_tile_update<SIGT>(
       [&](auto&& f) {
-        for (int e = threadIdx.x; e < kCB * kCB; e += kThreads) f(e / kCB, e % kCB, tu[e]);
+#pragma unroll
+        for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < G::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int rr = g.row_of(i, r), c = g.col_of(j);
+              f((i * G::TN + j) * 16 + r, rr, c, coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, ncol));
+            }
       },
       smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat, Ch, Cl);
 }
@@ -369,28 +358,10 @@ hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* 
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
                                   float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
                                   int64_t Na, const double* nWcol, Rule rule, double2* cstat,
-                                  double* csq, float* Tbuf, const int32_t* gate, hipStream_t s) {
-  // X = Yt = W^T stored gene-major: row m of W^T is column m of W.  The split
-  // form runs the bf16 product at full rate and the update at memory rate
-  // instead of alternating the two inside every block.
-  const int64_t nT = Nap / kCB;
-  const unsigned nb = (unsigned)(nT * (nT + 1) / 2);
-  k_coreg_sim<SymB3><<<dim3(nb), dim3(kThreads), 0, s>>>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt},
-                                                         Nep, Na, nWcol, Tbuf, gate);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (rule.sigma_from_T)
-    k_coreg_apply<true><<<dim3(nb), dim3(kThreads), 0, s>>>(Tbuf, C, ldc, Na, rule.alpha, cstat,
-                                                            csq, Nap, Ch, Cl, gate);
-  else
-    k_coreg_apply<false><<<dim3(nb), dim3(kThreads), 0, s>>>(Tbuf, C, ldc, Na, rule.alpha, cstat,
-                                                             csq, Nap, Ch, Cl, gate);
-  return hipGetLastError();
-}
-
-size_t coreg_tbuf_floats(int64_t Nap) {
-  const int64_t nT = Nap / kCB;
-  return (size_t)(nT * (nT + 1) / 2) * kCB * kCB;
+                                  double* csq, const int32_t* gate, hipStream_t s) {
+  // X = Yt = W^T stored gene-major: row m of W^T is column m of W.
+  return coreg_launch<SymB3>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol,
+                             rule, cstat, csq, Ch, Cl, gate, s);
 }
 
 int coop_splits(int64_t Nep, int64_t Nap) {
