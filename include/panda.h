@@ -163,6 +163,74 @@ enum {
 panda_status panda_ctx_set_timing(panda_ctx* ctx, int32_t enable);
 panda_status panda_ctx_phase_times(panda_ctx* ctx, double* total_ms, int64_t* count);
 
+/* ---- Batched form ---------------------------------------------------------
+ * n independent networks of arbitrary sizes iterate together (the paper runs
+ * PANDA on sets of networks, Sec. I; each network follows Eq. 2-7 exactly as
+ * a context does).  Every phase of an iteration is one grouped launch over
+ * all networks (persistent kernels over per-XCD work queues for the four
+ * similarity products); a network stops being updated once its own h < tol
+ * (its convergence mask), while the others go on.  One iteration can be
+ * captured in a HIP graph and replayed.  FP32 arithmetic only (precision must
+ * be PANDA_PREC_FP32).  All matrices are device pointers, row-major FP32.
+ *
+ * Workspace: panda_batch_workspace_bytes(n, Ne, Na, opt) bytes, 256-byte
+ * aligned, owned by the caller; it holds each network's state (about what a
+ * context of the same size needs) plus the work lists.  n >= 1, every
+ * Ne[i], Na[i] >= 1. */
+typedef struct panda_batch panda_batch;
+
+size_t panda_batch_workspace_bytes(int32_t n, const int64_t* Ne, const int64_t* Na,
+                                   const panda_options* opt);
+panda_status panda_batch_create(int32_t n, const int64_t* Ne, const int64_t* Na,
+                                const panda_options* opt, void* workspace, size_t ws_bytes,
+                                hipStream_t stream, panda_batch** out);
+void panda_batch_destroy(panda_batch* b);
+
+/* Tile choices of the grouped products, one per entry of the enum below;
+ * panda_batch_tile_candidates(phase) gives how many exist (choice in
+ * [0, count)).  set_tiles validates every entry and rebuilds the work lists
+ * (synchronises the stream).  autotune times every candidate of every phase
+ * on the batch's own shapes (reps timed launches each, best time wins) and
+ * keeps the fastest; it overwrites the whole state, so it must precede
+ * panda_batch_load (loaded networks are marked unloaded).  Timing does not
+ * depend on the values, so the state is zero while it runs. */
+enum {
+  PANDA_BATCH_TILE_R = 0,     /* R = T(P, W) tile                    */
+  PANDA_BATCH_TILE_AW = 1,    /* A = T(W, C) + W update tile         */
+  PANDA_BATCH_TILE_PPART = 2, /* K chunk of the W W^T partials       */
+  PANDA_BATCH_TILE_C = 3,     /* C update tile shape                 */
+  PANDA_BATCH_NTILE = 4
+};
+int32_t panda_batch_tile_candidates(int32_t phase);
+panda_status panda_batch_get_tiles(const panda_batch* b, int32_t* choice);
+panda_status panda_batch_set_tiles(panda_batch* b, const int32_t* choice);
+panda_status panda_batch_autotune(panda_batch* b, int32_t reps, float* best_ms);
+
+/* Load network i (0 <= i < n) as panda_ctx_load does, including the identity
+ * default for a NULL P or C. */
+panda_status panda_batch_load(panda_batch* b, int32_t i, const float* W, const float* P,
+                              const float* C, int32_t t);
+
+/* steps iterations of every network whose h is still >= tol (use_graph: by
+ * replaying the captured iteration; the graph is captured on first use and
+ * again after the tiles change).  Then reads the states back (synchronises
+ * the stream) and returns in *active how many networks are still iterating.
+ * Every network must be loaded. */
+panda_status panda_batch_iterate(panda_batch* b, int32_t steps, int32_t use_graph,
+                                 int32_t* active);
+/* Iterate until every network has converged or opt.max_iter iterations have
+ * run, reading the states back every opt.poll_every iterations.  Returns
+ * PANDA_OK when all converged, else PANDA_NOT_CONVERGED; *steps = iterations
+ * run by the batch. */
+panda_status panda_batch_run(panda_batch* b, int32_t use_graph, int32_t* steps);
+/* State of network i as of the last read-back: h, t and whether it is still
+ * iterating (any pointer may be NULL). */
+panda_status panda_batch_state(const panda_batch* b, int32_t i, double* h, int32_t* t,
+                               int32_t* active);
+/* Copy network i out, as panda_ctx_store does. */
+panda_status panda_batch_store(panda_batch* b, int32_t i, float* W, float* P, float* C,
+                               double* h, int32_t* t);
+
 const char* panda_status_string(panda_status s);
 const char* panda_last_error(void);
 

@@ -1,0 +1,254 @@
+// Epilogues of the similarity products and the C-tile update rule, shared
+// by the single-network kernels and the grouped (batched) kernels, so both
+// forms run the same arithmetic on every tile.
+#pragma once
+
+#include "gemm_core.h"
+
+namespace panda {
+namespace gemm {
+
+// ------------------------------------------------------------ epilogues --
+// T(X, Y) stored for i < M, j < N (Sec. II-C Tfunction; R of Eq. 3).  With
+// pd set, the peeled diagonal term pd[i][i] * pw[i][j] is added to the
+// product first (R = T(P, W) with P's diagonal outside the bf16 operand).
+struct EpiStoreT {
+  float* out;
+  int64_t ldo, M, N;
+  const double* nx;
+  const double* ny;
+  const float* pd;
+  int64_t ldpd;
+  const float* pw;
+  int64_t ldpw;
+  __device__ __forceinline__ void element(int64_t r, int64_t c, float acc) {
+    if (r < M && c < N) {
+      double dot = (double)acc;
+      if (pd) dot += (double)pd[r * ldpd + r] * (double)pw[r * ldpw + c];
+      out[r * ldo + c] = (float)tanimoto(dot, nx[r], ny[c]);
+    }
+  }
+  __device__ __forceinline__ void end_tile(int64_t, double*) {}
+};
+
+// A = T(W, C) (Eq. 4) folded into the W update of Eq. 2, with the tile's
+// share of the h sum of Eq. 7.  The new W goes to a second buffer because
+// the old one is still an operand of other blocks.  With cd set, the peeled
+// diagonal term W_ij * C_jj is added to the product first.
+struct EpiWUpdate {
+  const float* Wold;
+  const float* R;
+  float* Wnew;
+  int64_t ld, Ne, Na;
+  const double* nx;  // |W_i.|^2
+  const double* ny;  // |C_.j|^2
+  const float* cd;   // C (diagonal read at [j][j]) or null
+  int64_t ldcd;
+  double alpha;
+  int32_t h_undamped;
+  double* hpart;
+  double hsum;
+  __device__ __forceinline__ void element(int64_t r, int64_t c, float acc) {
+    if (r < Ne && c < Na) {
+      const int64_t o = r * ld + c;
+      const double w = Wold[o];
+      double dot = (double)acc;
+      if (cd) dot += w * (double)cd[c * ldcd + c];
+      const double a = tanimoto(dot, nx[r], ny[c]);
+      const double pred = 0.5 * (a + (double)R[o]);
+      const float wn = (float)((1.0 - alpha) * w + alpha * pred);
+      Wnew[o] = wn;
+      hsum += h_undamped ? fabs(pred - w) : fabs((double)wn - w);
+    }
+  }
+  __device__ __forceinline__ void end_tile(int64_t tile, double* red) {
+    const double s = block_sum(hsum, red);
+    if (threadIdx.x == 0) hpart[tile] = s;
+    hsum = 0.0;
+  }
+};
+
+// Tile configurations.  Rectangular products: 64 x 128 tiles (N_e = 700 pads
+// to 704 = 11 x 64), 4 waves side by side.  Symmetric C product: 128 x 128.
+using RectF32 = BlockGemm<64, 128, 1, 4, true, false, 16>;
+using RectB3 = BlockGemmB3<64, 128, 1, 4>;
+using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
+using SymB3 = BlockGemmB3<128, 128, 2, 2>;
+using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;
+using CoopB3 = BlockGemmB3<64, 64, 2, 2>;
+static_assert(RectF32::BM == RectB3::BM && RectF32::BN == RectB3::BN, "one tile grid");
+static_assert(CoopF32::BK == CoopB3::BK, "one K split");
+
+// ------------------------------------------------------------------------
+// C update of Eq. 5 on the upper tiles of T(W^T, W).  Within a tile only the
+// strictly-upper entries (global row < col) are updated, each written at
+// (i, j) and mirrored at (j, i), so C stays exactly symmetric and no entry
+// is read after another thread wrote it.  The updated tile is staged in LDS
+// for the coalesced mirror write and for the per-row sums (sum, sum of
+// squares) that give the sigma of Eq. 6: slot J of row i gets the sum over
+// the row part, slot I of row j the sum over the column part.  With SIGT the
+// sums are taken over the fresh similarities instead, and the sums of
+// squares of the updated entries (for |C_.j|^2) go to csq.  With shadows
+// (split-BF16 form) the hi/lo planes of the new entries are written too; the
+// diagonal of the planes stays zero.
+constexpr int kCB = 128;
+constexpr int kSymLD = kCB + 1;
+
+// Fresh similarity of one C-tile entry from its product (FP32 math, see
+// above); 0 outside the strictly-upper real part.
+__device__ __forceinline__ float coreg_sim(float acc, int64_t gr, int64_t gc, int64_t Na,
+                                           const double* __restrict__ ncol) {
+  if (!(gr < gc && gc < Na)) return 0.0f;
+  const float den = (float)(ncol[gr] + ncol[gc] - fabs((double)acc));
+  return den > 0.0f ? acc * __frsqrt_rn(den) : 0.0f;
+}
+
+// Everything of the C update after the similarities of tile (I, J) are
+// known.  Each thread owns kPer entries; fi(f) calls f(q, rr, c) and fv(f)
+// calls f(q, rr, c, tsim) for its q-th entry.  The old values of all owned
+// entries are loaded before any is written (the loads cannot be reordered
+// past stores to the same array, so this keeps them in flight together).
+constexpr int kPer = kCB * kCB / kThreads;
+
+template <bool SIGT, int CHUNK, class FI, class FV>
+__device__ __forceinline__ void coreg_tile_update(FI&& fi, FV&& fv, char* smem, int64_t I, int64_t J,
+                                                  float* __restrict__ C, int64_t ldc, int64_t Na,
+                                                  double alpha, double2* __restrict__ cstat,
+                                                  double* __restrict__ csq, int64_t ldstat,
+                                                  bf16_t* __restrict__ Ch,
+                                                  bf16_t* __restrict__ Cl) {
+  static_assert(kPer % CHUNK == 0, "whole chunks");
+  const int64_t m0 = I * kCB, n0 = J * kCB;
+  float* ts = reinterpret_cast<float*>(smem);  // updated values
+  float* tt = ts + kCB * kSymLD;               // fresh T (SIGT only)
+  const float keep = (float)(1.0 - alpha), alf = (float)alpha;
+#pragma unroll
+  for (int ch = 0; ch < kPer / CHUNK; ++ch) {  // CHUNK old values in flight at a time
+    float cold[CHUNK];
+    fi([&](int q, int rr, int c) {
+      if (q / CHUNK != ch) return;
+      const int64_t gr = m0 + rr, gc = n0 + c;
+      cold[q % CHUNK] = (gr < gc && gc < Na) ? C[gr * ldc + gc] : 0.0f;
+    });
+    fv([&](int q, int rr, int c, float tsim) {
+      if (q / CHUNK != ch) return;
+      const int64_t gr = m0 + rr, gc = n0 + c;
+      float v = 0.0f;
+      if (gr < gc && gc < Na) {
+        const int64_t o = gr * ldc + gc;
+        v = keep * cold[q % CHUNK] + alf * tsim;
+        C[o] = v;
+        if (Ch) split_bf16(v, Ch[o], Cl[o]);
+      }
+      ts[rr * kSymLD + c] = v;
+      if constexpr (SIGT) tt[rr * kSymLD + c] = tsim;
+    });
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  // mirror write: C[n0 + q][m0 + p] = ts[p][q] for global m0+p < n0+q
+  for (int e = t; e < kCB * kCB; e += kThreads) {
+    const int q = e / kCB, p = e % kCB;
+    const int64_t gi = m0 + p, gj = n0 + q;
+    if (gi < gj && gj < Na) {
+      const float v = ts[p * kSymLD + q];
+      const int64_t o = gj * ldc + gi;
+      C[o] = v;
+      if (Ch) split_bf16(v, Ch[o], Cl[o]);
+    }
+  }
+  // per-row partial sums of the off-diagonal entries
+  const float* sv = SIGT ? tt : ts;
+  if (I == J) {
+    if (t < kCB) {
+      double s1 = 0.0, s2 = 0.0, c2 = 0.0;
+      for (int q = 0; q < kCB; ++q) {  // row part (entries right of the diagonal)
+        const double x = sv[t * kSymLD + q];
+        s1 += x;
+        s2 += x * x;
+        if constexpr (SIGT) c2 += (double)ts[t * kSymLD + q] * (double)ts[t * kSymLD + q];
+      }
+      for (int p = 0; p < kCB; ++p) {  // column part (entries above the diagonal)
+        const double x = sv[p * kSymLD + t];
+        s1 += x;
+        s2 += x * x;
+        if constexpr (SIGT) c2 += (double)ts[p * kSymLD + t] * (double)ts[p * kSymLD + t];
+      }
+      cstat[I * ldstat + m0 + t] = make_double2(s1, s2);
+      if constexpr (SIGT) csq[I * ldstat + m0 + t] = c2;
+    }
+  } else {
+    const int q = t & (kCB - 1);
+    double s1 = 0.0, s2 = 0.0, c2 = 0.0;
+    if (t < kCB) {
+      for (int p = 0; p < kCB; ++p) {
+        const double x = sv[q * kSymLD + p];
+        s1 += x;
+        s2 += x * x;
+        if constexpr (SIGT) c2 += (double)ts[q * kSymLD + p] * (double)ts[q * kSymLD + p];
+      }
+      cstat[J * ldstat + m0 + q] = make_double2(s1, s2);
+      if constexpr (SIGT) csq[J * ldstat + m0 + q] = c2;
+    } else {
+      for (int p = 0; p < kCB; ++p) {
+        const double x = sv[p * kSymLD + q];
+        s1 += x;
+        s2 += x * x;
+        if constexpr (SIGT) c2 += (double)ts[p * kSymLD + q] * (double)ts[p * kSymLD + q];
+      }
+      cstat[I * ldstat + n0 + q] = make_double2(s1, s2);
+      if constexpr (SIGT) csq[I * ldstat + n0 + q] = c2;
+    }
+  }
+}
+
+// The C update of tile (I, J) from the accumulators of block GEMM g (each
+// thread owns TM * TN * 16 = kPer entries of the 128 x 128 tile).
+template <bool SIGT, class G>
+__device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I, int64_t J,
+                                               float* __restrict__ C, int64_t ldc, int64_t Na,
+                                               const double* __restrict__ ncol, double alpha,
+                                               double2* __restrict__ cstat,
+                                               double* __restrict__ csq, int64_t ldstat,
+                                               bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl) {
+  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
+  static_assert(G::TM * G::TN * 16 == kPer, "one accumulator per owned entry");
+  const int64_t m0 = I * kCB, n0 = J * kCB;
+  coreg_tile_update<SIGT, 16>(
+      [&](auto&& f) {
+#pragma unroll
+        for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < G::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) f((i * G::TN + j) * 16 + r, g.row_of(i, r), g.col_of(j));
+      },
+      [&](auto&& f) {
+#pragma unroll
+        for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < G::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int rr = g.row_of(i, r), c = g.col_of(j);
+              f((i * G::TN + j) * 16 + r, rr, c,
+                coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, ncol));
+            }
+      },
+      smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat, Ch, Cl);
+}
+
+// Shared memory of the C update with block GEMM G: the larger of the main
+// loop's stages and the staged tile (two tiles with SIGT).
+template <class G, bool SIGT>
+constexpr int coreg_smem_bytes() {
+  constexpr int TILE = kCB * kSymLD * 4 * (SIGT ? 2 : 1);
+  return G::MAIN_BYTES > TILE ? G::MAIN_BYTES : TILE;
+}
+
+// P update, first half: W W^T is only N_e x N_e but has K = N_a, so its
+// upper tiles are split over K into partial products.
+constexpr int kPB = (int)kCoopTile;
+
+}  // namespace gemm
+}  // namespace panda

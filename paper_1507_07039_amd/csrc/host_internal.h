@@ -1,0 +1,118 @@
+// Host-side internals shared by the single-network API (panda_api.hip) and
+// the batched API (batch_api.hip): error reporting, the workspace carver, the
+// per-network context and its workspace layout.
+#pragma once
+
+#include "panda.h"
+
+#include <stdio.h>
+
+#include "panda_internal.h"
+
+namespace panda {
+
+// Error text of the calling thread (panda_last_error); returns st.
+panda_status fail(panda_status st, const char* fmt, const char* what = "");
+panda_status hip_fail(hipError_t e, const char* where);
+
+#define HIP_TRY(call)                                         \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return panda::hip_fail(e_, #call);  \
+  } while (0)
+
+#define PANDA_TRY(call)                      \
+  do {                                       \
+    panda_status s_ = (call);                \
+    if (s_ != PANDA_OK) return s_;           \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace (sizes only when base is null).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+constexpr size_t kZsScratch = kZsBlocks + 8;  // doubles
+constexpr int kMaxPending = 16;               // timed iterations between read-backs
+
+Rule rule_of(const panda_options& o);
+panda_status check_options(const panda_options& o);
+bool dims_ok(int64_t Ne, int64_t Na);
+
+// Sizes of the buffers whose extent depends on the tile schedule.  The
+// single-network schedule fixes them; a batch sizes them for the smallest
+// tile and K chunk among its candidates, and needs no stream-K scratch.
+struct LayoutSpec {
+  bool batched;
+  int64_t hpart_tiles;  // per-tile h partials of the A + W product
+  int64_t ppart_splits; // K splits of the W W^T partial products
+};
+LayoutSpec single_spec(int64_t Ne, int64_t Na);
+
+}  // namespace panda
+
+struct panda_ctx {
+  int64_t Ne, Na, Nep, Nap;
+  panda_options opt;
+  panda::Rule rule;
+  hipStream_t stream;
+  float* W[2];
+  float* R;
+  float* P;
+  float* C;
+  float* Tside;
+  float* ppart;   // split-K partial products of W W^T
+  float* skpart;  // stream-K partial tiles (single-network schedule only)
+  double* nP;     // |P_i.|^2
+  double* nC;     // |C_.j|^2
+  double* nWr;    // |W_i.|^2
+  double* nWc;    // |W_.j|^2
+  double* colscr; // column-norm scratch
+  double* hpart;
+  double2* cstat;
+  double* csq;
+  double* zs;
+  uint32_t* corder;  // launch order of the upper C tiles
+  panda::DevState* st;
+  bool b3;  // split-BF16 products
+  panda::bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl, *Ch, *Cl;
+  panda::DevState* host;  // pinned
+  int splits;
+  int64_t nh;
+  int32_t t0;
+  int64_t executed;  // iterations known to have run since load
+  int64_t enqueued;  // iterations enqueued since load
+  bool loaded;
+  // phase timing
+  bool timing;
+  int npend;
+  hipEvent_t ev[16][PANDA_NPHASE + 1];
+  double tot_ms[PANDA_NPHASE];
+  int64_t cnt[PANDA_NPHASE];
+};
+
+namespace panda {
+
+// Workspace layout of one network: fills c (when not null) with pointers
+// into base and returns the bytes used.
+size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& spec, panda_ctx* c,
+                  char* base);
+// Context over an already carved workspace (no argument checks), with its
+// pinned state mirror; ctx_free releases what ctx_setup acquired.
+panda_status ctx_setup(panda_ctx* c, int64_t Ne, int64_t Na, const panda_options& o,
+                       const LayoutSpec& spec, char* base, hipStream_t stream);
+void ctx_free(panda_ctx* c);
+// Launch-order table of the upper C tiles (synchronises the context's stream).
+panda_status ctx_fill_order(panda_ctx* c);
+
+}  // namespace panda

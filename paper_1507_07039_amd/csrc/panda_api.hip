@@ -1,22 +1,21 @@
 // Host side of libpanda.so: argument checks, workspace layout, the
 // iteration sequence of Sec. II-B and the C ABI declared in include/panda.h.
-#include "panda.h"
-
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <new>
+#include <vector>
 
-#include "panda_internal.h"
+#include "host_internal.h"
 
 using namespace panda;
 
-namespace {
+namespace panda {
 
 thread_local char g_err[512] = "";
 
-panda_status fail(panda_status st, const char* fmt, const char* what = "") {
+panda_status fail(panda_status st, const char* fmt, const char* what) {
   snprintf(g_err, sizeof g_err, fmt, what);
   return st;
 }
@@ -26,29 +25,9 @@ panda_status hip_fail(hipError_t e, const char* where) {
   return PANDA_ERR_HIP;
 }
 
-#define HIP_TRY(call)                                   \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
-  } while (0)
+}  // namespace panda
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Bump allocator over the caller's workspace.
-struct Carver {
-  char* base;
-  size_t off = 0;
-  template <typename T>
-  T* take(size_t count) {
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += align_up(count * sizeof(T));
-    return p;
-  }
-};
-
-constexpr size_t kZsScratch = kZsBlocks + 8;  // doubles
-constexpr int kMaxPending = 16;               // timed iterations between read-backs
+namespace panda {
 
 Rule rule_of(const panda_options& o) {
   Rule r;
@@ -77,51 +56,18 @@ bool dims_ok(int64_t Ne, int64_t Na) {
   return Ne >= 1 && Na >= 1 && Ne <= (1 << 16) && Na <= (1 << 18);
 }
 
-}  // namespace
+}  // namespace panda
 
-struct panda_ctx {
-  int64_t Ne, Na, Nep, Nap;
-  panda_options opt;
-  Rule rule;
-  hipStream_t stream;
-  float* W[2];
-  float* R;
-  float* P;
-  float* C;
-  float* Tside;
-  float* ppart;   // split-K partial products of W W^T
-  float* skpart;  // stream-K partial tiles
-  double* nP;     // |P_i.|^2
-  double* nC;     // |C_.j|^2
-  double* nWr;    // |W_i.|^2
-  double* nWc;    // |W_.j|^2
-  double* colscr; // column-norm scratch
-  double* hpart;
-  double2* cstat;
-  double* csq;
-  double* zs;
-  DevState* st;
-  bool b3;  // split-BF16 products
-  bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl, *Ch, *Cl;
-  DevState* host;  // pinned
-  int splits;
-  int64_t nh;
-  int32_t t0;
-  int64_t executed;  // iterations known to have run since load
-  int64_t enqueued;  // iterations enqueued since load
-  bool loaded;
-  // phase timing
-  bool timing;
-  int npend;
-  hipEvent_t ev[16][PANDA_NPHASE + 1];
-  double tot_ms[PANDA_NPHASE];
-  int64_t cnt[PANDA_NPHASE];
-};
+namespace panda {
 
-namespace {
+LayoutSpec single_spec(int64_t Ne, int64_t Na) {
+  const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
+  return LayoutSpec{false, rect_tiles(Nep, Nap), coop_splits(Nep, Nap)};
+}
 
-// Workspace layout shared by the size query and the context.
-size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* base) {
+// Workspace layout shared by the size queries and the contexts.
+size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& spec, panda_ctx* c,
+                  char* base) {
   const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
   Carver cv{base};
   const size_t nw = (size_t)Nep * (size_t)Nap;
@@ -131,19 +77,20 @@ size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* bas
   float* p = cv.take<float>((size_t)Nep * Nep);
   float* cc = cv.take<float>((size_t)Nap * Nap);
   float* ts = cv.take<float>((size_t)Nep * Nep);
-  const int splits = coop_splits(Nep, Nap);
+  const int splits = (int)spec.ppart_splits;
   float* pp = cv.take<float>((size_t)splits * Nep * Nep);
-  float* sk = cv.take<float>(rect_partial_floats());
+  float* sk = spec.batched ? nullptr : cv.take<float>(rect_partial_floats());
   double* np_ = cv.take<double>((size_t)Nep);
   double* nc = cv.take<double>((size_t)Nap);
   double* nwr = cv.take<double>((size_t)Nep);
   double* nwc = cv.take<double>((size_t)Nap);
   double* scr = cv.take<double>((size_t)kColChunks * (size_t)Nap);
-  const int64_t nh = rect_tiles(Nep, Nap);
+  const int64_t nh = spec.hpart_tiles;
   double* hp = cv.take<double>((size_t)nh);
   double2* cs = cv.take<double2>((size_t)coreg_slots(Nap) * Nap);
   double* cq = cv.take<double>((size_t)coreg_slots(Nap) * Nap);
   double* zs = cv.take<double>(kZsScratch);
+  uint32_t* co = cv.take<uint32_t>((size_t)coreg_tiles(Nap));
   DevState* st = cv.take<DevState>(1);
   // split-BF16 operand planes
   const bool b3 = precision == PANDA_PREC_BF16X3;
@@ -180,6 +127,7 @@ size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* bas
     c->cstat = cs;
     c->csq = cq;
     c->zs = zs;
+    c->corder = co;
     c->st = st;
     c->b3 = b3;
     c->Wh = sh[0];
@@ -193,6 +141,43 @@ size_t layout(int64_t Ne, int64_t Na, int32_t precision, panda_ctx* c, char* bas
   }
   return cv.off;
 }
+
+panda_status ctx_setup(panda_ctx* c, int64_t Ne, int64_t Na, const panda_options& o,
+                       const LayoutSpec& spec, char* base, hipStream_t stream) {
+  c->Ne = Ne;
+  c->Na = Na;
+  c->opt = o;
+  c->rule = rule_of(o);
+  c->stream = stream;
+  ctx_layout(Ne, Na, o.precision, spec, c, base);
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(DevState),
+                        hipHostMallocDefault));
+  c->loaded = false;
+  return PANDA_OK;
+}
+
+panda_status ctx_fill_order(panda_ctx* c) {
+  // host table, copied before it goes away
+  std::vector<uint32_t> order((size_t)coreg_tiles(c->Nap));
+  coreg_order_fill(c->Nap, kCoregGroup, order.data());
+  HIP_TRY(hipMemcpyAsync(c->corder, order.data(), order.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return PANDA_OK;
+}
+
+void ctx_free(panda_ctx* c) {
+  if (c->host) (void)hipHostFree(c->host);
+  c->host = nullptr;
+  if (c->ev[0][0])
+    for (int i = 0; i < kMaxPending; ++i)
+      for (int p = 0; p <= PANDA_NPHASE; ++p) (void)hipEventDestroy(c->ev[i][p]);
+  c->ev[0][0] = nullptr;
+}
+
+}  // namespace panda
+
+namespace {
 
 // z-score of a strided matrix using `scratch`; synchronises the stream.
 panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, double* scratch,
@@ -235,12 +220,6 @@ panda_status read_state(panda_ctx* c) {
   c->executed = c->host->t - c->t0;
   return collect_times(c);
 }
-
-#define PANDA_TRY(call)                      \
-  do {                                       \
-    panda_status s_ = (call);                \
-    if (s_ != PANDA_OK) return s_;           \
-  } while (0)
 
 // Enqueue one iteration: R, A + W update, h, P update, C update, diagonals.
 // Iteration k (counted from the load) reads W[k % 2] and writes W[(k+1) % 2];
@@ -294,10 +273,11 @@ panda_status enqueue_iteration(panda_ctx* c) {
   // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
   if (c->b3)
     HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Ch, c->Cl, c->Nap,
-                                   c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, run_pc, s));
+                                   c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder,
+                                   run_pc, s));
   else
     HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc,
-                                c->rule, c->cstat, c->csq, run_pc, s));
+                                c->rule, c->cstat, c->csq, c->corder, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_DIAG));
   // Eq. 6, and |P_i.|^2, |C_.j|^2 for the next iteration
   HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->nP,
@@ -447,7 +427,8 @@ panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K
 size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt) {
   (void)opt;
   if (!dims_ok(Ne, Na)) return 0;
-  return layout(Ne, Na, opt ? opt->precision : PANDA_PREC_FP32, nullptr, nullptr);
+  return ctx_layout(Ne, Na, opt ? opt->precision : PANDA_PREC_FP32, single_spec(Ne, Na), nullptr,
+                    nullptr);
 }
 
 panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, void* workspace,
@@ -467,29 +448,18 @@ panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, 
     return fail(PANDA_ERR_WORKSPACE, "ctx_create: workspace too small or misaligned%s");
   panda_ctx* c = new (std::nothrow) panda_ctx();
   if (!c) return fail(PANDA_ERR_ARG, "ctx_create: out of host memory%s");
-  c->Ne = Ne;
-  c->Na = Na;
-  c->opt = o;
-  c->rule = rule_of(o);
-  c->stream = stream;
-  layout(Ne, Na, o.precision, c, static_cast<char*>(workspace));
-  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(DevState),
-                               hipHostMallocDefault);
-  if (e != hipSuccess) {
+  st = ctx_setup(c, Ne, Na, o, single_spec(Ne, Na), static_cast<char*>(workspace), stream);
+  if (st != PANDA_OK) {
     delete c;
-    return hip_fail(e, "hipHostMalloc");
+    return st;
   }
-  c->loaded = false;
   *out = c;
   return PANDA_OK;
 }
 
 void panda_ctx_destroy(panda_ctx* c) {
   if (!c) return;
-  if (c->host) (void)hipHostFree(c->host);
-  if (c->ev[0][0])
-    for (int i = 0; i < kMaxPending; ++i)
-      for (int p = 0; p <= PANDA_NPHASE; ++p) (void)hipEventDestroy(c->ev[i][p]);
+  ctx_free(c);
   delete c;
 }
 
@@ -543,6 +513,7 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
     HIP_TRY(launch_split_offdiag(c->P, Ne, Nep, c->Ph, c->Pl, s));
     HIP_TRY(launch_split_offdiag(c->C, Na, Nap, c->Ch, c->Cl, s));
   }
+  PANDA_TRY(ctx_fill_order(c));
   HIP_TRY(launch_state_init(c->st, t, s));
   c->t0 = t;
   c->executed = 0;

@@ -15,7 +15,8 @@ struct DevState {
   int32_t active;  // 1 while h >= tol: gates R, A, W and h
   int32_t run_pc;  // 1 when the current iteration updates P and C: gates Eq. 5-6
   int32_t conv;    // 1 once h < tol
-  int32_t pad[2];
+  int32_t wsel;    // index (0/1) of the buffer holding the current W; flipped with t
+  int32_t pad;
 };
 
 // Scalars of the update rules.
@@ -39,6 +40,7 @@ constexpr int kColChunks = 64;           // row chunks of the column-norm kernel
 constexpr int64_t kPadE = 64;
 constexpr int64_t kPadA = 128;
 constexpr int64_t kPadK = 32;            // K of a stand-alone similarity product
+constexpr int64_t kCoopTile = 64;        // tile side of the W W^T partial products
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ------------------------------------------------------------ launchers --
@@ -62,11 +64,22 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* 
                                 float* part, const int32_t* gate, hipStream_t s);
 
 // C update (Eq. 5) on the upper tiles of T(W^T, W) with mirror writes and
-// per-row partial sums for the sigma of Eq. 6 (and |C_.j|^2).
+// per-row partial sums for the sigma of Eq. 6 (and |C_.j|^2).  order holds
+// the upper tiles (I | J << 16) in launch order, see coreg_order_fill.
 hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* C, int64_t ldc,
                                int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
-                               double2* cstat, double* csq, const int32_t* gate, hipStream_t s);
+                               double2* cstat, double* csq, const uint32_t* order,
+                               const int32_t* gate, hipStream_t s);
 int64_t coreg_slots(int64_t Nap);
+// Upper tiles of the C product (Nap / 128 per side) and their launch order:
+// group x group super-tiles, so the tiles running together on one XCD share
+// 2 * group operand strips in its L2.
+int64_t coreg_tiles(int64_t Nap);
+void coreg_order_fill(int64_t Nap, int group, uint32_t* out);
+#ifndef PANDA_COREG_GROUP
+#define PANDA_COREG_GROUP 6
+#endif
+constexpr int kCoregGroup = PANDA_COREG_GROUP;
 
 // P update, split over K: partial products of W W^T on upper tiles.
 hipError_t launch_coop_partial(const float* W, int64_t ldw, int64_t Nep, int64_t Nap, int splits,
@@ -89,7 +102,8 @@ hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const bf1
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
                                   float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
                                   int64_t Na, const double* nWcol, Rule rule, double2* cstat,
-                                  double* csq, const int32_t* gate, hipStream_t s);
+                                  double* csq, const uint32_t* order, const int32_t* gate,
+                                  hipStream_t s);
 hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ldw, int64_t Nep,
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s);

@@ -3,57 +3,20 @@
 // squared-norm vectors the similarity epilogues read, and the z-score
 // normalisation of Sec. II-A.  All reductions are FP64 and run in a fixed
 // order, so results do not depend on scheduling.
-#include "panda_internal.h"
+#include "update_device.h"
 
 namespace panda {
 namespace {
 
-constexpr int kRT = 256;  // threads per block for the kernels in this file
+using upd::block_sum;
+using upd::split_bf16;
+constexpr int kRT = upd::kUT;  // threads per block for the kernels in this file
 
-// Sum of one double per thread over a 256-thread block, fixed order.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return ((red[0] + red[1]) + red[2]) + red[3];
-}
-
-// h = (1 / count) * sum of the per-tile partials (Eq. 7); advance t and set
-// the gates of the rest of this iteration and of the next one.
 __global__ __launch_bounds__(kRT) void k_finish_h(const double* __restrict__ hpart, int64_t n,
                                                   int64_t count, DevState* st, double tol,
                                                   int32_t update_last) {
   __shared__ double red[4];
-  if (st->active == 0) {  // converged earlier: this iteration is a no-op
-    if (threadIdx.x == 0) st->run_pc = 0;
-    return;
-  }
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kRT) s += hpart[i];
-  const double tot = block_sum(s, red);
-  if (threadIdx.x == 0) {
-    const double h = tot / (double)count;
-    st->h = h;
-    st->t = st->t + 1;
-    const int conv = h < tol;
-    st->conv = conv;
-    st->run_pc = (!conv || update_last) ? 1 : 0;
-    if (conv) st->active = 0;
-  }
-}
-
-// P update, second half (Eq. 5): for every i < j < Ne sum the split-K
-// partial products, form T(W_i., W_j.) with the row norms of the new W and
-// write the damped value at (i, j) and (j, i).
-__device__ __forceinline__ bf16_t to_bf16(float x) {
-  return __builtin_bit_cast(bf16_t, (__bf16)x);
-}
-// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even.
-__device__ __forceinline__ void split_bf16(float x, bf16_t& hi, bf16_t& lo) {
-  hi = to_bf16(x);
-  lo = to_bf16(x - (float)__builtin_bit_cast(__bf16, hi));
+  upd::finish_h(hpart, n, count, st, tol, update_last, red);
 }
 
 __global__ __launch_bounds__(kRT) void k_coop_finalize(
@@ -61,35 +24,12 @@ __global__ __launch_bounds__(kRT) void k_coop_finalize(
     float* __restrict__ P, int64_t ldp, int64_t Ne, double alpha, float* __restrict__ Tside,
     bf16_t* __restrict__ Ph, bf16_t* __restrict__ Pl, const int32_t* gate) {
   if (*gate == 0) return;
-  const int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x;
-  if (e >= Ne * Ne) return;
-  const int64_t i = e / Ne, j = e % Ne;
-  if (i >= j) return;
-  double dot = 0.0;
-  for (int s = 0; s < splits; ++s) dot += (double)part[(int64_t)s * Nep * Nep + i * Nep + j];
-  const double den = nW[i] + nW[j] - fabs(dot);
-  const double tv = den > 0.0 ? dot / sqrt(den) : 0.0;
-  const float v = (float)((1.0 - alpha) * (double)P[i * ldp + j] + alpha * tv);
-  P[i * ldp + j] = v;
-  P[j * ldp + i] = v;
-  if (Ph) {
-    bf16_t h, l;
-    split_bf16(v, h, l);
-    Ph[i * ldp + j] = Ph[j * ldp + i] = h;
-    Pl[i * ldp + j] = Pl[j * ldp + i] = l;
-  }
-  if (Tside) {
-    Tside[i * ldp + j] = (float)tv;
-    Tside[j * ldp + i] = (float)tv;
-  }
+  upd::coop_finalize_entry((int64_t)blockIdx.x * kRT + threadIdx.x, part, splits, Nep, nW, P, ldp,
+                           Ne, alpha, Tside, Ph, Pl);
 }
 
-// Eq. 6 for both networks, and the squared norms |P_i.|^2, |C_.j|^2 that the
-// next iteration's similarities need.  Blocks [0, Ne): row i of P, population
-// std of its off-diagonal entries by two passes over the row.  Remaining
-// blocks: one thread per row of C, from the per-slot (sum, sum of squares)
-// written by the C update.  New diagonal = (1 - alpha) old + f * mult *
-// sigma * exp(2 alpha t), f = alpha (default reading) or 1 (literal Eq. 6).
+// Eq. 6 for both networks.  Blocks [0, Ne): row i of P; remaining blocks:
+// one thread per row of C.
 __global__ __launch_bounds__(kRT) void k_diagonals(
     float* __restrict__ P, int64_t ldp, int64_t Ne, const float* __restrict__ Tside,
     double* __restrict__ nP, float* __restrict__ C, int64_t ldc, int64_t Na,
@@ -97,55 +37,13 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st) {
   __shared__ double red[4];
   if (st->run_pc == 0) return;
-  const double g = exp(2.0 * alpha * (double)st->t);
-  const double f = diag_alpha ? alpha : 1.0;
+  const upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
   if ((int64_t)blockIdx.x < Ne) {
-    const int64_t i = blockIdx.x;
-    const float* prow = P + i * ldp;
-    const float* row = Tside ? Tside + i * ldp : prow;
-    double s = 0.0, q2 = 0.0;
-    for (int64_t m = threadIdx.x; m < Ne; m += kRT)
-      if (m != i) {
-        s += row[m];
-        q2 += (double)prow[m] * (double)prow[m];
-      }
-    const double n = (double)(Ne - 1);
-    const double mean = Ne > 1 ? block_sum(s, red) / n : 0.0;
-    const double off2 = block_sum(q2, red);
-    double q = 0.0;
-    for (int64_t m = threadIdx.x; m < Ne; m += kRT)
-      if (m != i) q += ((double)row[m] - mean) * ((double)row[m] - mean);
-    const double var = Ne > 1 ? block_sum(q, red) / n : 0.0;
-    if (threadIdx.x == 0) {
-      const double mult = n_own ? (double)Ne : (double)Na;
-      const double d = (double)P[i * ldp + i];
-      const float dn = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
-      P[i * ldp + i] = dn;
-      nP[i] = off2 + (double)dn * (double)dn;
-    }
+    upd::diag_p_row(blockIdx.x, P, ldp, Ne, Na, Tside, nP, dr, red);
     return;
   }
   const int64_t r = ((int64_t)blockIdx.x - Ne) * kRT + threadIdx.x;
-  if (r >= Na) return;
-  double s1 = 0.0, s2 = 0.0, c2 = 0.0;
-  for (int64_t sl = 0; sl < nslots; ++sl) {  // slot stride = ldc (both are the padded N_a)
-    const double2 v = cstat[sl * ldc + r];
-    s1 += v.x;
-    s2 += v.y;
-    if (csq) c2 += csq[sl * ldc + r];
-  }
-  if (!csq) c2 = s2;
-  double var = 0.0;
-  if (Na > 1) {
-    const double n = (double)(Na - 1), mean = s1 / n;
-    var = s2 / n - mean * mean;
-    if (var < 0.0) var = 0.0;
-  }
-  const double mult = n_own ? (double)Na : (double)Ne;
-  const double d = (double)C[r * ldc + r];
-  const float dn = (float)((1.0 - alpha) * d + f * mult * sqrt(var) * g);
-  C[r * ldc + r] = dn;
-  nC[r] = c2 + (double)dn * (double)dn;
+  if (r < Na) upd::diag_c_row(r, C, ldc, Ne, Na, cstat, csq, nslots, nC, dr);
 }
 
 // ---- split-BF16 operand planes ----------------------------------------------
@@ -205,10 +103,7 @@ __global__ __launch_bounds__(kRT) void k_row_sqnorms(const float* __restrict__ M
                                                      const int32_t* gate) {
   __shared__ double red[4];
   if (gate && *gate == 0) return;
-  const float* row = M + (int64_t)blockIdx.x * ld;
-  double s = 0.0;
-  for (int64_t j = threadIdx.x; j < cols; j += kRT) s += (double)row[j] * (double)row[j];
-  const double tot = block_sum(s, red);
+  const double tot = upd::row_sqnorm(M + (int64_t)blockIdx.x * ld, cols, red);
   if (threadIdx.x == 0) out[blockIdx.x] = tot;
 }
 
@@ -222,9 +117,7 @@ __global__ __launch_bounds__(kRT) void k_col_sqnorms_part(const float* __restric
   if (j >= cols) return;
   const int64_t r0 = (int64_t)blockIdx.y * chunk;
   const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
-  double s = 0.0;
-  for (int64_t i = r0; i < r1; ++i) s += (double)M[i * ld + j] * (double)M[i * ld + j];
-  scr[(int64_t)blockIdx.y * cols + j] = s;
+  scr[(int64_t)blockIdx.y * cols + j] = upd::col_sqnorm_part(M, ld, j, r0, r1);
 }
 
 __global__ __launch_bounds__(kRT) void k_col_sqnorms_sum(const double* __restrict__ scr,
@@ -308,7 +201,8 @@ __global__ void k_state_init(DevState* st, int32_t t0) {
     st->active = 1;
     st->run_pc = 0;
     st->conv = 0;
-    st->pad[0] = st->pad[1] = 0;
+    st->wsel = 0;
+    st->pad = 0;
   }
 }
 
@@ -369,9 +263,7 @@ hipError_t launch_row_sqnorms(const float* M, int64_t rows, int64_t cols, int64_
 
 hipError_t launch_col_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,
                               double* scratch, const int32_t* gate, hipStream_t s) {
-  int nch = (int)((rows + 63) / 64);  // about 64 rows per chunk
-  if (nch > kColChunks) nch = kColChunks;
-  if (nch < 1) nch = 1;
+  const int nch = upd::col_chunks(rows);
   const int64_t chunk = (rows + nch - 1) / nch;
   const unsigned gx = (unsigned)((cols + kRT - 1) / kRT);
   k_col_sqnorms_part<<<dim3(gx, (unsigned)nch), kRT, 0, s>>>(M, rows, cols, ld, chunk, scratch,

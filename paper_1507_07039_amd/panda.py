@@ -24,8 +24,14 @@ EXPORTS = (
     "panda_tanimoto_workspace_bytes", "panda_tanimoto", "panda_workspace_bytes",
     "panda_ctx_create", "panda_ctx_load", "panda_iterate", "panda_ctx_store",
     "panda_ctx_destroy", "panda_run", "panda_ctx_set_timing", "panda_ctx_phase_times",
+    "panda_batch_workspace_bytes", "panda_batch_create", "panda_batch_destroy",
+    "panda_batch_tile_candidates", "panda_batch_get_tiles", "panda_batch_set_tiles",
+    "panda_batch_autotune", "panda_batch_load", "panda_batch_iterate", "panda_batch_run",
+    "panda_batch_state", "panda_batch_store",
     "panda_status_string", "panda_last_error",
 )
+
+BATCH_TILES = ("R", "A+W", "P-partial", "C")
 
 PHASES = ("R", "A+W", "h", "P-partial", "P-final", "C", "diag")
 
@@ -74,6 +80,20 @@ def load_library(path: str = LIB_PATH):
                                  ct.POINTER(i32), ct.POINTER(dbl), vp]),
         "panda_ctx_set_timing": (ct.c_int, [vp, i32]),
         "panda_ctx_phase_times": (ct.c_int, [vp, ct.POINTER(dbl), ct.POINTER(i64)]),
+        "panda_batch_workspace_bytes": (sz, [i32, ct.POINTER(i64), ct.POINTER(i64), op]),
+        "panda_batch_create": (ct.c_int, [i32, ct.POINTER(i64), ct.POINTER(i64), op, vp, sz, vp,
+                                          ct.POINTER(vp)]),
+        "panda_batch_destroy": (None, [vp]),
+        "panda_batch_tile_candidates": (i32, [i32]),
+        "panda_batch_get_tiles": (ct.c_int, [vp, ct.POINTER(i32)]),
+        "panda_batch_set_tiles": (ct.c_int, [vp, ct.POINTER(i32)]),
+        "panda_batch_autotune": (ct.c_int, [vp, i32, ct.POINTER(ct.c_float)]),
+        "panda_batch_load": (ct.c_int, [vp, i32, vp, vp, vp, i32]),
+        "panda_batch_iterate": (ct.c_int, [vp, i32, i32, ct.POINTER(i32)]),
+        "panda_batch_run": (ct.c_int, [vp, i32, ct.POINTER(i32)]),
+        "panda_batch_state": (ct.c_int, [vp, i32, ct.POINTER(dbl), ct.POINTER(i32),
+                                         ct.POINTER(i32)]),
+        "panda_batch_store": (ct.c_int, [vp, i32, vp, vp, vp, ct.POINTER(dbl), ct.POINTER(i32)]),
         "panda_status_string": (ct.c_char_p, [ct.c_int]),
         "panda_last_error": (ct.c_char_p, []),
     }
@@ -259,3 +279,110 @@ def run(W0, P0=None, C0=None, alpha: float = 0.1, tol: float = 1e-3, max_iter: i
                          ct.byref(o), ct.byref(it), ct.byref(hv), _stream())
     _check(code, allow=(OK, NOT_CONVERGED))
     return RunResult(W, P, C, it.value, hv.value, code)
+
+
+def _shape_arrays(shapes):
+    n = len(shapes)
+    Ne = (ct.c_int64 * n)(*[int(a) for a, _ in shapes])
+    Na = (ct.c_int64 * n)(*[int(b) for _, b in shapes])
+    return n, Ne, Na
+
+
+def batch_workspace_bytes(shapes, opts: Options | None = None) -> int:
+    """Workspace of a batch of networks with shapes [(Ne, Na), ...]."""
+    o = opts or default_options()
+    n, Ne, Na = _shape_arrays(shapes)
+    return load_library().panda_batch_workspace_bytes(n, Ne, Na, ct.byref(o))
+
+
+class Batch:
+    """Independent networks iterating together in grouped launches."""
+
+    def __init__(self, shapes, opts: Options | None = None, ws=None):
+        self.lib = load_library()
+        self.shapes = [(int(a), int(b)) for a, b in shapes]
+        self.opts = opts or default_options()
+        need = batch_workspace_bytes(self.shapes, self.opts)
+        if need == 0:
+            raise PandaError(ERR_ARG, "bad batch shapes")
+        self.ws = ws if ws is not None else workspace(need)
+        n, Ne, Na = _shape_arrays(self.shapes)
+        h = ct.c_void_p()
+        _check(self.lib.panda_batch_create(n, Ne, Na, ct.byref(self.opts), self.ws.data_ptr(),
+                                           self.ws.numel(), _stream(), ct.byref(h)))
+        self.h = h
+
+    def __len__(self):
+        return len(self.shapes)
+
+    @staticmethod
+    def candidates():
+        lib = load_library()
+        return [lib.panda_batch_tile_candidates(p) for p in range(len(BATCH_TILES))]
+
+    @property
+    def tiles(self):
+        c = (ct.c_int32 * len(BATCH_TILES))()
+        _check(self.lib.panda_batch_get_tiles(self.h, c))
+        return list(c)
+
+    @tiles.setter
+    def tiles(self, choice):
+        c = (ct.c_int32 * len(BATCH_TILES))(*[int(x) for x in choice])
+        _check(self.lib.panda_batch_set_tiles(self.h, c))
+
+    def autotune(self, reps: int = 3):
+        """Pick the fastest tile of every grouped product (before loading);
+        returns {product: best ms}."""
+        ms = (ct.c_float * len(BATCH_TILES))()
+        _check(self.lib.panda_batch_autotune(self.h, int(reps), ms))
+        return dict(zip(BATCH_TILES, list(ms)))
+
+    def load(self, i: int, W, P=None, C=None, t: int = 0):
+        Ne, Na = self.shapes[i]
+        pw = _dev(W, "W", (Ne, Na))
+        pp = None if P is None else _dev(P, "P", (Ne, Ne))
+        pc = None if C is None else _dev(C, "C", (Na, Na))
+        _check(self.lib.panda_batch_load(self.h, int(i), pw, pp, pc, int(t)))
+
+    def iterate(self, steps: int = 1, graph: bool = False) -> int:
+        """steps iterations; returns how many networks are still iterating."""
+        a = ct.c_int32()
+        _check(self.lib.panda_batch_iterate(self.h, int(steps), int(graph), ct.byref(a)))
+        return a.value
+
+    def run(self, graph: bool = True):
+        """Iterate to convergence (or max_iter); returns (status, steps)."""
+        st = ct.c_int32()
+        code = self.lib.panda_batch_run(self.h, int(graph), ct.byref(st))
+        _check(code, allow=(OK, NOT_CONVERGED))
+        return code, st.value
+
+    def status(self, i: int):
+        """(h, t, still iterating) of network i at the last read-back."""
+        hv, tv, av = ct.c_double(), ct.c_int32(), ct.c_int32()
+        _check(self.lib.panda_batch_state(self.h, int(i), ct.byref(hv), ct.byref(tv),
+                                          ct.byref(av)))
+        return hv.value, tv.value, bool(av.value)
+
+    def state(self, i: int):
+        torch = _torch()
+        Ne, Na = self.shapes[i]
+        W = torch.empty((Ne, Na), dtype=torch.float32, device="cuda")
+        P = torch.empty((Ne, Ne), dtype=torch.float32, device="cuda")
+        C = torch.empty((Na, Na), dtype=torch.float32, device="cuda")
+        hv, tv = ct.c_double(), ct.c_int32()
+        _check(self.lib.panda_batch_store(self.h, int(i), W.data_ptr(), P.data_ptr(),
+                                          C.data_ptr(), ct.byref(hv), ct.byref(tv)))
+        return W, P, C, hv.value, tv.value
+
+    def close(self):
+        if self.h:
+            self.lib.panda_batch_destroy(self.h)
+            self.h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

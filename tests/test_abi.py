@@ -97,3 +97,39 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 for pat in (r"^\s*(from|import)\s+oracle", r"liboracle", r"panda_oracle"):
                     assert not re.search(pat, txt, flags=re.M), (pat, os.path.join(dirpath, f))
+
+
+def test_batch_host_validation(lib):
+    """Batched entry points reject bad shapes, options and workspaces on the host."""
+    o = panda.default_options()
+    Ne = (ct.c_int64 * 3)(40, 3, 700)
+    Na = (ct.c_int64 * 3)(400, 5, 18000)
+    total = lib.panda_batch_workspace_bytes(3, Ne, Na, ct.byref(o))
+    singles = sum(lib.panda_workspace_bytes(a, b, ct.byref(o)) for a, b in zip(Ne, Na))
+    # one region per network (no stream-K scratch, work lists on top)
+    assert 0.5 * singles < total < 1.5 * singles
+    assert lib.panda_batch_workspace_bytes(0, Ne, Na, ct.byref(o)) == 0
+    bad = (ct.c_int64 * 3)(40, 0, 700)
+    assert lib.panda_batch_workspace_bytes(3, bad, Na, ct.byref(o)) == 0
+    out = ct.c_void_p()
+    fake = ct.c_void_p(256)
+    assert lib.panda_batch_create(3, bad, Na, ct.byref(o), fake, 1 << 40, None,
+                                  ct.byref(out)) == panda.ERR_ARG
+    assert lib.panda_batch_create(3, Ne, Na, ct.byref(o), None, 1 << 40, None,
+                                  ct.byref(out)) == panda.ERR_WORKSPACE
+    assert lib.panda_batch_create(3, Ne, Na, ct.byref(o), fake, 64, None,
+                                  ct.byref(out)) == panda.ERR_WORKSPACE
+    b3 = panda.default_options(precision=1)
+    assert lib.panda_batch_create(3, Ne, Na, ct.byref(b3), fake, 1 << 40, None,
+                                  ct.byref(out)) == panda.ERR_ARG
+    assert b"FP32" in lib.panda_last_error()
+    assert [lib.panda_batch_tile_candidates(p) for p in range(4)] == [3, 3, 4, 3]
+    assert lib.panda_batch_tile_candidates(4) == 0 and lib.panda_batch_tile_candidates(-1) == 0
+    a = ct.c_int32()
+    h = ct.c_double()
+    assert lib.panda_batch_iterate(None, 1, 0, ct.byref(a)) == panda.ERR_ARG
+    assert lib.panda_batch_run(None, 0, ct.byref(a)) == panda.ERR_ARG
+    assert lib.panda_batch_state(None, 0, ct.byref(h), ct.byref(a), ct.byref(a)) == panda.ERR_ARG
+    assert lib.panda_batch_load(None, 0, fake, None, None, 0) == panda.ERR_ARG
+    assert lib.panda_batch_set_tiles(None, (ct.c_int32 * 4)()) == panda.ERR_ARG
+    lib.panda_batch_destroy(None)  # no-op

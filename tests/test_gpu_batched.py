@@ -1,0 +1,227 @@
+"""The batched form (panda_batch_*): many networks of different sizes iterating
+together in grouped launches, against the FP64 oracle run on each network
+alone, with the same tolerances as the single-network parity tests (W, P and
+C off-diagonals max-abs 1e-4; diagonals relative 1e-5; h relative 1e-5).
+
+Also: every tile candidate of every grouped product, convergence masks (each
+network stops at its own iteration), max_iter, graph replay against eager
+launches (bit-exact), the autotuner, and the 48-network workload at full
+size against single-network runs and sampled FP64 entries.
+"""
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from paper_1507_07039_amd import inputs as I
+from test_gpu_parity import compare_state, cuda, f32r, host, prep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def pd(torch):
+    from paper_1507_07039_amd import panda
+    panda.load_library()
+    return panda
+
+
+RAGGED = [(3, 5), (65, 300), (70, 257), (1, 7), (17, 130)]
+
+
+def ragged(Ne, Na):
+    rng = np.random.default_rng(Ne * 1000 + Na)
+    W = f32r(rng.normal(size=(Ne, Na)))
+    P = f32r(I.random_symmetric(Ne + 1, Ne))
+    C = f32r(I.random_symmetric(Na + 2, Na))
+    return W, P, C
+
+
+def small_like(oracle, seed, Ne=40, Na=400):
+    return prep(oracle, *I.priors(seed, Ne, Na, 0.05, 0.03, 30, 8))
+
+
+def new_batch(torch, pd, nets, tiles=None, **kw):
+    b = pd.Batch([W.shape for W, _, _ in nets], pd.default_options(**kw))
+    if tiles is not None:
+        b.tiles = tiles
+    for i, (W, P, C) in enumerate(nets):
+        b.load(i, cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    return b
+
+
+def check_steps(torch, pd, oracle, nets, steps, tiles=None, what=""):
+    """Iterate the batch one step at a time next to the oracle on every network."""
+    b = new_batch(torch, pd, nets, tiles, tol=0.0)
+    o = oracle.Options(tol=0.0)
+    refs = [list(n) for n in nets]
+    for t in range(1, steps + 1):
+        assert b.iterate(1) == len(nets)
+        for i in range(len(nets)):
+            Wo, Po, Co, ho, _ = oracle.step(*refs[i], t, o)
+            refs[i] = [Wo, Po, Co]
+            Wg, Pg, Cg, hg, tg = b.state(i)
+            assert tg == t
+            assert abs(hg - ho) <= 1e-5 * ho + 1e-9, (what, i, t, hg, ho)
+            compare_state(host(Wg), host(Pg), host(Cg), Wo, Po, Co, what=f"{what} net {i} t={t}")
+    b.close()
+
+
+def test_batch_matches_oracle_per_network(torch, pd, oracle):
+    nets = [prep(oracle, *I.workload_priors(I.SMALL))] + [ragged(*s) for s in RAGGED]
+    check_steps(torch, pd, oracle, nets, 6, what="default tiles")
+
+
+@pytest.mark.parametrize("phase", [0, 1, 2, 3])
+def test_every_tile_candidate(torch, pd, oracle, phase):
+    nets = [prep(oracle, *I.workload_priors(I.SMALL)), ragged(65, 300), ragged(70, 257)]
+    for c in range(pd.Batch.candidates()[phase]):
+        tiles = [0, 0, 0, 0]
+        tiles[phase] = c
+        check_steps(torch, pd, oracle, nets, 3, tiles, what=f"tiles {tiles}")
+
+
+def test_convergence_masks_and_max_iter(torch, pd, oracle):
+    """Each network stops at its own iteration; converged ones stay frozen."""
+    nets = [small_like(oracle, s) for s in (1507, 11, 12)] + [small_like(oracle, 13, 30, 300)]
+    refs = [oracle.run(*n) for n in nets]
+    b = new_batch(torch, pd, nets)
+    status, steps = b.run(graph=True)
+    assert status == pd.OK
+    assert steps >= max(r.iters for r in refs)
+    assert len({r.iters for r in refs}) > 1  # the networks converge at different t
+    for i, r in enumerate(refs):
+        Wg, Pg, Cg, hg, tg = b.state(i)
+        assert tg == r.iters, (i, tg, r.iters)
+        assert abs(hg - r.h) <= 1e-5 * r.h
+        compare_state(host(Wg), host(Pg), host(Cg), r.W, r.P, r.C, what=f"net {i}")
+        assert b.status(i)[2] is False
+    before = [b.state(i) for i in range(len(nets))]
+    assert b.iterate(3) == 0
+    for i in range(len(nets)):
+        after = b.state(i)
+        assert all(torch.equal(x, y) for x, y in zip(before[i][:3], after[:3]))
+        assert after[4] == before[i][4]
+    # max_iter: every network stops at 5 with the oracle's state of t = 5
+    b5 = new_batch(torch, pd, nets, max_iter=5, poll_every=2)
+    status, steps = b5.run(graph=False)
+    assert status == pd.NOT_CONVERGED and steps == 5
+    for i, n in enumerate(nets):
+        r5 = oracle.run(*n, oracle.Options(max_iter=5))
+        Wg, Pg, Cg, _, tg = b5.state(i)
+        assert tg == 5
+        compare_state(host(Wg), host(Pg), host(Cg), r5.W, r5.P, r5.C, what=f"max_iter net {i}")
+
+
+def test_graph_replay_equals_eager(torch, pd, oracle):
+    """Replays of the captured iteration give bit-identical states to eager
+    launches, with other GPU work and synchronisations between replays, and
+    after the tiles (hence the graph) change."""
+    nets = [prep(oracle, *I.workload_priors(I.SMALL))] + [ragged(*s) for s in RAGGED[:3]]
+    eager = new_batch(torch, pd, nets, tol=0.0)
+    graph = new_batch(torch, pd, nets, tol=0.0)
+    x = torch.randn(1 << 20, device="cuda")
+    for chunk in (1, 2, 3, 1):
+        eager.iterate(chunk, graph=False)
+        y = (x * 2.0).sum()  # unrelated work on the same stream
+        graph.iterate(chunk, graph=True)
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        for i in range(len(nets)):
+            a, g = eager.state(i), graph.state(i)
+            assert a[4] == g[4] and a[3] == g[3]
+            assert all(torch.equal(p, q) for p, q in zip(a[:3], g[:3])), (chunk, i)
+    eager.tiles = [1, 2, 1, 2]
+    graph.tiles = [1, 2, 1, 2]
+    eager.iterate(2, graph=False)
+    graph.iterate(2, graph=True)
+    for i in range(len(nets)):
+        a, g = eager.state(i), graph.state(i)
+        assert all(torch.equal(p, q) for p, q in zip(a[:3], g[:3]))
+
+
+def test_autotune_then_iterate(torch, pd, oracle):
+    nets = [prep(oracle, *I.workload_priors(I.SMALL)), ragged(65, 300)]
+    b = pd.Batch([W.shape for W, _, _ in nets], pd.default_options(tol=0.0))
+    best = b.autotune(reps=2)
+    assert set(best) == {"R", "A+W", "P-partial", "C"} and all(v > 0 for v in best.values())
+    tiles = b.tiles
+    assert all(0 <= c < n for c, n in zip(tiles, pd.Batch.candidates()))
+    with pytest.raises(pd.PandaError):
+        b.iterate(1)  # autotune leaves every network unloaded
+    b.close()
+    check_steps(torch, pd, oracle, nets, 2, tiles, what=f"tuned {tiles}")
+
+
+@pytest.mark.timeout(900)
+def test_48_networks_full_size(torch, pd, oracle):
+    """48 networks, T in [50, 700], G in [1000, 18000]: sampled FP64 entries of
+    the first iteration, then whole runs against single-network runs."""
+    shapes = I.batched_shapes()
+
+    def gen(s):
+        T, G, seed = s
+        return I.to_f32(*I.priors(seed, T, G, 0.03, 0.01, 200, 20))
+
+    t0 = time.perf_counter()
+    dev = []
+    with ThreadPoolExecutor(4) as ex:
+        for W0, P0, C0 in ex.map(gen, shapes):
+            d = [torch.from_numpy(M).cuda() for M in (W0, P0, C0)]
+            for M in d:
+                pd.normalize(M)
+            dev.append(d)
+            del W0, P0, C0
+    print(f"\n48 networks generated in {time.perf_counter() - t0:.1f} s")
+    b = pd.Batch([(T, G) for T, G, _ in shapes])
+    best = b.autotune(reps=2)
+    print("autotuned tiles", b.tiles, {k: round(v, 3) for k, v in best.items()})
+    for i, d in enumerate(dev):
+        b.load(i, *d)
+    b.iterate(1)
+    rng = np.random.default_rng(5)
+    order = sorted(range(48), key=lambda i: shapes[i][0] * shapes[i][1] ** 2)
+    for i in (order[0], order[24], order[-1]):
+        Wg = host(b.state(i)[0])
+        W, P, C = (host(M) for M in dev[i])
+        Ne, Na = W.shape
+        r = rng.integers(0, Ne, size=1024)
+        c = rng.integers(0, Na, size=1024)
+        want = oracle.step_w_entries(W, P, C, 0.1, r, c)
+        err = np.abs(Wg[r, c] - want).max()
+        print(f"  net {i} ({Ne}x{Na}) t=1: max sampled |W - oracle| = {err:.2e}")
+        assert err <= 1e-4
+        del W, P, C
+    # whole runs: batched (graph replays) against each network run alone
+    for i, d in enumerate(dev):
+        b.load(i, *d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, steps = b.run(graph=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    assert status == pd.OK
+    t_single = 0.0
+    worst = 0.0
+    for i, d in enumerate(dev):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref = pd.run(*d)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t0
+        Wg, _, _, _, tg = b.state(i)
+        assert abs(tg - ref.iters) <= 2, (i, tg, ref.iters)
+        rel = (Wg - ref.W).abs().max().item() / max(1.0, ref.W.abs().max().item())
+        worst = max(worst, rel)
+        assert rel <= 1e-3, (i, rel)
+    print(f"  batched run {t_batch:.3f} s ({steps} steps) vs {t_single:.3f} s for the 48 "
+          f"networks one by one; worst max|dW|/max|W| = {worst:.2e}")
