@@ -231,6 +231,69 @@ panda_status panda_batch_state(const panda_batch* b, int32_t i, double* h, int32
 panda_status panda_batch_store(panda_batch* b, int32_t i, float* W, float* P, float* C,
                                double* h, int32_t* t);
 
+/* ---- Learned warm start ---------------------------------------------------
+ * Not part of the paper's method: a small network predicts the converged W
+ * of a run from features of the priors, and the message passing of Eq. 2-7
+ * is then polished from a state rebuilt around that prediction.  The plain
+ * run from the priors remains the reference and the fallback.
+ *
+ * Features (16 per edge (i, j), row i*Na + j of F, FP32, each column z-scored
+ * over the Ne*Na edges with the population std; a constant column is 0):
+ *   W0_ij; sum_j W0_ij; sum_i W0_ij; for k < 6: a_k[i] b_k[j] and c_k[i] d_k[j];
+ *   (R0_ij + A0_ij) / 2.  a = orthonormal basis (Cholesky QR; a rank-deficient
+ *   sketch ends the basis and zeroes the rest) of P0 (P0 omegaP), b = W0^T P0 a;
+ *   d = basis of C0 (C0 omegaC), c = W0 C0 d; R0 = T(P0, W0), A0 = T(W0, C0)
+ *   (Eq. 1, 3, 4).  omegaP (Ne x 6) and omegaC (Na x 6) are the caller's
+ *   random sketch matrices (device, FP32, row-major).  The features are taken
+ *   from a context just loaded with the normalised priors (a context of a
+ *   batch is rejected); *tau = population std of (R0 + A0) / 2 - W0, the unit
+ *   of the network's output.  Synchronises the context's stream. */
+enum { PANDA_WS_FEATURES = 16, PANDA_WS_SKETCH = 6, PANDA_MLP_PARAMS = 5313 };
+size_t panda_ws_features_workspace_bytes(int64_t Ne, int64_t Na);
+panda_status panda_ws_features(panda_ctx* ctx, const float* omegaP, const float* omegaC, float* F,
+                               double* tau, void* workspace, size_t ws_bytes);
+
+/* The network: 16 -> 64 -> 64 -> 1, ReLU, parameters (FP32 master copy,
+ * PANDA_MLP_PARAMS floats, device) packed as W1[64][16], b1[64], W2[64][64]
+ * (out, in), b2[64], w3[64], b3.  Products take bf16-rounded weights and
+ * activations on matrix cores with FP32 accumulation.  forward: y[e] for the
+ * n rows of F (n x 16).  grad: gradient (PANDA_MLP_PARAMS floats, device) of
+ * the mean squared error of y against target over a batch of n rows (rows
+ * idx[e] of F / target when idx is given, indices outside [0, nrows) are
+ * skipped; rows 0..n-1 otherwise) and the loss (device double, may be NULL);
+ * in the backward pass dz2 and dz1 enter the products bf16-rounded.  adam: one
+ * Adam update at step >= 1 (m, v: FP32 moments, zero before step 1).
+ * train_step: grad then adam with beta1 0.9, beta2 0.999, eps 1e-8.  All
+ * enqueue on `stream` without synchronising. */
+panda_status panda_mlp_forward(const float* params, const float* F, int64_t n, float* y,
+                               hipStream_t stream);
+size_t panda_mlp_grad_workspace_bytes(int64_t n);
+panda_status panda_mlp_grad(const float* params, const float* F, int64_t nrows,
+                            const float* target, const int64_t* idx, int64_t n, float* grad,
+                            double* loss, void* workspace, size_t ws_bytes, hipStream_t stream);
+panda_status panda_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                            float lr, float beta1, float beta2, float eps, hipStream_t stream);
+panda_status panda_mlp_train_step(float* params, float* m, float* v, int32_t step, float lr,
+                                  const float* F, int64_t nrows, const float* target,
+                                  const int64_t* idx, int64_t n, float* grad, double* loss,
+                                  void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Target and prediction in the units above (rows x cols, row-major, device):
+ * out = (Wstar - W0) / tau and Wpred = W0 + tau * y. */
+panda_status panda_ws_target(const float* W0, const float* Wstar, int64_t rows, int64_t cols,
+                             double tau, float* out, hipStream_t stream);
+panda_status panda_ws_predict(const float* W0, const float* y, int64_t rows, int64_t cols,
+                              double tau, float* Wpred, hipStream_t stream);
+
+/* Warm state of a loaded context (its P and C diagonals are the priors'):
+ * W = Wpred (Ne x Na, device); P and C off-diagonals = T of the rows /
+ * columns of Wpred (the fixed point of Eq. 5 for this W); diagonals = t0
+ * steps of Eq. 6 in closed form with sigma held at the std of the rebuilt
+ * off-diagonal row, (1-a)^t0 d0 + f N sigma sum_{s<=t0} (1-a)^(t0-s) e^(2as);
+ * t = t0.  panda_iterate then continues from iteration t0 + 1.  Synchronises
+ * the stream. */
+panda_status panda_ws_init(panda_ctx* ctx, const float* Wpred, int32_t t0);
+
 const char* panda_status_string(panda_status s);
 const char* panda_last_error(void);
 

@@ -126,6 +126,16 @@ hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tsid
                             float* C, int64_t ldc, int64_t Na, const double2* cstat,
                             const double* csq, int64_t nslots, double* nC, Rule rule,
                             const DevState* st, hipStream_t s);
+// The same with the diagonal rule new = keep * old + f * N * sigma * g given
+// (closed form of several steps of Eq. 6).
+hipError_t launch_diagonals_schedule(float* P, int64_t ldp, int64_t Ne, const float* Tside,
+                                     double* nP, float* C, int64_t ldc, int64_t Na,
+                                     const double2* cstat, const double* csq, int64_t nslots,
+                                     double* nC, Rule rule, double keep, double g,
+                                     const DevState* st, hipStream_t s);
+// t, the gates, and the current-W selector back to buffer 0.
+hipError_t launch_state_set(DevState* st, int32_t t, int32_t active, int32_t run_pc,
+                            hipStream_t s);
 // Squared norms of the rows / columns of a rows x cols matrix with leading
 // dimension ld.  The column version needs kColChunks * cols doubles of scratch.
 hipError_t launch_row_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,

@@ -88,14 +88,17 @@ __device__ __forceinline__ void coop_finalize_entry(
   }
 }
 
-// Scalars of the diagonal rule (Eq. 6) at iteration t.
+// Scalars of the diagonal rule: new = keep * old + f * N * sigma * g.  One
+// step of Eq. 6 at iteration t: keep = 1 - alpha, g = exp(2 alpha t); f =
+// alpha (default reading) or 1 (literal).  The warm state uses the closed
+// form of t0 such steps with sigma held fixed (diag_schedule_host).
 struct DiagRule {
-  double alpha, g, f;  // g = exp(2 alpha t); f = alpha (default reading) or 1 (literal)
+  double keep, g, f;
   int32_t n_own;
 };
 __device__ __forceinline__ DiagRule diag_rule(double alpha, int32_t diag_alpha, int32_t n_own,
                                               int32_t t) {
-  return DiagRule{alpha, exp(2.0 * alpha * (double)t), diag_alpha ? alpha : 1.0, n_own};
+  return DiagRule{1.0 - alpha, exp(2.0 * alpha * (double)t), diag_alpha ? alpha : 1.0, n_own};
 }
 
 // Eq. 6 for row i of P (one block): population std of the off-diagonal
@@ -123,7 +126,7 @@ __device__ __forceinline__ void diag_p_row(int64_t i, float* __restrict__ P, int
   if (threadIdx.x == 0) {
     const double mult = dr.n_own ? (double)Ne : (double)Na;
     const double d = (double)P[i * ldp + i];
-    const float dn = (float)((1.0 - dr.alpha) * d + dr.f * mult * sqrt(var) * dr.g);
+    const float dn = (float)(dr.keep * d + dr.f * mult * sqrt(var) * dr.g);
     P[i * ldp + i] = dn;
     nP[i] = off2 + (double)dn * (double)dn;
   }
@@ -153,7 +156,7 @@ __device__ __forceinline__ void diag_c_row(int64_t r, float* __restrict__ C, int
   }
   const double mult = dr.n_own ? (double)Na : (double)Ne;
   const double d = (double)C[r * ldc + r];
-  const float dn = (float)((1.0 - dr.alpha) * d + dr.f * mult * sqrt(var) * dr.g);
+  const float dn = (float)(dr.keep * d + dr.f * mult * sqrt(var) * dr.g);
   C[r * ldc + r] = dn;
   nC[r] = c2 + (double)dn * (double)dn;
 }

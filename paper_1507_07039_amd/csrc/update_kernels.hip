@@ -34,10 +34,15 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     float* __restrict__ P, int64_t ldp, int64_t Ne, const float* __restrict__ Tside,
     double* __restrict__ nP, float* __restrict__ C, int64_t ldc, int64_t Na,
     const double2* __restrict__ cstat, const double* __restrict__ csq, int64_t nslots,
-    double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st) {
+    double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st,
+    int32_t sched, double keep, double g) {
   __shared__ double red[4];
   if (st->run_pc == 0) return;
-  const upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
+  upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
+  if (sched) {  // closed form of several steps (warm state)
+    dr.keep = keep;
+    dr.g = g;
+  }
   if ((int64_t)blockIdx.x < Ne) {
     upd::diag_p_row(blockIdx.x, P, ldp, Ne, Na, Tside, nP, dr, red);
     return;
@@ -194,6 +199,15 @@ __global__ __launch_bounds__(kRT) void k_fill_identity(float* __restrict__ M, in
   }
 }
 
+__global__ void k_state_set(DevState* st, int32_t t, int32_t active, int32_t run_pc) {
+  if (threadIdx.x == 0) {
+    st->t = t;
+    st->wsel = 0;
+    st->active = active;
+    st->run_pc = run_pc;
+  }
+}
+
 __global__ void k_state_init(DevState* st, int32_t t0) {
   if (threadIdx.x == 0) {
     st->h = 0.0;
@@ -251,7 +265,25 @@ hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tsid
   const int64_t nb = Ne + (Na + kRT - 1) / kRT;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, nP, C, ldc, Na, cstat, csq,
                                                  nslots, nC, rule.alpha, rule.diag_alpha,
-                                                 rule.n_own, st);
+                                                 rule.n_own, st, 0, 0.0, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagonals_schedule(float* P, int64_t ldp, int64_t Ne, const float* Tside,
+                                     double* nP, float* C, int64_t ldc, int64_t Na,
+                                     const double2* cstat, const double* csq, int64_t nslots,
+                                     double* nC, Rule rule, double keep, double g,
+                                     const DevState* st, hipStream_t s) {
+  const int64_t nb = Ne + (Na + kRT - 1) / kRT;
+  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, nP, C, ldc, Na, cstat, csq,
+                                                 nslots, nC, rule.alpha, rule.diag_alpha,
+                                                 rule.n_own, st, 1, keep, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_set(DevState* st, int32_t t, int32_t active, int32_t run_pc,
+                            hipStream_t s) {
+  k_state_set<<<1, 64, 0, s>>>(st, t, active, run_pc);
   return hipGetLastError();
 }
 

@@ -108,3 +108,10 @@ def batched_shapes(master_seed: int = 48, n: int = 48, t_range=(50, 700), g_rang
 def to_f32(*arrs):
     """Round FP64 arrays to FP32 (round-to-nearest-even), C-contiguous."""
     return tuple(np.ascontiguousarray(a, dtype=np.float32) for a in arrs)
+
+
+def sketch_matrices(seed: int, Ne: int, Na: int, k: int = 6):
+    """Gaussian sketch matrices (Ne x k, Na x k, FP32) of the warm-start features."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (np.ascontiguousarray(rng.standard_normal((Ne, k)), dtype=np.float32),
+            np.ascontiguousarray(rng.standard_normal((Na, k)), dtype=np.float32))

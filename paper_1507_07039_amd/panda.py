@@ -28,8 +28,13 @@ EXPORTS = (
     "panda_batch_tile_candidates", "panda_batch_get_tiles", "panda_batch_set_tiles",
     "panda_batch_autotune", "panda_batch_load", "panda_batch_iterate", "panda_batch_run",
     "panda_batch_state", "panda_batch_store",
+    "panda_ws_features_workspace_bytes", "panda_ws_features", "panda_mlp_forward",
+    "panda_mlp_grad_workspace_bytes", "panda_mlp_grad", "panda_mlp_adam", "panda_mlp_train_step",
+    "panda_ws_target", "panda_ws_predict", "panda_ws_init",
     "panda_status_string", "panda_last_error",
 )
+
+WS_FEATURES, WS_SKETCH, MLP_PARAMS = 16, 6, 5313
 
 BATCH_TILES = ("R", "A+W", "P-partial", "C")
 
@@ -94,6 +99,18 @@ def load_library(path: str = LIB_PATH):
         "panda_batch_state": (ct.c_int, [vp, i32, ct.POINTER(dbl), ct.POINTER(i32),
                                          ct.POINTER(i32)]),
         "panda_batch_store": (ct.c_int, [vp, i32, vp, vp, vp, ct.POINTER(dbl), ct.POINTER(i32)]),
+        "panda_ws_features_workspace_bytes": (sz, [i64, i64]),
+        "panda_ws_features": (ct.c_int, [vp, vp, vp, vp, ct.POINTER(dbl), vp, sz]),
+        "panda_mlp_forward": (ct.c_int, [vp, vp, i64, vp, vp]),
+        "panda_mlp_grad_workspace_bytes": (sz, [i64]),
+        "panda_mlp_grad": (ct.c_int, [vp, vp, i64, vp, vp, i64, vp, vp, vp, sz, vp]),
+        "panda_mlp_adam": (ct.c_int, [vp, vp, vp, vp, i32, ct.c_float, ct.c_float, ct.c_float,
+                                      ct.c_float, vp]),
+        "panda_mlp_train_step": (ct.c_int, [vp, vp, vp, i32, ct.c_float, vp, i64, vp, vp, i64, vp,
+                                            vp, vp, sz, vp]),
+        "panda_ws_target": (ct.c_int, [vp, vp, i64, i64, dbl, vp, vp]),
+        "panda_ws_predict": (ct.c_int, [vp, vp, i64, i64, dbl, vp, vp]),
+        "panda_ws_init": (ct.c_int, [vp, vp, i32]),
         "panda_status_string": (ct.c_char_p, [ct.c_int]),
         "panda_last_error": (ct.c_char_p, []),
     }
@@ -225,6 +242,21 @@ class Context:
         cnt = (ct.c_int64 * n)()
         _check(self.lib.panda_ctx_phase_times(self.h, ms, cnt))
         return {PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def features(self, omegaP, omegaC):
+        """Warm-start features of the loaded priors: (F (Ne*Na x 16), tau)."""
+        torch = _torch()
+        F = torch.empty((self.Ne * self.Na, WS_FEATURES), dtype=torch.float32, device="cuda")
+        ws = workspace(self.lib.panda_ws_features_workspace_bytes(self.Ne, self.Na))
+        tau = ct.c_double()
+        _check(self.lib.panda_ws_features(self.h, _dev(omegaP, "omegaP", (self.Ne, WS_SKETCH)),
+                                          _dev(omegaC, "omegaC", (self.Na, WS_SKETCH)),
+                                          F.data_ptr(), ct.byref(tau), ws.data_ptr(), ws.numel()))
+        return F, tau.value
+
+    def ws_init(self, Wpred, t0: int):
+        """Warm state around a predicted W at iteration t0 (panda_ws_init)."""
+        _check(self.lib.panda_ws_init(self.h, _dev(Wpred, "Wpred", (self.Ne, self.Na)), int(t0)))
 
     def state(self):
         torch = _torch()
@@ -386,3 +418,64 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------- warm start ---
+
+def mlp_forward(params, F):
+    """y for every row of F (panda_mlp_forward)."""
+    torch = _torch()
+    n = F.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(load_library().panda_mlp_forward(_dev(params, "params", (MLP_PARAMS,)),
+                                            _dev(F, "F", (n, WS_FEATURES)), n, y.data_ptr(),
+                                            _stream()))
+    return y
+
+
+def mlp_grad(params, F, target, idx=None, n=None, ws=None):
+    """(gradient, loss as a device double) of the MSE over a batch (panda_mlp_grad)."""
+    torch = _torch()
+    lib = load_library()
+    nrows = F.shape[0]
+    if idx is not None:
+        if idx.dtype != torch.int64 or not idx.is_cuda or not idx.is_contiguous():
+            raise TypeError("idx must be a contiguous int64 tensor on the GPU")
+        n = idx.numel() if n is None else n
+    n = nrows if n is None else n
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    if ws is None:
+        ws = workspace(lib.panda_mlp_grad_workspace_bytes(n))
+    _check(lib.panda_mlp_grad(_dev(params, "params", (MLP_PARAMS,)), _dev(F, "F", (nrows, WS_FEATURES)),
+                              nrows, _dev(target, "target", (nrows,)),
+                              None if idx is None else idx.data_ptr(), n, grad.data_ptr(),
+                              loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return grad, loss
+
+
+def mlp_adam(params, m, v, grad, step: int, lr: float = 1e-3, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update of params in place (panda_mlp_adam)."""
+    _check(load_library().panda_mlp_adam(
+        _dev(params, "params", (MLP_PARAMS,)), _dev(m, "m", (MLP_PARAMS,)),
+        _dev(v, "v", (MLP_PARAMS,)), _dev(grad, "grad", (MLP_PARAMS,)), int(step), lr, beta1,
+        beta2, eps, _stream()))
+
+
+def ws_target(W0, Wstar, tau: float):
+    torch = _torch()
+    rows, cols = W0.shape
+    out = torch.empty_like(W0)
+    _check(load_library().panda_ws_target(_dev(W0, "W0"), _dev(Wstar, "Wstar", (rows, cols)),
+                                          rows, cols, float(tau), out.data_ptr(), _stream()))
+    return out
+
+
+def ws_predict(W0, y, tau: float):
+    torch = _torch()
+    rows, cols = W0.shape
+    out = torch.empty_like(W0)
+    _check(load_library().panda_ws_predict(_dev(W0, "W0"), _dev(y, "y"), rows, cols, float(tau),
+                                           out.data_ptr(), _stream()))
+    return out
