@@ -62,7 +62,9 @@ typedef enum {
  *                      hi*hi + hi*lo + lo*hi on bf16 matrix cores with FP32
  *                      accumulation; the diagonals of P and C are kept out
  *                      of the split operands and their terms added in FP64.
- *                      Needs about twice the workspace of C. */
+ *                      C stays FP32 (split while it is staged for the
+ *                      products); the extra workspace is the hi/lo planes of
+ *                      W (two layouts) and P, about 4 * Ne * Na * 2 bytes. */
 enum { PANDA_PREC_FP32 = 0, PANDA_PREC_BF16X3 = 1 };
 
 /* Run parameters and the readings of the paper where it is ambiguous.

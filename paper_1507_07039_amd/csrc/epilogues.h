@@ -72,6 +72,7 @@ struct EpiWUpdate {
 // to 704 = 11 x 64), 4 waves side by side.  Symmetric C product: 128 x 128.
 using RectF32 = BlockGemm<64, 128, 1, 4, true, false, 16>;
 using RectB3 = BlockGemmB3<64, 128, 1, 4>;
+using RectB3F = BlockGemmB3<64, 128, 1, 4, 32, true>;  // Y = FP32 C, split while staged
 using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
 using SymB3 = BlockGemmB3<128, 128, 2, 2>;
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;

@@ -14,6 +14,8 @@
 // the remainder split stream-K style), described at k_rect_streamk.
 #pragma once
 
+#include <type_traits>
+
 #include "panda_internal.h"
 
 namespace panda {
@@ -150,6 +152,7 @@ template <int BM_, int BN_, int WM, int WN, bool XK, bool YK, int BK_>
 struct BlockGemm {
   using Ops = OpsF32;
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = kThreads;
+  static constexpr int WAVES_PER_EU = 1;  // occupancy asked of the compiler (1: no request)
   static_assert(WM * WN == 4, "four waves per block");
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
@@ -260,6 +263,15 @@ struct OpsB3 {
   const bf16_t* Yl;
   int64_t ldy;
 };
+// The same with Y an FP32 symmetric matrix (Yt = Y, rows read K-contiguous)
+// that is split into hi/lo while it is staged, its diagonal set to zero.
+struct OpsB3F {
+  const bf16_t* Xh;
+  const bf16_t* Xl;
+  int64_t ldx;
+  const float* Y;
+  int64_t ldy;
+};
 
 // MN x BK tile of one K-contiguous operand, both planes, loaded by NT
 // threads.  LDS rows are BK bf16 (chunks of 8 bf16 = 16 B) with the chunk
@@ -304,25 +316,90 @@ struct TileLoadB3 {
   }
 };
 
+// MN x BK tile of a K-contiguous FP32 operand (row mn = mn0 + r holds k
+// values k0..), split into the two planes of the TileLoadB3 layout when it is
+// written to LDS; entries with mn == k (the diagonal of a square symmetric
+// operand) become zero, so that term can be added back in FP64.
+template <int MN, int NT, int BK_>
+struct TileLoadB3F {
+  using Planes = TileLoadB3<MN, NT, BK_>;
+  static constexpr int BK = BK_, CPR = Planes::CPR, RP = Planes::RP, NV = Planes::NV;
+  static constexpr bool ALL = Planes::ALL;
+  static constexpr int PLANE = Planes::PLANE;
+  __device__ __forceinline__ static int swz(int row, int chunk) { return Planes::swz(row, chunk); }
+
+  f4 a[NV], b[NV];
+  int64_t mn0, k0;
+
+  __device__ __forceinline__ void load(const float* __restrict__ M, int64_t ld, int64_t mn0_,
+                                       int64_t k0_, int t) {
+    mn0 = mn0_;
+    k0 = k0_;
+    if (!ALL && t >= MN * CPR) return;
+    const int c = (t % CPR) * 8;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int r = t / CPR + i * RP;
+      const float* p = M + (mn0 + r) * ld + k0 + c;
+      a[i] = *reinterpret_cast<const f4*>(p);
+      b[i] = *reinterpret_cast<const f4*>(p + 4);
+    }
+  }
+  __device__ __forceinline__ void store(bf16_t* lds, int t) const {
+    if (!ALL && t >= MN * CPR) return;
+    const int c = t % CPR;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int r = t / CPR + i * RP;
+      float v[8] = {a[i].x, a[i].y, a[i].z, a[i].w, b[i].x, b[i].y, b[i].z, b[i].w};
+      const int64_t d = mn0 + r - (k0 + 8 * c);  // position of the diagonal in this chunk
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (d == e) v[e] = 0.0f;
+      unsigned hw[4], lw[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        bf16_t h0, l0, h1, l1;
+        split_bf16(v[2 * e], h0, l0);
+        split_bf16(v[2 * e + 1], h1, l1);
+        hw[e] = (unsigned)h0 | ((unsigned)h1 << 16);
+        lw[e] = (unsigned)l0 | ((unsigned)l1 << 16);
+      }
+      const int off = Planes::swz(r, c);
+      *reinterpret_cast<u4*>(lds + off) = u4{hw[0], hw[1], hw[2], hw[3]};
+      *reinterpret_cast<u4*>(lds + PLANE + off) = u4{lw[0], lw[1], lw[2], lw[3]};
+    }
+  }
+};
+
 // Block-level split-BF16 GEMM, WM x WN waves of (BM/WM) x (BN/WN) each.
 // All fragments of a K-tile are read from LDS before its MFMAs are issued,
 // so the LDS latency is paid once per tile rather than once per 16-k step.
-template <int BM_, int BN_, int WM, int WN, int BK_ = 32>
+template <int BM_, int BN_, int WM, int WN, int BK_ = 32, bool YF32 = false, int WPE = 1>
 struct BlockGemmB3 {
-  using Ops = OpsB3;
+  using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
+  static constexpr int WAVES_PER_EU = WPE;  // occupancy asked of the compiler (1: no request)
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
   static constexpr int KS = BK / 16;  // MFMA k-steps per K-tile
   static_assert(TM >= 1 && TN >= 1, "wave tile below one MFMA block");
   using LX = TileLoadB3<BM, NT, BK>;
-  using LY = TileLoadB3<BN, NT, BK>;
+  using LY = typename std::conditional<YF32, TileLoadB3F<BN, NT, BK>, TileLoadB3<BN, NT, BK>>::type;
   static constexpr int XS = 2 * LX::PLANE;  // bf16 per stage
   static constexpr int YS = 2 * LY::PLANE;
   static constexpr int MAIN_BYTES = 2 * (XS + YS) * 2;
 
   floatx16 acc[TM][TN];
   int lane, wm, wn;
+
+  __device__ __forceinline__ static void load_y(LY& ly, const Ops& o, int64_t n0, int64_t k0,
+                                                int t) {
+    if constexpr (YF32)
+      ly.load(o.Y, o.ldy, n0, k0, t);
+    else
+      ly.load(o.Yh, o.Yl, o.ldy, n0, k0, t);
+  }
 
   __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
                                       int64_t kend, char* smem) {
@@ -344,7 +421,7 @@ struct BlockGemmB3 {
     const int64_t nk = (kend - kbeg) / BK;
     if (nk > 0) {
       lx.load(o.Xh, o.Xl, o.ldx, m0, kbeg, t);
-      ly.load(o.Yh, o.Yl, o.ldy, n0, kbeg, t);
+      load_y(ly, o, n0, kbeg, t);
       lx.store(xs, t);
       ly.store(ys, t);
     }
@@ -357,7 +434,7 @@ struct BlockGemmB3 {
       const bool more = kt + 1 < nk;
       if (more) {
         lx.load(o.Xh, o.Xl, o.ldx, m0, kbeg + (kt + 1) * BK, t);
-        ly.load(o.Yh, o.Yl, o.ldy, n0, kbeg + (kt + 1) * BK, t);
+        load_y(ly, o, n0, kbeg + (kt + 1) * BK, t);
       }
       const bf16_t* xc = xs + cur * XS;
       const bf16_t* yc = ys + cur * YS;
@@ -442,7 +519,8 @@ __device__ __forceinline__ int64_t sk_owner(int64_t i, int64_t total, int64_t G)
 constexpr int64_t kTailSplit = 4;
 
 template <class G, class Epi>
-__global__ __launch_bounds__(G::NT) void k_rect_streamk(typename G::Ops ops, int64_t nMT,
+__global__ __launch_bounds__(G::NT) __attribute__((amdgpu_waves_per_eu(G::WAVES_PER_EU)))
+void k_rect_streamk(typename G::Ops ops, int64_t nMT,
                                                         int64_t nTiles, int64_t U, int64_t nbt,
                                                         Epi epi, float* __restrict__ part,
                                                         const int32_t* gate) {

@@ -85,7 +85,7 @@ struct panda_ctx {
   uint32_t* corder;  // launch order of the upper C tiles
   panda::DevState* st;
   bool b3;  // split-BF16 products
-  panda::bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl, *Ch, *Cl;
+  panda::bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl;  // split planes (C stays FP32)
   panda::DevState* host;  // pinned
   int splits;
   int64_t nh;

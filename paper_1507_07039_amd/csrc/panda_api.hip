@@ -94,7 +94,7 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   DevState* st = cv.take<DevState>(1);
   // split-BF16 operand planes
   const bool b3 = precision == PANDA_PREC_BF16X3;
-  bf16_t* sh[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bf16_t* sh[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (b3) {
     sh[0] = cv.take<bf16_t>(nw);                   // W hi, row-major
     sh[1] = cv.take<bf16_t>(nw);                   // W lo
@@ -102,8 +102,6 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
     sh[3] = cv.take<bf16_t>(nw);                   // W^T lo
     sh[4] = cv.take<bf16_t>((size_t)Nep * Nep);    // P hi, zero diagonal
     sh[5] = cv.take<bf16_t>((size_t)Nep * Nep);    // P lo
-    sh[6] = cv.take<bf16_t>((size_t)Nap * Nap);    // C hi, zero diagonal
-    sh[7] = cv.take<bf16_t>((size_t)Nap * Nap);    // C lo
   }
   if (c) {
     c->Nep = Nep;
@@ -136,8 +134,6 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
     c->Wtl = sh[3];
     c->Ph = sh[4];
     c->Pl = sh[5];
-    c->Ch = sh[6];
-    c->Cl = sh[7];
   }
   return cv.off;
 }
@@ -244,7 +240,7 @@ panda_status enqueue_iteration(panda_ctx* c) {
   PANDA_TRY(mark(c, PANDA_PHASE_AW));
   // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
   if (c->b3)
-    HIP_TRY(launch_avail_wupdate_b3(c->Wh, c->Wl, c->Ch, c->Cl, Wold, c->C, c->R, Wnew, c->Nap,
+    HIP_TRY(launch_avail_wupdate_b3(c->Wh, c->Wl, Wold, c->C, c->R, Wnew, c->Nap,
                                     c->Nep, c->Nap, c->Ne, c->Na, c->nWr, c->nC, c->rule,
                                     c->hpart, c->skpart, active, s));
   else
@@ -272,7 +268,7 @@ panda_status enqueue_iteration(panda_ctx* c) {
   PANDA_TRY(mark(c, PANDA_PHASE_C));
   // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
   if (c->b3)
-    HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Ch, c->Cl, c->Nap,
+    HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Nap,
                                    c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder,
                                    run_pc, s));
   else
@@ -507,11 +503,8 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
     HIP_TRY(hipMemsetAsync(c->Wtl, 0, nw * 2, s));
     HIP_TRY(hipMemsetAsync(c->Ph, 0, (size_t)Nep * Nep * 2, s));
     HIP_TRY(hipMemsetAsync(c->Pl, 0, (size_t)Nep * Nep * 2, s));
-    HIP_TRY(hipMemsetAsync(c->Ch, 0, (size_t)Nap * Nap * 2, s));
-    HIP_TRY(hipMemsetAsync(c->Cl, 0, (size_t)Nap * Nap * 2, s));
     HIP_TRY(launch_w_shadows(c->W[0], Ne, Na, Nap, c->Wh, c->Wl, c->Wth, c->Wtl, Nep, nullptr, s));
     HIP_TRY(launch_split_offdiag(c->P, Ne, Nep, c->Ph, c->Pl, s));
-    HIP_TRY(launch_split_offdiag(c->C, Na, Nap, c->Ch, c->Cl, s));
   }
   PANDA_TRY(ctx_fill_order(c));
   HIP_TRY(launch_state_init(c->st, t, s));

@@ -87,23 +87,24 @@ hipError_t launch_coop_partial(const float* W, int64_t ldw, int64_t Nep, int64_t
 int coop_splits(int64_t Nep, int64_t Nap);
 
 // Split-BF16 forms of the same products.  Operands are K-contiguous hi/lo
-// planes: P (diagonal zero), W row-major, W^T (gene-major), C (diagonal zero).
+// planes: P (diagonal zero), W row-major, W^T (gene-major); C stays FP32.
 hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const bf16_t* Wth,
                           const bf16_t* Wtl, int64_t ldwt, int64_t Nep, int64_t Nap, int64_t Ne,
                           int64_t Na, const float* P, const float* W, int64_t ldw,
                           const double* nP, const double* nWc, float* R, float* part,
                           const int32_t* gate, hipStream_t s);
-hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const bf16_t* Ch,
-                                   const bf16_t* Cl, const float* Wold, const float* C,
-                                   const float* R, float* Wnew, int64_t ld, int64_t Nep,
-                                   int64_t Nap, int64_t Ne, int64_t Na, const double* nWrow,
-                                   const double* nC, Rule rule, double* hpart, float* part,
-                                   const int32_t* gate, hipStream_t s);
+// A = T(W, C) + W update with X = the W planes and Y = the FP32 C itself
+// (symmetric; split into hi/lo while staged, its diagonal peeled).
+hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const float* Wold,
+                                   const float* C, const float* R, float* Wnew, int64_t ld,
+                                   int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
+                                   const double* nWrow, const double* nC, Rule rule,
+                                   double* hpart, float* part, const int32_t* gate,
+                                   hipStream_t s);
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
-                                  float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
-                                  int64_t Na, const double* nWcol, Rule rule, double2* cstat,
-                                  double* csq, const uint32_t* order, const int32_t* gate,
-                                  hipStream_t s);
+                                  float* C, int64_t ldc, int64_t Nap, int64_t Na,
+                                  const double* nWcol, Rule rule, double2* cstat, double* csq,
+                                  const uint32_t* order, const int32_t* gate, hipStream_t s);
 hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ldw, int64_t Nep,
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s);

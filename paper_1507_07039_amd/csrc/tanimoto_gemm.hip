@@ -96,15 +96,16 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* 
   return launch_rect<RectF32>(OpsF32{Wold, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
 }
 
-hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const bf16_t* Ch,
-                                   const bf16_t* Cl, const float* Wold, const float* C,
-                                   const float* R, float* Wnew, int64_t ld, int64_t Nep,
-                                   int64_t Nap, int64_t Ne, int64_t Na, const double* nWrow,
-                                   const double* nC, Rule rule, double* hpart, float* part,
-                                   const int32_t* gate, hipStream_t s) {
+hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const float* Wold,
+                                   const float* C, const float* R, float* Wnew, int64_t ld,
+                                   int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
+                                   const double* nWrow, const double* nC, Rule rule,
+                                   double* hpart, float* part, const int32_t* gate,
+                                   hipStream_t s) {
   EpiWUpdate epi{Wold, R,       Wnew,       ld,  Ne,  Na, nWrow, nC, C, ld, rule.alpha,
                  rule.h_undamped, hpart, 0.0};
-  return launch_rect<RectB3>(OpsB3{Wh, Wl, ld, Ch, Cl, ld}, Nep, Nap, Nap, epi, part, gate, s);
+  // C is symmetric: its row n is the column n the product needs
+  return launch_rect<RectB3F>(OpsB3F{Wh, Wl, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
 }
 
 int64_t coreg_slots(int64_t Nap) { return Nap / kCB; }
@@ -147,13 +148,13 @@ hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* 
 }
 
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
-                                  float* C, bf16_t* Ch, bf16_t* Cl, int64_t ldc, int64_t Nap,
-                                  int64_t Na, const double* nWcol, Rule rule, double2* cstat,
-                                  double* csq, const uint32_t* order, const int32_t* gate,
-                                  hipStream_t s) {
-  // X = Yt = W^T stored gene-major: row m of W^T is column m of W.
+                                  float* C, int64_t ldc, int64_t Nap, int64_t Na,
+                                  const double* nWcol, Rule rule, double2* cstat, double* csq,
+                                  const uint32_t* order, const int32_t* gate, hipStream_t s) {
+  // X = Yt = W^T stored gene-major: row m of W^T is column m of W.  Only the
+  // FP32 C is written; the next A product splits it while staging.
   return coreg_launch<SymB3>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol,
-                             rule, cstat, csq, Ch, Cl, order, gate, s);
+                             rule, cstat, csq, nullptr, nullptr, order, gate, s);
 }
 
 int coop_splits(int64_t Nep, int64_t Nap) {

@@ -200,7 +200,7 @@ panda_status panda_ws_init(panda_ctx* c, const float* Wpred, int32_t t0) {
   HIP_TRY(launch_coop_finalize(c->ppart, c->splits, Nep, c->nWr, c->P, Nep, Ne, r1,
                                c->rule.sigma_from_T ? c->Tside : nullptr, c->Ph, c->Pl, run_pc, s));
   if (c->b3)
-    HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, Nep, Nep, c->C, c->Ch, c->Cl, Nap, Nap, Na,
+    HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, Nep, Nep, c->C, Nap, Nap, Na,
                                    c->nWc, r1, c->cstat, c->csq, c->corder, run_pc, s));
   else
     HIP_TRY(launch_coreg_update(W, Nap, Nep, c->C, Nap, Nap, Na, c->nWc, r1, c->cstat, c->csq,
