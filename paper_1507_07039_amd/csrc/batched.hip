@@ -57,8 +57,10 @@ struct PhResp {
     const int64_t nMT = d.Nep / G::BM;
     const int64_t m0 = (local % nMT) * G::BM, n0 = (local / nMT) * G::BN;
     G g;
-    g.run(OpsF32{d.P, d.Nep, W, d.Nap}, m0, n0, 0, d.Nep, smem);
-    EpiStoreT epi{d.R, d.Nap, d.Ne, d.Na, d.nP, d.nWc, nullptr, 0, nullptr, 0};
+    OpsF32 ops{d.P, d.Nep, W, d.Nap};
+    ops.xdiag = 1;  // P's diagonal is added in FP64 by the epilogue
+    g.run(ops, m0, n0, 0, d.Nep, smem);
+    EpiStoreT epi{d.R, d.Nap, d.Ne, d.Na, d.nP, d.nWc, d.P, d.Nep, W, d.Nap};
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
   }
 };
@@ -80,9 +82,11 @@ struct PhAvail {
     const int64_t nMT = d.Nep / G::BM;
     const int64_t m0 = (local % nMT) * G::BM, n0 = (local / nMT) * G::BN;
     G g;
-    g.run(OpsF32{Wold, d.Nap, d.C, d.Nap}, m0, n0, 0, d.Nap, smem);
+    OpsF32 ops{Wold, d.Nap, d.C, d.Nap};
+    ops.ydiag = 1;  // C's diagonal is added in FP64 by the epilogue
+    g.run(ops, m0, n0, 0, d.Nap, smem);
     EpiWUpdate epi{Wold,  d.R,   d.W[ws ^ 1], d.Nap,      d.Ne,    d.Na, d.nWr,
-                   d.nC,  nullptr, 0,         alpha,      h_undamped, d.hpart, 0.0};
+                   d.nC,  d.C,   d.Nap,       alpha,      h_undamped, d.hpart, 0.0};
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
     epi.end_tile(local, red);
   }

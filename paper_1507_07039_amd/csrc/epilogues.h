@@ -73,6 +73,10 @@ struct EpiWUpdate {
 using RectF32 = BlockGemm<64, 128, 1, 4, true, false, 16>;
 using RectB3 = BlockGemmB3<64, 128, 1, 4>;
 using RectB3F = BlockGemmB3<64, 128, 1, 4, 32, true>;  // Y = FP32 C, split while staged
+#ifndef PANDA_B3D_WN
+#define PANDA_B3D_WN 2
+#endif
+using RectB3D = BlockGemmB3D<64, 128, 1, PANDA_B3D_WN, 3, true>;  // the same, direct-to-LDS pipeline
 using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
 using SymB3 = BlockGemmB3<128, 128, 2, 2>;
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;

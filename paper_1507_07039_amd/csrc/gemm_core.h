@@ -114,6 +114,30 @@ struct TileLoad {
     }
   }
 
+  // Zero the entries with global mn == k (the diagonal of a square operand)
+  // when the tile [mn0, mn0 + MN) x [k0, k0 + BK) meets it.
+  __device__ __forceinline__ void zero_diagonal(int64_t mn0, int64_t k0, int t) {
+    if (!(mn0 < k0 + BK && k0 < mn0 + MN)) return;  // the same for the whole block
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int64_t mn, k;
+      int64_t d;  // position of the diagonal among the four values, if any
+      if constexpr (KC) {
+        mn = mn0 + t / KQ + i * RP;
+        k = k0 + (t % KQ) * 4;
+        d = mn - k;
+      } else {
+        k = k0 + t / TPR + i * RPP;
+        mn = mn0 + (t % TPR) * 4;
+        d = k - mn;
+      }
+      if (d == 0) v[i].x = 0.0f;
+      if (d == 1) v[i].y = 0.0f;
+      if (d == 2) v[i].z = 0.0f;
+      if (d == 3) v[i].w = 0.0f;
+    }
+  }
+
   __device__ __forceinline__ void store(float* lds, int t) const {
     if constexpr (KC) {
       const int kq = (t % KQ) * 4;
@@ -137,12 +161,17 @@ struct TileLoad {
 };
 
 // FP32 operands: X element (m, k) = XK ? X[m*ldx + k] : X[k*ldx + m];
-// Y element (k, n) = YK ? Y[n*ldy + k] : Y[k*ldy + n].
+// Y element (k, n) = YK ? Y[n*ldy + k] : Y[k*ldy + n].  With xdiag / ydiag
+// set, the diagonal (m == k, resp. k == n) of that square operand enters the
+// product as zero; the epilogue adds its term in FP64 (the diagonals of P and
+// C grow like exp(2 alpha t), Eq. 6, and would swamp an FP32 accumulator).
 struct OpsF32 {
   const float* X;
   int64_t ldx;
   const float* Y;
   int64_t ldy;
+  int32_t xdiag = 0;
+  int32_t ydiag = 0;
 };
 
 // Block-level FP32 GEMM over k in [kbeg, kend) for a BM x BN tile with WM x WN
@@ -188,6 +217,8 @@ struct BlockGemm {
     if (nk > 0) {
       lx.load(o.X, o.ldx, m0, kbeg, t);
       ly.load(o.Y, o.ldy, n0, kbeg, t);
+      if (o.xdiag) lx.zero_diagonal(m0, kbeg, t);
+      if (o.ydiag) ly.zero_diagonal(n0, kbeg, t);
       lx.store(xs, t);
       ly.store(ys, t);
     }
@@ -220,6 +251,8 @@ struct BlockGemm {
         __builtin_amdgcn_iglp_opt(0);  // interleave LDS reads with the MFMAs
       }
       if (more) {
+        if (o.xdiag) lx.zero_diagonal(m0, kbeg + (kt + 1) * BK, t);
+        if (o.ydiag) ly.zero_diagonal(n0, kbeg + (kt + 1) * BK, t);
         lx.store(xs + (cur ^ 1) * XS, t);
         ly.store(ys + (cur ^ 1) * YS, t);
       }
@@ -471,6 +504,265 @@ struct BlockGemmB3 {
       }
       __syncthreads();
     }
+  }
+
+  __device__ __forceinline__ int row_of(int i, int r) const {
+    return wm * (BM / WM) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  }
+  __device__ __forceinline__ int col_of(int j) const {
+    return wn * (BN / WN) + j * 32 + (lane & 31);
+  }
+  template <class F>
+  __device__ __forceinline__ void for_each(F&& f) const {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int c = col_of(j);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) f(row_of(i, r), c, acc[i][j][r]);
+      }
+  }
+};
+
+// ============================================ pipelined split-BF16 loop ==
+// The same products with the operand tiles moved by direct global -> LDS
+// loads (global_load_lds_dwordx4: lane l of a wave writes its 16 bytes at
+// LDS base + 16 l), so STAGES - 1 K-tiles are in flight without holding
+// registers.  Which global chunk each lane fetches is chosen so that the LDS
+// image is the swizzled layout the fragment reads want:
+//   bf16 planes: rows of BK bf16, slot s of row r holds chunk s ^ f(r) (as
+//     TileLoadB3);
+//   FP32 rows (Y = a symmetric FP32 matrix, split at fragment-read time with
+//     its diagonal zeroed): rows of BK floats = BK/4 chunks, slot s of row r
+//     holds chunk s ^ (r % 8).
+typedef __attribute__((address_space(3))) void* lds_vptr;
+typedef __attribute__((address_space(1))) void* gbl_vptr;
+
+__device__ __forceinline__ void dma16(const void* g, void* lds) {
+  __builtin_amdgcn_global_load_lds((gbl_vptr)g, (lds_vptr)lds, 16, 0, 0);
+}
+
+// Wait until at most n vector-memory operations of this wave are pending
+// (gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14; exp and lgkm counts left at
+// their maxima, i.e. not waited for).
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int BM_, int BN_, int WM, int WN, int STAGES, bool YF32>
+struct BlockGemmB3D {
+  using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
+  static constexpr int BM = BM_, BN = BN_, BK = 32, NT = 64 * WM * WN;
+  static constexpr int WAVES = WM * WN;
+  static constexpr int WAVES_PER_EU = 1;
+  static constexpr int TM = BM / WM / 32;
+  static constexpr int TN = BN / WN / 32;
+  static constexpr int KS = BK / 16;
+  static_assert(TM >= 1 && TN >= 1 && STAGES >= 2, "shape");
+  using PX = TileLoadB3<BM, NT, BK>;  // swizzle of the bf16 planes
+  using PY = TileLoadB3<BN, NT, BK>;
+  static constexpr int CPR = BK / 8;                        // 16-byte chunks per bf16 row
+  static constexpr int XQ = BM * CPR;                       // chunks per X plane
+  static constexpr int YQ = YF32 ? BN * (BK / 4) : BN * CPR;  // chunks per Y plane (1 or 2 planes)
+  static constexpr int YPLANES = YF32 ? 1 : 2;
+  static constexpr int STAGE_BYTES = (2 * XQ + YPLANES * YQ) * 16;
+  static constexpr int MAIN_BYTES = 16;  // the stages are run()'s own LDS objects
+  static constexpr int XI = 2 * XQ / 64, YI = YPLANES * YQ / 64;  // wave-instructions per stage
+  static_assert((2 * XQ) % 64 == 0 && (YPLANES * YQ) % 64 == 0, "whole wave loads");
+  static_assert((XI + YI) % WAVES == 0, "loads split evenly over the waves");
+  static constexpr int IPW = (XI + YI) / WAVES;  // loads per wave and stage
+
+  floatx16 acc[TM][TN];
+  int lane, wm, wn;
+
+  // Issue the loads of K-tile k0 into stage buffer st (this wave's share).
+  __device__ __forceinline__ void issue(const Ops& o, int64_t m0, int64_t n0, int64_t k0,
+                                       char* st, int w) const {
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) {
+      const int ins = w + q * WAVES;  // wave-instruction index within the stage
+      const int pos = (ins % (XI + YI) < XI ? ins : ins - XI) * 64 + lane;
+      if (ins < XI) {
+        const int plane = pos / XQ, p = pos % XQ;
+        const int r = p / CPR, slot = p % CPR;
+        const int chunk = slot ^ ((r / PX::RG) & (CPR - 1));
+        const bf16_t* src = (plane ? o.Xl : o.Xh) + (m0 + r) * o.ldx + k0 + chunk * 8;
+        dma16(src, st + (size_t)ins * 1024);
+      } else {
+        char* dst = st + 2 * XQ * 16 + (size_t)(ins - XI) * 1024;
+        if constexpr (YF32) {
+          const int r = pos / (BK / 4), slot = pos % (BK / 4);
+          const int chunk = slot ^ (r & 7);
+          dma16(o.Y + (n0 + r) * o.ldy + k0 + chunk * 4, dst);
+        } else {
+          const int plane = pos / YQ, p = pos % YQ;
+          const int r = p / CPR, slot = p % CPR;
+          const int chunk = slot ^ ((r / PY::RG) & (CPR - 1));
+          dma16((plane ? o.Yl : o.Yh) + (n0 + r) * o.ldy + k0 + chunk * 8, dst);
+        }
+      }
+    }
+  }
+
+  template <int N>
+  __device__ __forceinline__ static void wait_ahead(int ahead) {
+    // pending loads allowed: `ahead` later stages of IPW loads each
+    if constexpr (N <= 0) {
+      wait_vmem<0>();
+    } else {
+      if (ahead >= N) {
+        wait_vmem<N * IPW>();
+      } else {
+        wait_ahead<N - 1>(ahead);
+      }
+    }
+  }
+
+  // LDS byte address of a generic pointer into shared memory.
+  __device__ __forceinline__ static unsigned lds_addr(const void* p) {
+    return (unsigned)(size_t)(const __attribute__((address_space(3))) char*)p;
+  }
+
+  __device__ __forceinline__ void compute(const char* st, int64_t n0, int64_t k0) {
+    static_assert(YF32 && KS == 2 && TM == 2 && (TN == 1 || TN == 2), "fragment reads written for these shapes");
+    constexpr int PER = 2 * TM + 2 * TN;  // fragments per k-step
+    constexpr int NR = KS * PER;
+    const int mrow = wm * (BM / WM) + (lane & 31);
+    const int khalf = lane >> 5;
+    const unsigned base = lds_addr(st);
+    const unsigned ybase = base + 2 * XQ * 16;
+    unsigned ad[NR];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int chunk = 2 * ks + khalf;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const unsigned off = 2u * PX::swz(mrow + i * 32, chunk);
+        ad[PER * ks + 2 * i] = base + off;
+        ad[PER * ks + 2 * i + 1] = base + 2u * BM * BK + off;
+      }
+      const int c0 = 4 * ks + 2 * khalf;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn * (BN / WN) + j * 32 + (lane & 31);
+        ad[PER * ks + 2 * TM + 2 * j] = ybase + 4u * (n * BK + ((c0 ^ (n & 7)) << 2));
+        ad[PER * ks + 2 * TM + 2 * j + 1] = ybase + 4u * (n * BK + (((c0 + 1) ^ (n & 7)) << 2));
+      }
+    }
+    // All reads of the K-tile in one block that waits for them before it
+    // ends, so no read is left in flight when its result is used.
+    u4 r[NR];
+    if constexpr (NR == 12) {
+      asm volatile(
+          "ds_read_b128 %0, %12\n\tds_read_b128 %1, %13\n\tds_read_b128 %2, %14\n\t"
+          "ds_read_b128 %3, %15\n\tds_read_b128 %4, %16\n\tds_read_b128 %5, %17\n\t"
+          "ds_read_b128 %6, %18\n\tds_read_b128 %7, %19\n\tds_read_b128 %8, %20\n\t"
+          "ds_read_b128 %9, %21\n\tds_read_b128 %10, %22\n\tds_read_b128 %11, %23\n\t"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+            "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11])
+          : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]), "v"(ad[6]),
+            "v"(ad[7]), "v"(ad[8]), "v"(ad[9]), "v"(ad[10]), "v"(ad[11]));
+    } else {
+      asm volatile(
+          "ds_read_b128 %0, %16\n\tds_read_b128 %1, %17\n\tds_read_b128 %2, %18\n\t"
+          "ds_read_b128 %3, %19\n\tds_read_b128 %4, %20\n\tds_read_b128 %5, %21\n\t"
+          "ds_read_b128 %6, %22\n\tds_read_b128 %7, %23\n\tds_read_b128 %8, %24\n\t"
+          "ds_read_b128 %9, %25\n\tds_read_b128 %10, %26\n\tds_read_b128 %11, %27\n\t"
+          "ds_read_b128 %12, %28\n\tds_read_b128 %13, %29\n\tds_read_b128 %14, %30\n\t"
+          "ds_read_b128 %15, %31\n\ts_waitcnt lgkmcnt(0)"
+          : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+            "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11]),
+            "=&v"(r[12]), "=&v"(r[13]), "=&v"(r[14]), "=&v"(r[15])
+          : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]), "v"(ad[6]),
+            "v"(ad[7]), "v"(ad[8]), "v"(ad[9]), "v"(ad[10]), "v"(ad[11]), "v"(ad[12]),
+            "v"(ad[13]), "v"(ad[14]), "v"(ad[15]));
+    }
+    bf16x8 xh[KS][TM], xl[KS][TM], yh[KS][TN], yl[KS][TN];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        xh[ks][i] = __builtin_bit_cast(bf16x8, r[PER * ks + 2 * i]);
+        xl[ks][i] = __builtin_bit_cast(bf16x8, r[PER * ks + 2 * i + 1]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const f4 a = __builtin_bit_cast(f4, r[PER * ks + 2 * TM + 2 * j]);
+        const f4 b = __builtin_bit_cast(f4, r[PER * ks + 2 * TM + 2 * j + 1]);
+        float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        const int n = wn * (BN / WN) + j * 32 + (lane & 31);
+        const int64_t d = n0 + n - (k0 + 16 * ks + 8 * khalf);  // diagonal position, if any
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (d == e) v[e] = 0.0f;
+          const __bf16 h = (__bf16)v[e];
+          yh[ks][j][e] = h;
+          yl[ks][j][e] = (__bf16)(v[e] - (float)h);
+        }
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ks][i], yl[ks][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ks][i], yh[ks][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ks][i], yh[ks][j], acc[i][j], 0, 0, 0);
+        }
+  }
+
+  // One K-tile step: wait for stage `cur`, release stage `nxt`, start its
+  // loads (tile kt + STAGES - 1), compute on `cur`.  Stages are distinct
+  // LDS objects so that the compiler can tell the loads in flight from the
+  // stage being read and does not wait for them.
+  __device__ __forceinline__ void step(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
+                                       int kt, int nk, char* cur, char* nxt, int w) {
+    const int ahead = nk - 1 - kt < STAGES - 2 ? nk - 1 - kt : STAGES - 2;
+    wait_ahead<STAGES - 2>(ahead);
+    // Every wave has waited for its own loads of stage kt; the barrier alone
+    // (no memory fence, which would wait for the later stages too) makes
+    // stage kt complete for all and stage kt-1 free (its reads fed MFMAs).
+    __builtin_amdgcn_s_barrier();
+    if (kt + STAGES - 1 < nk) issue(o, m0, n0, kbeg + (int64_t)(kt + STAGES - 1) * BK, nxt, w);
+    compute(cur, n0, kbeg + (int64_t)kt * BK);
+  }
+
+  __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
+                                      int64_t kend, char*) {
+    static_assert(STAGES == 3, "three stage buffers");
+    __shared__ __align__(16) char s0[STAGE_BYTES];
+    __shared__ __align__(16) char s1[STAGE_BYTES];
+    __shared__ __align__(16) char s2[STAGE_BYTES];
+    const int t = threadIdx.x;
+    lane = t & 63;
+    const int w = t >> 6;
+    wm = w % WM;
+    wn = w / WM;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int nk = (int)((kend - kbeg) / BK);
+    wait_vmem<0>();   // only this tile's loads are counted below
+    __syncthreads();  // the previous tile's reads of every stage are done
+    if (nk > 0) issue(o, m0, n0, kbeg, s0, w);
+    if (nk > 1) issue(o, m0, n0, kbeg + BK, s1, w);
+    int kt = 0;
+    for (; kt + 3 <= nk; kt += 3) {
+      step(o, m0, n0, kbeg, kt, nk, s0, s2, w);
+      step(o, m0, n0, kbeg, kt + 1, nk, s1, s0, w);
+      step(o, m0, n0, kbeg, kt + 2, nk, s2, s1, w);
+    }
+    if (kt < nk) step(o, m0, n0, kbeg, kt, nk, s0, s2, w);
+    if (kt + 1 < nk) step(o, m0, n0, kbeg, kt + 1, nk, s1, s0, w);
   }
 
   __device__ __forceinline__ int row_of(int i, int r) const {

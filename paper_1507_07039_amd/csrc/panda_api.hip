@@ -235,8 +235,8 @@ panda_status enqueue_iteration(panda_ctx* c) {
     HIP_TRY(launch_resp_b3(c->Ph, c->Pl, c->Nep, c->Wth, c->Wtl, c->Nep, c->Nep, c->Nap, c->Ne,
                            c->Na, c->P, Wold, c->Nap, c->nP, c->nWc, c->R, c->skpart, active, s));
   else
-    HIP_TRY(launch_tanimoto_store(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Nep, c->Ne, c->Na,
-                                  c->nP, c->nWc, c->R, c->Nap, c->skpart, active, s));
+    HIP_TRY(launch_resp(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Ne, c->Na, c->nP, c->nWc,
+                        c->R, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_AW));
   // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
   if (c->b3)

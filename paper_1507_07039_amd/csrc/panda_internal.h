@@ -57,7 +57,13 @@ hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, in
                                  const double* nx, const double* ny, float* Out, int64_t ldo,
                                  float* part, const int32_t* gate, hipStream_t s);
 
-// A = T(W, C) fused with the W update of Eq. 2 and per-tile h partials (Eq. 7).
+// R = T(P, W) of the iteration (Eq. 3): P's diagonal is added in FP64.
+hipError_t launch_resp(const float* P, int64_t ldp, const float* W, int64_t ldw, int64_t Nep,
+                       int64_t Nap, int64_t Ne, int64_t Na, const double* nP, const double* nWc,
+                       float* R, float* part, const int32_t* gate, hipStream_t s);
+
+// A = T(W, C) fused with the W update of Eq. 2 and per-tile h partials (Eq. 7);
+// C's diagonal is added in FP64.
 hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* R, float* Wnew,
                                 int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
                                 const double* nWrow, const double* nC, Rule rule, double* hpart,

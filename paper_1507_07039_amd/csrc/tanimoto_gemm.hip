@@ -78,6 +78,16 @@ hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, in
   return launch_rect<RectF32>(OpsF32{X, ldx, Y, ldy}, Mp, Np, Kp, epi, part, gate, s);
 }
 
+hipError_t launch_resp(const float* P, int64_t ldp, const float* W, int64_t ldw, int64_t Nep,
+                       int64_t Nap, int64_t Ne, int64_t Na, const double* nP, const double* nWc,
+                       float* R, float* part, const int32_t* gate, hipStream_t s) {
+  // P's diagonal is left out of the FP32 product and added in FP64
+  EpiStoreT epi{R, ldw, Ne, Na, nP, nWc, P, ldp, W, ldw};
+  OpsF32 ops{P, ldp, W, ldw};
+  ops.xdiag = 1;
+  return launch_rect<RectF32>(ops, Nep, Nap, Nep, epi, part, gate, s);
+}
+
 hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const bf16_t* Wth,
                           const bf16_t* Wtl, int64_t ldwt, int64_t Nep, int64_t Nap, int64_t Ne,
                           int64_t Na, const float* P, const float* W, int64_t ldw,
@@ -91,9 +101,12 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* 
                                 int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
                                 const double* nWrow, const double* nC, Rule rule, double* hpart,
                                 float* part, const int32_t* gate, hipStream_t s) {
-  EpiWUpdate epi{Wold, R,       Wnew,       ld,  Ne,  Na, nWrow, nC, nullptr, 0, rule.alpha,
+  // C's diagonal is left out of the FP32 product and added in FP64
+  EpiWUpdate epi{Wold, R,       Wnew,       ld,  Ne,  Na, nWrow, nC, C, ld, rule.alpha,
                  rule.h_undamped, hpart, 0.0};
-  return launch_rect<RectF32>(OpsF32{Wold, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
+  OpsF32 ops{Wold, ld, C, ld};
+  ops.ydiag = 1;
+  return launch_rect<RectF32>(ops, Nep, Nap, Nap, epi, part, gate, s);
 }
 
 hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const float* Wold,
@@ -105,7 +118,7 @@ hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const flo
   EpiWUpdate epi{Wold, R,       Wnew,       ld,  Ne,  Na, nWrow, nC, C, ld, rule.alpha,
                  rule.h_undamped, hpart, 0.0};
   // C is symmetric: its row n is the column n the product needs
-  return launch_rect<RectB3F>(OpsB3F{Wh, Wl, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
+  return launch_rect<RectB3D>(OpsB3F{Wh, Wl, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
 }
 
 int64_t coreg_slots(int64_t Nap) { return Nap / kCB; }
