@@ -199,6 +199,8 @@ panda_status upload_insts(panda_batch* b) {
     d.C = c.C;
     d.Tside = c.Tside;
     d.ppart = c.ppart;
+    d.dP = c.dP;
+    d.dC = c.dC;
     d.nP = c.nP;
     d.nC = c.nC;
     d.nWr = c.nWr;

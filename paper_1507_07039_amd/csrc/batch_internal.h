@@ -17,6 +17,8 @@ struct BInst {
   float* C;
   float* Tside;
   float* ppart;
+  double* dP;  // diagonals of P and C (FP64; zero in the matrices)
+  double* dC;
   double* nP;
   double* nC;
   double* nWr;

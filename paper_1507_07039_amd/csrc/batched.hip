@@ -57,10 +57,8 @@ struct PhResp {
     const int64_t nMT = d.Nep / G::BM;
     const int64_t m0 = (local % nMT) * G::BM, n0 = (local / nMT) * G::BN;
     G g;
-    OpsF32 ops{d.P, d.Nep, W, d.Nap};
-    ops.xdiag = 1;  // P's diagonal is added in FP64 by the epilogue
-    g.run(ops, m0, n0, 0, d.Nep, smem);
-    EpiStoreT epi{d.R, d.Nap, d.Ne, d.Na, d.nP, d.nWc, d.P, d.Nep, W, d.Nap};
+    g.run(OpsF32{d.P, d.Nep, W, d.Nap}, m0, n0, 0, d.Nep, smem);
+    EpiStoreT epi{d.R, d.Nap, d.Ne, d.Na, d.nP, d.nWc, d.dP, W, d.Nap};
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
   }
 };
@@ -82,11 +80,9 @@ struct PhAvail {
     const int64_t nMT = d.Nep / G::BM;
     const int64_t m0 = (local % nMT) * G::BM, n0 = (local / nMT) * G::BN;
     G g;
-    OpsF32 ops{Wold, d.Nap, d.C, d.Nap};
-    ops.ydiag = 1;  // C's diagonal is added in FP64 by the epilogue
-    g.run(ops, m0, n0, 0, d.Nap, smem);
-    EpiWUpdate epi{Wold,  d.R,   d.W[ws ^ 1], d.Nap,      d.Ne,    d.Na, d.nWr,
-                   d.nC,  d.C,   d.Nap,       alpha,      h_undamped, d.hpart, 0.0};
+    g.run(OpsF32{Wold, d.Nap, d.C, d.Nap}, m0, n0, 0, d.Nap, smem);
+    EpiWUpdate epi{Wold, d.R,   d.W[ws ^ 1], d.Nap, d.Ne,       d.Na,    d.nWr,
+                   d.nC, d.dC,  alpha,       h_undamped, d.hpart, 0.0};
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
     epi.end_tile(local, red);
   }
@@ -238,12 +234,13 @@ __global__ __launch_bounds__(kUT) void k_batch_diagonals(const BInst* __restrict
   const upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
   const int64_t q = (int64_t)blockIdx.x - fl.seg_first[seg];
   if (q < d.Ne) {
-    upd::diag_p_row(q, d.P, d.Nep, d.Ne, d.Na, sigma_from_T ? d.Tside : nullptr, d.nP, dr, red);
+    upd::diag_p_row(q, d.P, d.Nep, d.dP, d.Ne, d.Na, sigma_from_T ? d.Tside : nullptr, d.nP, dr,
+                    red);
     return;
   }
   const int64_t r = (q - d.Ne) * kUT + threadIdx.x;
   if (r < d.Na)
-    upd::diag_c_row(r, d.C, d.Nap, d.Ne, d.Na, d.cstat, sigma_from_T ? d.csq : nullptr,
+    upd::diag_c_row(r, d.dC, d.Nap, d.Ne, d.Na, d.cstat, sigma_from_T ? d.csq : nullptr,
                     d.Nap / kCB, d.nC, dr);
 }
 

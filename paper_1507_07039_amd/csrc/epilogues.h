@@ -9,22 +9,32 @@ namespace panda {
 namespace gemm {
 
 // ------------------------------------------------------------ epilogues --
+// The diagonals of P and C grow like exp(2 alpha t) (Eq. 6).  They are kept
+// outside the matrices, as FP64 vectors (the matrices hold zeros there), so
+// the products see only off-diagonal entries and the diagonal term of each
+// dot product is added here in FP64: an FP32 or bf16 accumulator holding
+// P_ii W_ij or W_ij C_jj would lose every other term late in a run.
+//
 // T(X, Y) stored for i < M, j < N (Sec. II-C Tfunction; R of Eq. 3).  With
-// pd set, the peeled diagonal term pd[i][i] * pw[i][j] is added to the
-// product first (R = T(P, W) with P's diagonal outside the bf16 operand).
+// xd set, X's diagonal term xd[i] * yv[i][j] is added to the product (R =
+// T(P, W): xd = diagonal of P, yv = W); with yd set, Y's diagonal term
+// xv[i][j] * yd[j] (T(W, C): xv = W, yd = diagonal of C).
 struct EpiStoreT {
   float* out;
   int64_t ldo, M, N;
   const double* nx;
   const double* ny;
-  const float* pd;
-  int64_t ldpd;
-  const float* pw;
-  int64_t ldpw;
+  const double* xd = nullptr;
+  const float* yv = nullptr;
+  int64_t ldyv = 0;
+  const double* yd = nullptr;
+  const float* xv = nullptr;
+  int64_t ldxv = 0;
   __device__ __forceinline__ void element(int64_t r, int64_t c, float acc) {
     if (r < M && c < N) {
       double dot = (double)acc;
-      if (pd) dot += (double)pd[r * ldpd + r] * (double)pw[r * ldpw + c];
+      if (xd) dot += xd[r] * (double)yv[r * ldyv + c];
+      if (yd) dot += (double)xv[r * ldxv + c] * yd[c];
       out[r * ldo + c] = (float)tanimoto(dot, nx[r], ny[c]);
     }
   }
@@ -33,8 +43,8 @@ struct EpiStoreT {
 
 // A = T(W, C) (Eq. 4) folded into the W update of Eq. 2, with the tile's
 // share of the h sum of Eq. 7.  The new W goes to a second buffer because
-// the old one is still an operand of other blocks.  With cd set, the peeled
-// diagonal term W_ij * C_jj is added to the product first.
+// the old one is still an operand of other blocks.  C's diagonal term
+// W_ij * C_jj is added to the product from the FP64 vector cd.
 struct EpiWUpdate {
   const float* Wold;
   const float* R;
@@ -42,8 +52,7 @@ struct EpiWUpdate {
   int64_t ld, Ne, Na;
   const double* nx;  // |W_i.|^2
   const double* ny;  // |C_.j|^2
-  const float* cd;   // C (diagonal read at [j][j]) or null
-  int64_t ldcd;
+  const double* cd;  // diagonal of C
   double alpha;
   int32_t h_undamped;
   double* hpart;
@@ -53,7 +62,7 @@ struct EpiWUpdate {
       const int64_t o = r * ld + c;
       const double w = Wold[o];
       double dot = (double)acc;
-      if (cd) dot += w * (double)cd[c * ldcd + c];
+      dot += w * cd[c];
       const double a = tanimoto(dot, nx[r], ny[c]);
       const double pred = 0.5 * (a + (double)R[o]);
       const float wn = (float)((1.0 - alpha) * w + alpha * pred);

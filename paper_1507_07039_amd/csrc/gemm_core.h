@@ -114,30 +114,6 @@ struct TileLoad {
     }
   }
 
-  // Zero the entries with global mn == k (the diagonal of a square operand)
-  // when the tile [mn0, mn0 + MN) x [k0, k0 + BK) meets it.
-  __device__ __forceinline__ void zero_diagonal(int64_t mn0, int64_t k0, int t) {
-    if (!(mn0 < k0 + BK && k0 < mn0 + MN)) return;  // the same for the whole block
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      int64_t mn, k;
-      int64_t d;  // position of the diagonal among the four values, if any
-      if constexpr (KC) {
-        mn = mn0 + t / KQ + i * RP;
-        k = k0 + (t % KQ) * 4;
-        d = mn - k;
-      } else {
-        k = k0 + t / TPR + i * RPP;
-        mn = mn0 + (t % TPR) * 4;
-        d = k - mn;
-      }
-      if (d == 0) v[i].x = 0.0f;
-      if (d == 1) v[i].y = 0.0f;
-      if (d == 2) v[i].z = 0.0f;
-      if (d == 3) v[i].w = 0.0f;
-    }
-  }
-
   __device__ __forceinline__ void store(float* lds, int t) const {
     if constexpr (KC) {
       const int kq = (t % KQ) * 4;
@@ -161,17 +137,12 @@ struct TileLoad {
 };
 
 // FP32 operands: X element (m, k) = XK ? X[m*ldx + k] : X[k*ldx + m];
-// Y element (k, n) = YK ? Y[n*ldy + k] : Y[k*ldy + n].  With xdiag / ydiag
-// set, the diagonal (m == k, resp. k == n) of that square operand enters the
-// product as zero; the epilogue adds its term in FP64 (the diagonals of P and
-// C grow like exp(2 alpha t), Eq. 6, and would swamp an FP32 accumulator).
+// Y element (k, n) = YK ? Y[n*ldy + k] : Y[k*ldy + n].
 struct OpsF32 {
   const float* X;
   int64_t ldx;
   const float* Y;
   int64_t ldy;
-  int32_t xdiag = 0;
-  int32_t ydiag = 0;
 };
 
 // Block-level FP32 GEMM over k in [kbeg, kend) for a BM x BN tile with WM x WN
@@ -217,8 +188,6 @@ struct BlockGemm {
     if (nk > 0) {
       lx.load(o.X, o.ldx, m0, kbeg, t);
       ly.load(o.Y, o.ldy, n0, kbeg, t);
-      if (o.xdiag) lx.zero_diagonal(m0, kbeg, t);
-      if (o.ydiag) ly.zero_diagonal(n0, kbeg, t);
       lx.store(xs, t);
       ly.store(ys, t);
     }
@@ -251,8 +220,6 @@ struct BlockGemm {
         __builtin_amdgcn_iglp_opt(0);  // interleave LDS reads with the MFMAs
       }
       if (more) {
-        if (o.xdiag) lx.zero_diagonal(m0, kbeg + (kt + 1) * BK, t);
-        if (o.ydiag) ly.zero_diagonal(n0, kbeg + (kt + 1) * BK, t);
         lx.store(xs + (cur ^ 1) * XS, t);
         ly.store(ys + (cur ^ 1) * YS, t);
       }
@@ -297,7 +264,7 @@ struct OpsB3 {
   int64_t ldy;
 };
 // The same with Y an FP32 symmetric matrix (Yt = Y, rows read K-contiguous)
-// that is split into hi/lo while it is staged, its diagonal set to zero.
+// that is split into hi/lo while it is staged.
 struct OpsB3F {
   const bf16_t* Xh;
   const bf16_t* Xl;
@@ -351,8 +318,7 @@ struct TileLoadB3 {
 
 // MN x BK tile of a K-contiguous FP32 operand (row mn = mn0 + r holds k
 // values k0..), split into the two planes of the TileLoadB3 layout when it is
-// written to LDS; entries with mn == k (the diagonal of a square symmetric
-// operand) become zero, so that term can be added back in FP64.
+// written to LDS.
 template <int MN, int NT, int BK_>
 struct TileLoadB3F {
   using Planes = TileLoadB3<MN, NT, BK_>;
@@ -384,11 +350,7 @@ struct TileLoadB3F {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int r = t / CPR + i * RP;
-      float v[8] = {a[i].x, a[i].y, a[i].z, a[i].w, b[i].x, b[i].y, b[i].z, b[i].w};
-      const int64_t d = mn0 + r - (k0 + 8 * c);  // position of the diagonal in this chunk
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (d == e) v[e] = 0.0f;
+      const float v[8] = {a[i].x, a[i].y, a[i].z, a[i].w, b[i].x, b[i].y, b[i].z, b[i].w};
       unsigned hw[4], lw[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -533,9 +495,8 @@ struct BlockGemmB3 {
 // image is the swizzled layout the fragment reads want:
 //   bf16 planes: rows of BK bf16, slot s of row r holds chunk s ^ f(r) (as
 //     TileLoadB3);
-//   FP32 rows (Y = a symmetric FP32 matrix, split at fragment-read time with
-//     its diagonal zeroed): rows of BK floats = BK/4 chunks, slot s of row r
-//     holds chunk s ^ (r % 8).
+//   FP32 rows (Y = a symmetric FP32 matrix, split at fragment-read time):
+//     rows of BK floats = BK/4 chunks, slot s of row r holds chunk s ^ (r % 8).
 typedef __attribute__((address_space(3))) void* lds_vptr;
 typedef __attribute__((address_space(1))) void* gbl_vptr;
 
@@ -693,12 +654,9 @@ struct BlockGemmB3D {
       for (int j = 0; j < TN; ++j) {
         const f4 a = __builtin_bit_cast(f4, r[PER * ks + 2 * TM + 2 * j]);
         const f4 b = __builtin_bit_cast(f4, r[PER * ks + 2 * TM + 2 * j + 1]);
-        float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-        const int n = wn * (BN / WN) + j * 32 + (lane & 31);
-        const int64_t d = n0 + n - (k0 + 16 * ks + 8 * khalf);  // diagonal position, if any
+        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          if (d == e) v[e] = 0.0f;
           const __bf16 h = (__bf16)v[e];
           yh[ks][j][e] = h;
           yl[ks][j][e] = (__bf16)(v[e] - (float)h);

@@ -73,6 +73,8 @@ struct panda_ctx {
   float* Tside;
   float* ppart;   // split-K partial products of W W^T
   float* skpart;  // stream-K partial tiles (single-network schedule only)
+  double* dP;     // diagonal of P (FP64; P holds zero there)
+  double* dC;     // diagonal of C
   double* nP;     // |P_i.|^2
   double* nC;     // |C_.j|^2
   double* nWr;    // |W_i.|^2

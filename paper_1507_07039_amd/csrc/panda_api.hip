@@ -80,6 +80,8 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   const int splits = (int)spec.ppart_splits;
   float* pp = cv.take<float>((size_t)splits * Nep * Nep);
   float* sk = spec.batched ? nullptr : cv.take<float>(rect_partial_floats());
+  double* dp = cv.take<double>((size_t)Nep);
+  double* dc = cv.take<double>((size_t)Nap);
   double* np_ = cv.take<double>((size_t)Nep);
   double* nc = cv.take<double>((size_t)Nap);
   double* nwr = cv.take<double>((size_t)Nep);
@@ -114,6 +116,8 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
     c->Tside = ts;
     c->ppart = pp;
     c->skpart = sk;
+    c->dP = dp;
+    c->dC = dc;
     c->nP = np_;
     c->nC = nc;
     c->nWr = nwr;
@@ -232,20 +236,20 @@ panda_status enqueue_iteration(panda_ctx* c) {
   PANDA_TRY(mark(c, PANDA_PHASE_R));
   // Eq. 3: R = T(P, W), K = N_e
   if (c->b3)
-    HIP_TRY(launch_resp_b3(c->Ph, c->Pl, c->Nep, c->Wth, c->Wtl, c->Nep, c->Nep, c->Nap, c->Ne,
-                           c->Na, c->P, Wold, c->Nap, c->nP, c->nWc, c->R, c->skpart, active, s));
+    HIP_TRY(launch_resp_b3(c->Ph, c->Pl, c->Nep, c->dP, c->Wth, c->Wtl, c->Nep, c->Nep, c->Nap,
+                           c->Ne, c->Na, Wold, c->Nap, c->nP, c->nWc, c->R, c->skpart, active, s));
   else
-    HIP_TRY(launch_resp(c->P, c->Nep, Wold, c->Nap, c->Nep, c->Nap, c->Ne, c->Na, c->nP, c->nWc,
-                        c->R, c->skpart, active, s));
+    HIP_TRY(launch_resp(c->P, c->Nep, c->dP, Wold, c->Nap, c->Nep, c->Nap, c->Ne, c->Na, c->nP,
+                        c->nWc, c->R, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_AW));
   // Eq. 4 + Eq. 2 + Eq. 7 partials: A = T(W, C), K = N_a
   if (c->b3)
-    HIP_TRY(launch_avail_wupdate_b3(c->Wh, c->Wl, Wold, c->C, c->R, Wnew, c->Nap,
-                                    c->Nep, c->Nap, c->Ne, c->Na, c->nWr, c->nC, c->rule,
-                                    c->hpart, c->skpart, active, s));
+    HIP_TRY(launch_avail_wupdate_b3(c->Wh, c->Wl, Wold, c->C, c->dC, c->R, Wnew, c->Nap, c->Nep,
+                                    c->Nap, c->Ne, c->Na, c->nWr, c->nC, c->rule, c->hpart,
+                                    c->skpart, active, s));
   else
-    HIP_TRY(launch_avail_wupdate(Wold, c->C, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne, c->Na,
-                                 c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s));
+    HIP_TRY(launch_avail_wupdate(Wold, c->C, c->dC, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne,
+                                 c->Na, c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s));
   PANDA_TRY(mark(c, PANDA_PHASE_H));
   HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
   // squared norms (and split planes) of the new W
@@ -276,9 +280,10 @@ panda_status enqueue_iteration(panda_ctx* c) {
                                 c->rule, c->cstat, c->csq, c->corder, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_DIAG));
   // Eq. 6, and |P_i.|^2, |C_.j|^2 for the next iteration
-  HIP_TRY(launch_diagonals(c->P, c->Nep, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr, c->nP,
-                           c->C, c->Nap, c->Na, c->cstat, c->rule.sigma_from_T ? c->csq : nullptr,
-                           coreg_slots(c->Nap), c->nC, c->rule, c->st, s));
+  HIP_TRY(launch_diagonals(c->P, c->Nep, c->dP, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr,
+                           c->nP, c->dC, c->Nap, c->Na, c->cstat,
+                           c->rule.sigma_from_T ? c->csq : nullptr, coreg_slots(c->Nap), c->nC,
+                           c->rule, c->st, s));
   PANDA_TRY(mark(c, PANDA_NPHASE));
   if (c->timing) c->npend += 1;
   c->enqueued += 1;
@@ -494,6 +499,9 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
   HIP_TRY(launch_col_sqnorms(c->C, Na, Na, Nap, c->nC, c->colscr, nullptr, s));
   HIP_TRY(launch_row_sqnorms(c->W[0], Ne, Na, Nap, c->nWr, nullptr, s));
   HIP_TRY(launch_col_sqnorms(c->W[0], Ne, Na, Nap, c->nWc, c->colscr, nullptr, s));
+  // the diagonals of P and C move to their FP64 vectors (zero in the matrices)
+  HIP_TRY(launch_take_diag(c->P, Ne, Nep, c->dP, s));
+  HIP_TRY(launch_take_diag(c->C, Na, Nap, c->dC, s));
   if (c->b3) {
     // planes of the loaded state; padding and the P/C diagonals stay zero
     const size_t nw = (size_t)Nep * Nap;
@@ -542,12 +550,16 @@ panda_status panda_ctx_store(panda_ctx* c, float* W, float* P, float* C, double*
   if (W)
     HIP_TRY(hipMemcpy2DAsync(W, (size_t)c->Na * 4, Wc, (size_t)c->Nap * 4, (size_t)c->Na * 4,
                              (size_t)c->Ne, hipMemcpyDeviceToDevice, s));
-  if (P)
+  if (P) {
     HIP_TRY(hipMemcpy2DAsync(P, (size_t)c->Ne * 4, c->P, (size_t)c->Nep * 4, (size_t)c->Ne * 4,
                              (size_t)c->Ne, hipMemcpyDeviceToDevice, s));
-  if (C)
+    HIP_TRY(launch_put_diag(P, c->Ne, c->Ne, c->dP, s));
+  }
+  if (C) {
     HIP_TRY(hipMemcpy2DAsync(C, (size_t)c->Na * 4, c->C, (size_t)c->Nap * 4, (size_t)c->Na * 4,
                              (size_t)c->Na, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_put_diag(C, c->Na, c->Na, c->dC, s));
+  }
   if (h) *h = c->host->h;
   if (t) *t = c->host->t;
   return PANDA_OK;

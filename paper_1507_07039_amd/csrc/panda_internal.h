@@ -51,23 +51,28 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 int64_t rect_tiles(int64_t Mp, int64_t Np);
 size_t rect_partial_floats();
 
-// Out[i][j] = T(X, Y)_ij for i < M, j < N.
+// Out[i][j] = T(X, Y)_ij for i < M, j < N.  yd (optional): Y is square with
+// its diagonal held apart in this FP64 vector (and zero in Y).
 hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, int64_t ldy,
                                  int64_t Mp, int64_t Np, int64_t Kp, int64_t M, int64_t N,
                                  const double* nx, const double* ny, float* Out, int64_t ldo,
-                                 float* part, const int32_t* gate, hipStream_t s);
+                                 float* part, const int32_t* gate, hipStream_t s,
+                                 const double* yd = nullptr);
 
-// R = T(P, W) of the iteration (Eq. 3): P's diagonal is added in FP64.
-hipError_t launch_resp(const float* P, int64_t ldp, const float* W, int64_t ldw, int64_t Nep,
-                       int64_t Nap, int64_t Ne, int64_t Na, const double* nP, const double* nWc,
-                       float* R, float* part, const int32_t* gate, hipStream_t s);
+// The diagonals of P and C are held apart in FP64 vectors dP, dC (the
+// matrices hold zero there); the products add their terms in the epilogues.
+// R = T(P, W) of the iteration (Eq. 3).
+hipError_t launch_resp(const float* P, int64_t ldp, const double* dP, const float* W, int64_t ldw,
+                       int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na, const double* nP,
+                       const double* nWc, float* R, float* part, const int32_t* gate,
+                       hipStream_t s);
 
-// A = T(W, C) fused with the W update of Eq. 2 and per-tile h partials (Eq. 7);
-// C's diagonal is added in FP64.
-hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* R, float* Wnew,
-                                int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
-                                const double* nWrow, const double* nC, Rule rule, double* hpart,
-                                float* part, const int32_t* gate, hipStream_t s);
+// A = T(W, C) fused with the W update of Eq. 2 and per-tile h partials (Eq. 7).
+hipError_t launch_avail_wupdate(const float* Wold, const float* C, const double* dC,
+                                const float* R, float* Wnew, int64_t ld, int64_t Nep, int64_t Nap,
+                                int64_t Ne, int64_t Na, const double* nWrow, const double* nC,
+                                Rule rule, double* hpart, float* part, const int32_t* gate,
+                                hipStream_t s);
 
 // C update (Eq. 5) on the upper tiles of T(W^T, W) with mirror writes and
 // per-row partial sums for the sigma of Eq. 6 (and |C_.j|^2).  order holds
@@ -94,16 +99,16 @@ int coop_splits(int64_t Nep, int64_t Nap);
 
 // Split-BF16 forms of the same products.  Operands are K-contiguous hi/lo
 // planes: P (diagonal zero), W row-major, W^T (gene-major); C stays FP32.
-hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const bf16_t* Wth,
-                          const bf16_t* Wtl, int64_t ldwt, int64_t Nep, int64_t Nap, int64_t Ne,
-                          int64_t Na, const float* P, const float* W, int64_t ldw,
+hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
+                          const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
+                          int64_t Nap, int64_t Ne, int64_t Na, const float* W, int64_t ldw,
                           const double* nP, const double* nWc, float* R, float* part,
                           const int32_t* gate, hipStream_t s);
 // A = T(W, C) + W update with X = the W planes and Y = the FP32 C itself
-// (symmetric; split into hi/lo while staged, its diagonal peeled).
+// (symmetric; split into hi/lo while staged).
 hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const float* Wold,
-                                   const float* C, const float* R, float* Wnew, int64_t ld,
-                                   int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
+                                   const float* C, const double* dC, const float* R, float* Wnew,
+                                   int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
                                    const double* nWrow, const double* nC, Rule rule,
                                    double* hpart, float* part, const int32_t* gate,
                                    hipStream_t s);
@@ -129,17 +134,21 @@ hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevSta
 hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, const double* nWrow,
                                 float* P, int64_t ldp, int64_t Ne, Rule rule, float* Tside,
                                 bf16_t* Ph, bf16_t* Pl, const int32_t* gate, hipStream_t s);
-hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, double* nP,
-                            float* C, int64_t ldc, int64_t Na, const double2* cstat,
-                            const double* csq, int64_t nslots, double* nC, Rule rule,
-                            const DevState* st, hipStream_t s);
+hipError_t launch_diagonals(const float* P, int64_t ldp, double* dP, int64_t Ne,
+                            const float* Tside, double* nP, double* dC, int64_t ldc, int64_t Na,
+                            const double2* cstat, const double* csq, int64_t nslots, double* nC,
+                            Rule rule, const DevState* st, hipStream_t s);
 // The same with the diagonal rule new = keep * old + f * N * sigma * g given
 // (closed form of several steps of Eq. 6).
-hipError_t launch_diagonals_schedule(float* P, int64_t ldp, int64_t Ne, const float* Tside,
-                                     double* nP, float* C, int64_t ldc, int64_t Na,
-                                     const double2* cstat, const double* csq, int64_t nslots,
-                                     double* nC, Rule rule, double keep, double g,
+hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, int64_t Ne,
+                                     const float* Tside, double* nP, double* dC, int64_t ldc,
+                                     int64_t Na, const double2* cstat, const double* csq,
+                                     int64_t nslots, double* nC, Rule rule, double keep, double g,
                                      const DevState* st, hipStream_t s);
+// The diagonal of an n x n matrix into / out of its FP64 vector (take also
+// sets the matrix diagonal to zero).
+hipError_t launch_take_diag(float* M, int64_t n, int64_t ld, double* d, hipStream_t s);
+hipError_t launch_put_diag(float* M, int64_t n, int64_t ld, const double* d, hipStream_t s);
 // t, the gates, and the current-W selector back to buffer 0.
 hipError_t launch_state_set(DevState* st, int32_t t, int32_t active, int32_t run_pc,
                             hipStream_t s);

@@ -73,50 +73,50 @@ size_t rect_partial_floats() {
 hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, int64_t ldy,
                                  int64_t Mp, int64_t Np, int64_t Kp, int64_t M, int64_t N,
                                  const double* nx, const double* ny, float* Out, int64_t ldo,
-                                 float* part, const int32_t* gate, hipStream_t s) {
-  EpiStoreT epi{Out, ldo, M, N, nx, ny, nullptr, 0, nullptr, 0};
+                                 float* part, const int32_t* gate, hipStream_t s,
+                                 const double* yd) {
+  EpiStoreT epi{Out, ldo, M, N, nx, ny};
+  if (yd) {  // Y's diagonal held apart: its term X_ij Y_jj (X square with Y)
+    epi.yd = yd;
+    epi.xv = X;
+    epi.ldxv = ldx;
+  }
   return launch_rect<RectF32>(OpsF32{X, ldx, Y, ldy}, Mp, Np, Kp, epi, part, gate, s);
 }
 
-hipError_t launch_resp(const float* P, int64_t ldp, const float* W, int64_t ldw, int64_t Nep,
-                       int64_t Nap, int64_t Ne, int64_t Na, const double* nP, const double* nWc,
-                       float* R, float* part, const int32_t* gate, hipStream_t s) {
-  // P's diagonal is left out of the FP32 product and added in FP64
-  EpiStoreT epi{R, ldw, Ne, Na, nP, nWc, P, ldp, W, ldw};
-  OpsF32 ops{P, ldp, W, ldw};
-  ops.xdiag = 1;
-  return launch_rect<RectF32>(ops, Nep, Nap, Nep, epi, part, gate, s);
+hipError_t launch_resp(const float* P, int64_t ldp, const double* dP, const float* W, int64_t ldw,
+                       int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na, const double* nP,
+                       const double* nWc, float* R, float* part, const int32_t* gate,
+                       hipStream_t s) {
+  EpiStoreT epi{R, ldw, Ne, Na, nP, nWc, dP, W, ldw};
+  return launch_rect<RectF32>(OpsF32{P, ldp, W, ldw}, Nep, Nap, Nep, epi, part, gate, s);
 }
 
-hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const bf16_t* Wth,
-                          const bf16_t* Wtl, int64_t ldwt, int64_t Nep, int64_t Nap, int64_t Ne,
-                          int64_t Na, const float* P, const float* W, int64_t ldw,
+hipError_t launch_resp_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
+                          const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
+                          int64_t Nap, int64_t Ne, int64_t Na, const float* W, int64_t ldw,
                           const double* nP, const double* nWc, float* R, float* part,
                           const int32_t* gate, hipStream_t s) {
-  EpiStoreT epi{R, ldw, Ne, Na, nP, nWc, P, ldp, W, ldw};
+  EpiStoreT epi{R, ldw, Ne, Na, nP, nWc, dP, W, ldw};
   return launch_rect<RectB3>(OpsB3{Ph, Pl, ldp, Wth, Wtl, ldwt}, Nep, Nap, Nep, epi, part, gate, s);
 }
 
-hipError_t launch_avail_wupdate(const float* Wold, const float* C, const float* R, float* Wnew,
-                                int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
-                                const double* nWrow, const double* nC, Rule rule, double* hpart,
-                                float* part, const int32_t* gate, hipStream_t s) {
-  // C's diagonal is left out of the FP32 product and added in FP64
-  EpiWUpdate epi{Wold, R,       Wnew,       ld,  Ne,  Na, nWrow, nC, C, ld, rule.alpha,
-                 rule.h_undamped, hpart, 0.0};
-  OpsF32 ops{Wold, ld, C, ld};
-  ops.ydiag = 1;
-  return launch_rect<RectF32>(ops, Nep, Nap, Nap, epi, part, gate, s);
+hipError_t launch_avail_wupdate(const float* Wold, const float* C, const double* dC,
+                                const float* R, float* Wnew, int64_t ld, int64_t Nep, int64_t Nap,
+                                int64_t Ne, int64_t Na, const double* nWrow, const double* nC,
+                                Rule rule, double* hpart, float* part, const int32_t* gate,
+                                hipStream_t s) {
+  EpiWUpdate epi{Wold, R, Wnew, ld, Ne, Na, nWrow, nC, dC, rule.alpha, rule.h_undamped, hpart, 0.0};
+  return launch_rect<RectF32>(OpsF32{Wold, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
 }
 
 hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const float* Wold,
-                                   const float* C, const float* R, float* Wnew, int64_t ld,
-                                   int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
+                                   const float* C, const double* dC, const float* R, float* Wnew,
+                                   int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
                                    const double* nWrow, const double* nC, Rule rule,
                                    double* hpart, float* part, const int32_t* gate,
                                    hipStream_t s) {
-  EpiWUpdate epi{Wold, R,       Wnew,       ld,  Ne,  Na, nWrow, nC, C, ld, rule.alpha,
-                 rule.h_undamped, hpart, 0.0};
+  EpiWUpdate epi{Wold, R, Wnew, ld, Ne, Na, nWrow, nC, dC, rule.alpha, rule.h_undamped, hpart, 0.0};
   // C is symmetric: its row n is the column n the product needs
   return launch_rect<RectB3D>(OpsB3F{Wh, Wl, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
 }

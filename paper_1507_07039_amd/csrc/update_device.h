@@ -103,9 +103,11 @@ __device__ __forceinline__ DiagRule diag_rule(double alpha, int32_t diag_alpha, 
 
 // Eq. 6 for row i of P (one block): population std of the off-diagonal
 // entries by two passes over the row (of the fresh similarities when Tside is
-// set), the new diagonal, and |P_i.|^2 for the next iteration.
-__device__ __forceinline__ void diag_p_row(int64_t i, float* __restrict__ P, int64_t ldp,
-                                           int64_t Ne, int64_t Na, const float* __restrict__ Tside,
+// set), the new diagonal dP[i] (an FP32 value held in FP64 beside P, which
+// holds zero there), and |P_i.|^2 for the next iteration.
+__device__ __forceinline__ void diag_p_row(int64_t i, const float* __restrict__ P, int64_t ldp,
+                                           double* __restrict__ dP, int64_t Ne, int64_t Na,
+                                           const float* __restrict__ Tside,
                                            double* __restrict__ nP, const DiagRule& dr,
                                            double* red) {
   const float* prow = P + i * ldp;
@@ -125,17 +127,17 @@ __device__ __forceinline__ void diag_p_row(int64_t i, float* __restrict__ P, int
   const double var = Ne > 1 ? block_sum(q, red) / n : 0.0;
   if (threadIdx.x == 0) {
     const double mult = dr.n_own ? (double)Ne : (double)Na;
-    const double d = (double)P[i * ldp + i];
-    const float dn = (float)(dr.keep * d + dr.f * mult * sqrt(var) * dr.g);
-    P[i * ldp + i] = dn;
-    nP[i] = off2 + (double)dn * (double)dn;
+    // rounded to FP32 like every stored entry, so a stored state resumes exactly
+    const double dn = (double)(float)(dr.keep * dP[i] + dr.f * mult * sqrt(var) * dr.g);
+    dP[i] = dn;
+    nP[i] = off2 + dn * dn;
   }
 }
 
 // Eq. 6 for row r of C (one thread), from the per-slot (sum, sum of squares)
-// written by the C update (slot stride = ldc, the padded N_a), and
-// |C_.r|^2 for the next iteration.
-__device__ __forceinline__ void diag_c_row(int64_t r, float* __restrict__ C, int64_t ldc,
+// written by the C update (slot stride = ldc, the padded N_a): the new
+// diagonal dC[r] (FP64) and |C_.r|^2 for the next iteration.
+__device__ __forceinline__ void diag_c_row(int64_t r, double* __restrict__ dC, int64_t ldc,
                                            int64_t Ne, int64_t Na,
                                            const double2* __restrict__ cstat,
                                            const double* __restrict__ csq, int64_t nslots,
@@ -155,10 +157,9 @@ __device__ __forceinline__ void diag_c_row(int64_t r, float* __restrict__ C, int
     if (var < 0.0) var = 0.0;
   }
   const double mult = dr.n_own ? (double)Na : (double)Ne;
-  const double d = (double)C[r * ldc + r];
-  const float dn = (float)(dr.keep * d + dr.f * mult * sqrt(var) * dr.g);
-  C[r * ldc + r] = dn;
-  nC[r] = c2 + (double)dn * (double)dn;
+  const double dn = (double)(float)(dr.keep * dC[r] + dr.f * mult * sqrt(var) * dr.g);
+  dC[r] = dn;
+  nC[r] = c2 + dn * dn;
 }
 
 // |M_r.|^2 of one row (one block).

@@ -29,13 +29,13 @@ __global__ __launch_bounds__(kRT) void k_coop_finalize(
 }
 
 // Eq. 6 for both networks.  Blocks [0, Ne): row i of P; remaining blocks:
-// one thread per row of C.
+// one thread per row of C.  The diagonals live in the FP64 vectors dP, dC.
 __global__ __launch_bounds__(kRT) void k_diagonals(
-    float* __restrict__ P, int64_t ldp, int64_t Ne, const float* __restrict__ Tside,
-    double* __restrict__ nP, float* __restrict__ C, int64_t ldc, int64_t Na,
-    const double2* __restrict__ cstat, const double* __restrict__ csq, int64_t nslots,
-    double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own, const DevState* st,
-    int32_t sched, double keep, double g) {
+    const float* __restrict__ P, int64_t ldp, double* __restrict__ dP, int64_t Ne,
+    const float* __restrict__ Tside, double* __restrict__ nP, double* __restrict__ dC,
+    int64_t ldc, int64_t Na, const double2* __restrict__ cstat, const double* __restrict__ csq,
+    int64_t nslots, double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own,
+    const DevState* st, int32_t sched, double keep, double g) {
   __shared__ double red[4];
   if (st->run_pc == 0) return;
   upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
@@ -44,11 +44,27 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     dr.g = g;
   }
   if ((int64_t)blockIdx.x < Ne) {
-    upd::diag_p_row(blockIdx.x, P, ldp, Ne, Na, Tside, nP, dr, red);
+    upd::diag_p_row(blockIdx.x, P, ldp, dP, Ne, Na, Tside, nP, dr, red);
     return;
   }
   const int64_t r = ((int64_t)blockIdx.x - Ne) * kRT + threadIdx.x;
-  if (r < Na) upd::diag_c_row(r, C, ldc, Ne, Na, cstat, csq, nslots, nC, dr);
+  if (r < Na) upd::diag_c_row(r, dC, ldc, Ne, Na, cstat, csq, nslots, nC, dr);
+}
+
+// d[i] = M[i][i] and M[i][i] = 0: the diagonal moves to its FP64 vector.
+__global__ __launch_bounds__(kRT) void k_take_diag(float* __restrict__ M, int64_t n, int64_t ld,
+                                                   double* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * kRT + threadIdx.x;
+  if (i >= n) return;
+  d[i] = (double)M[i * ld + i];
+  M[i * ld + i] = 0.0f;
+}
+
+// M[i][i] = d[i] (rounded to FP32): the diagonal back into a stored matrix.
+__global__ __launch_bounds__(kRT) void k_put_diag(float* __restrict__ M, int64_t n, int64_t ld,
+                                                  const double* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * kRT + threadIdx.x;
+  if (i < n) M[i * ld + i] = (float)d[i];
 }
 
 // ---- split-BF16 operand planes ----------------------------------------------
@@ -258,26 +274,36 @@ hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* M
   return hipGetLastError();
 }
 
-hipError_t launch_diagonals(float* P, int64_t ldp, int64_t Ne, const float* Tside, double* nP,
-                            float* C, int64_t ldc, int64_t Na, const double2* cstat,
-                            const double* csq, int64_t nslots, double* nC, Rule rule,
-                            const DevState* st, hipStream_t s) {
+hipError_t launch_diagonals(const float* P, int64_t ldp, double* dP, int64_t Ne,
+                            const float* Tside, double* nP, double* dC, int64_t ldc, int64_t Na,
+                            const double2* cstat, const double* csq, int64_t nslots, double* nC,
+                            Rule rule, const DevState* st, hipStream_t s) {
   const int64_t nb = Ne + (Na + kRT - 1) / kRT;
-  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, nP, C, ldc, Na, cstat, csq,
-                                                 nslots, nC, rule.alpha, rule.diag_alpha,
+  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
+                                                 csq, nslots, nC, rule.alpha, rule.diag_alpha,
                                                  rule.n_own, st, 0, 0.0, 0.0);
   return hipGetLastError();
 }
 
-hipError_t launch_diagonals_schedule(float* P, int64_t ldp, int64_t Ne, const float* Tside,
-                                     double* nP, float* C, int64_t ldc, int64_t Na,
-                                     const double2* cstat, const double* csq, int64_t nslots,
-                                     double* nC, Rule rule, double keep, double g,
+hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, int64_t Ne,
+                                     const float* Tside, double* nP, double* dC, int64_t ldc,
+                                     int64_t Na, const double2* cstat, const double* csq,
+                                     int64_t nslots, double* nC, Rule rule, double keep, double g,
                                      const DevState* st, hipStream_t s) {
   const int64_t nb = Ne + (Na + kRT - 1) / kRT;
-  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, Ne, Tside, nP, C, ldc, Na, cstat, csq,
-                                                 nslots, nC, rule.alpha, rule.diag_alpha,
+  k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
+                                                 csq, nslots, nC, rule.alpha, rule.diag_alpha,
                                                  rule.n_own, st, 1, keep, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_diag(float* M, int64_t n, int64_t ld, double* d, hipStream_t s) {
+  k_take_diag<<<dim3((unsigned)((n + kRT - 1) / kRT)), kRT, 0, s>>>(M, n, ld, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_diag(float* M, int64_t n, int64_t ld, const double* d, hipStream_t s) {
+  k_put_diag<<<dim3((unsigned)((n + kRT - 1) / kRT)), kRT, 0, s>>>(M, n, ld, d);
   return hipGetLastError();
 }
 

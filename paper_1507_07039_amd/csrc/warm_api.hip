@@ -69,10 +69,10 @@ panda_status panda_ws_features(panda_ctx* c, const float* omegaP, const float* o
   hipStream_t s = c->stream;
   const float* W0 = c->W[c->executed & 1];
   // one-step similarities R0 = T(P0, W0) (into R) and A0 = T(W0, C0) (into S)
-  HIP_TRY(launch_tanimoto_store(c->P, Nep, W0, Nap, Nep, Nap, Nep, Ne, Na, c->nP, c->nWc, c->R,
-                                Nap, c->skpart, nullptr, s));
+  HIP_TRY(launch_resp(c->P, Nep, c->dP, W0, Nap, Nep, Nap, Ne, Na, c->nP, c->nWc, c->R,
+                      c->skpart, nullptr, s));
   HIP_TRY(launch_tanimoto_store(W0, Nap, c->C, Nap, Nep, Nap, Nap, Ne, Na, c->nWr, c->nC, L.S,
-                                Nap, c->skpart, nullptr, s));
+                                Nap, c->skpart, nullptr, s, c->dC));
   HIP_TRY(launch_half_sum(c->R, L.S, Ne, Na, Nap, s));
   // statistics of W0, S and S - W0 (tau)
   HIP_TRY(launch_zscore_stats(W0, Ne, Na, Nap, L.zsW, s));
@@ -81,6 +81,10 @@ panda_status panda_ws_features(panda_ctx* c, const float* omegaP, const float* o
   HIP_TRY(launch_zscore_stats(c->R, Ne, Na, Nap, L.zsD, s));
   // degrees and the two sketch bases
   HIP_TRY(launch_degrees(W0, Ne, Na, Nap, L.dr, L.dc, s));
+  // the sketches use the whole P0 and C0: their diagonals go back in for now
+  // (the vectors hold the FP32 values taken out at load, so this is exact)
+  HIP_TRY(launch_put_diag(c->P, Ne, Nep, c->dP, s));
+  HIP_TRY(launch_put_diag(c->C, Na, Nap, c->dC, s));
   HIP_TRY(launch_widen6(omegaP, Ne, L.omP, s));
   HIP_TRY(launch_widen6(omegaC, Na, L.omC, s));
   HIP_TRY(launch_ws_sketch(c->P, Ne, Nep, L.omP, L.tmpP, L.yP, s));
@@ -91,6 +95,8 @@ panda_status panda_ws_features(panda_ctx* c, const float* omegaP, const float* o
   HIP_TRY(launch_cholqr(L.yC, Na, kSketchPivotRel, L.LinvC, L.d, s));
   HIP_TRY(launch_skinny(c->C, Na, Na, Nap, L.d, L.zC, s));          // C0 d
   HIP_TRY(launch_skinny(W0, Ne, Na, Nap, L.zC, L.c, s));            // c = W0 C0 d
+  HIP_TRY(launch_take_diag(c->P, Ne, Nep, c->dP, s));
+  HIP_TRY(launch_take_diag(c->C, Na, Nap, c->dC, s));
   // moments of the 26 vectors, then the statistics of the 16 features
   VecRefHost refs[kNumVec];
   refs[0] = VecRefHost{L.dr, Ne, 1};
@@ -210,10 +216,10 @@ panda_status panda_ws_init(panda_ctx* c, const float* Wpred, int32_t t0) {
   double g = 0.0;
   for (int32_t tau = 1; tau <= t0; ++tau) g += pow(1.0 - a, (double)(t0 - tau)) * exp(2.0 * a * tau);
   const double keep = pow(1.0 - a, (double)t0);
-  HIP_TRY(launch_diagonals_schedule(c->P, Nep, Ne, c->rule.sigma_from_T ? c->Tside : nullptr,
-                                    c->nP, c->C, Nap, Na, c->cstat,
-                                    c->rule.sigma_from_T ? c->csq : nullptr, coreg_slots(Nap),
-                                    c->nC, c->rule, keep, g, c->st, s));
+  HIP_TRY(launch_diagonals_schedule(c->P, Nep, c->dP, Ne,
+                                    c->rule.sigma_from_T ? c->Tside : nullptr, c->nP, c->dC, Nap,
+                                    Na, c->cstat, c->rule.sigma_from_T ? c->csq : nullptr,
+                                    coreg_slots(Nap), c->nC, c->rule, keep, g, c->st, s));
   HIP_TRY(launch_state_set(c->st, t0, 1, 0, s));
   HIP_TRY(hipStreamSynchronize(s));
   c->t0 = t0;
