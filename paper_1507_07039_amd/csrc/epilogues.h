@@ -81,11 +81,11 @@ struct EpiWUpdate {
 // to 704 = 11 x 64), 4 waves side by side.  Symmetric C product: 128 x 128.
 using RectF32 = BlockGemm<64, 128, 1, 4, true, false, 16>;
 using RectB3 = BlockGemmB3<64, 128, 1, 4>;
-using RectB3F = BlockGemmB3<64, 128, 1, 4, 32, true>;  // Y = FP32 C, split while staged
-#ifndef PANDA_B3D_WN
-#define PANDA_B3D_WN 2
-#endif
-using RectB3D = BlockGemmB3D<64, 128, 1, PANDA_B3D_WN, 3, true>;  // the same, direct-to-LDS pipeline
+// The split-BF16 A product moves its operands by direct loads into LDS, and
+// that path bounds it: 256 x 128 tiles (4 waves of 64 x 128) move half the
+// bytes per MFMA of 64 x 128 ones.  N_e is padded to the tile (704 -> 768)
+// by clamped reads; the padded rows are computed and dropped.
+using RectB3D = BlockGemmB3P<256, 128, 4, 1>;
 using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
 using SymB3 = BlockGemmB3<128, 128, 2, 2>;
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;

@@ -49,8 +49,8 @@ __device__ __forceinline__ double tanimoto(double dot, double xx, double yy) {
   return den > 0.0 ? dot / sqrt(den) : 0.0;
 }
 
-// Deterministic sum of one double per thread over the block (at most 8
-// waves); red holds one double per wave.
+// Deterministic sum of one double per thread over the block; red holds one
+// double per wave.
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -271,6 +271,7 @@ struct OpsB3F {
   int64_t ldx;
   const float* Y;
   int64_t ldy;
+  int64_t mrows = INT64_MAX;  // rows of X that exist (loaders may clamp to them)
 };
 
 // MN x BK tile of one K-contiguous operand, both planes, loaded by NT
@@ -316,63 +317,12 @@ struct TileLoadB3 {
   }
 };
 
-// MN x BK tile of a K-contiguous FP32 operand (row mn = mn0 + r holds k
-// values k0..), split into the two planes of the TileLoadB3 layout when it is
-// written to LDS.
-template <int MN, int NT, int BK_>
-struct TileLoadB3F {
-  using Planes = TileLoadB3<MN, NT, BK_>;
-  static constexpr int BK = BK_, CPR = Planes::CPR, RP = Planes::RP, NV = Planes::NV;
-  static constexpr bool ALL = Planes::ALL;
-  static constexpr int PLANE = Planes::PLANE;
-  __device__ __forceinline__ static int swz(int row, int chunk) { return Planes::swz(row, chunk); }
-
-  f4 a[NV], b[NV];
-  int64_t mn0, k0;
-
-  __device__ __forceinline__ void load(const float* __restrict__ M, int64_t ld, int64_t mn0_,
-                                       int64_t k0_, int t) {
-    mn0 = mn0_;
-    k0 = k0_;
-    if (!ALL && t >= MN * CPR) return;
-    const int c = (t % CPR) * 8;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int r = t / CPR + i * RP;
-      const float* p = M + (mn0 + r) * ld + k0 + c;
-      a[i] = *reinterpret_cast<const f4*>(p);
-      b[i] = *reinterpret_cast<const f4*>(p + 4);
-    }
-  }
-  __device__ __forceinline__ void store(bf16_t* lds, int t) const {
-    if (!ALL && t >= MN * CPR) return;
-    const int c = t % CPR;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int r = t / CPR + i * RP;
-      const float v[8] = {a[i].x, a[i].y, a[i].z, a[i].w, b[i].x, b[i].y, b[i].z, b[i].w};
-      unsigned hw[4], lw[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        bf16_t h0, l0, h1, l1;
-        split_bf16(v[2 * e], h0, l0);
-        split_bf16(v[2 * e + 1], h1, l1);
-        hw[e] = (unsigned)h0 | ((unsigned)h1 << 16);
-        lw[e] = (unsigned)l0 | ((unsigned)l1 << 16);
-      }
-      const int off = Planes::swz(r, c);
-      *reinterpret_cast<u4*>(lds + off) = u4{hw[0], hw[1], hw[2], hw[3]};
-      *reinterpret_cast<u4*>(lds + PLANE + off) = u4{lw[0], lw[1], lw[2], lw[3]};
-    }
-  }
-};
-
 // Block-level split-BF16 GEMM, WM x WN waves of (BM/WM) x (BN/WN) each.
 // All fragments of a K-tile are read from LDS before its MFMAs are issued,
 // so the LDS latency is paid once per tile rather than once per 16-k step.
-template <int BM_, int BN_, int WM, int WN, int BK_ = 32, bool YF32 = false, int WPE = 1>
+template <int BM_, int BN_, int WM, int WN, int BK_ = 32, int WPE = 1>
 struct BlockGemmB3 {
-  using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
+  using Ops = OpsB3;
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
   static constexpr int WAVES_PER_EU = WPE;  // occupancy asked of the compiler (1: no request)
   static constexpr int TM = BM / WM / 32;
@@ -380,7 +330,7 @@ struct BlockGemmB3 {
   static constexpr int KS = BK / 16;  // MFMA k-steps per K-tile
   static_assert(TM >= 1 && TN >= 1, "wave tile below one MFMA block");
   using LX = TileLoadB3<BM, NT, BK>;
-  using LY = typename std::conditional<YF32, TileLoadB3F<BN, NT, BK>, TileLoadB3<BN, NT, BK>>::type;
+  using LY = TileLoadB3<BN, NT, BK>;
   static constexpr int XS = 2 * LX::PLANE;  // bf16 per stage
   static constexpr int YS = 2 * LY::PLANE;
   static constexpr int MAIN_BYTES = 2 * (XS + YS) * 2;
@@ -390,10 +340,7 @@ struct BlockGemmB3 {
 
   __device__ __forceinline__ static void load_y(LY& ly, const Ops& o, int64_t n0, int64_t k0,
                                                 int t) {
-    if constexpr (YF32)
-      ly.load(o.Y, o.ldy, n0, k0, t);
-    else
-      ly.load(o.Yh, o.Yl, o.ldy, n0, k0, t);
+    ly.load(o.Yh, o.Yl, o.ldy, n0, k0, t);
   }
 
   __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
@@ -487,21 +434,48 @@ struct BlockGemmB3 {
   }
 };
 
-// ============================================ pipelined split-BF16 loop ==
-// The same products with the operand tiles moved by direct global -> LDS
-// loads (global_load_lds_dwordx4: lane l of a wave writes its 16 bytes at
-// LDS base + 16 l), so STAGES - 1 K-tiles are in flight without holding
-// registers.  Which global chunk each lane fetches is chosen so that the LDS
-// image is the swizzled layout the fragment reads want:
+// =============================== software-pipelined split-BF16 loop ==
+// A x C with A given as bf16 hi/lo planes and C as FP32 (split into hi/lo
+// as its fragments are read; C is symmetric, so its row n is the column the
+// product needs).  Operand tiles move by direct global -> LDS loads
+// (global_load_lds_dwordx4: lane l of a wave writes its 16 bytes at LDS base
+// + 16 l) into three stages, so two K-tiles are in flight without holding
+// registers.  Which global chunk a lane fetches is chosen so that the LDS
+// image is swizzled for conflict-free fragment reads:
 //   bf16 planes: rows of BK bf16, slot s of row r holds chunk s ^ f(r) (as
 //     TileLoadB3);
-//   FP32 rows (Y = a symmetric FP32 matrix, split at fragment-read time):
-//     rows of BK floats = BK/4 chunks, slot s of row r holds chunk s ^ (r % 8).
-typedef __attribute__((address_space(3))) void* lds_vptr;
-typedef __attribute__((address_space(1))) void* gbl_vptr;
-
-__device__ __forceinline__ void dma16(const void* g, void* lds) {
-  __builtin_amdgcn_global_load_lds((gbl_vptr)g, (lds_vptr)lds, 16, 0, 0);
+//   FP32 rows: BK floats = 8 chunks, slot s of row r holds chunk
+//     s ^ ((r / 2) % 8), so the 16 rows one read touches at a time cover all
+//     64 banks.
+// The loop is also software-pipelined in registers: while the matrix cores
+// work on K-tile k, the wave issues the loads of K-tile k + 3, reads the
+// fragments of K-tile k + 1 from LDS and splits them.
+//
+// The direct loads are issued from inline assembly (no register results;
+// the LDS base goes through M0), so the compiler's own LDS reads are not
+// held back for them; ordering is explicit instead: every wave waits for its
+// own loads of a stage (vmcnt), then a barrier that is also a compiler
+// memory barrier makes the stage complete for all waves.  A stage is
+// refilled only after the barrier that follows its last reads.
+__device__ __forceinline__ void lds_dma16(unsigned voff, const void* sbase, unsigned ldsa) {
+  // the base and the LDS address are wave-uniform; say so, so that they sit
+  // in scalar registers whatever the compiler concluded about them
+  // (the builtin returns a signed int: widen through unsigned, or a low half
+  // with bit 31 set would be sign-extended into the high half)
+  const uint64_t b = (uint64_t)sbase;
+  const uint64_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const uint64_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  const uint64_t bs = lo | (hi << 32);
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+               :
+               : "v"(voff), "s"(bs), "s"(__builtin_amdgcn_readfirstlane(ldsa))
+               : "memory", "m0");
+}
+// Barrier after this wave's LDS reads have completed (so no read of a stage
+// can still be pending when another wave refills it); also a compiler
+// memory barrier.
+__device__ __forceinline__ void wave_barrier_mem() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // Wait until at most n vector-memory operations of this wave are pending
@@ -513,193 +487,272 @@ __device__ __forceinline__ void wait_vmem() {
   __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-template <int BM_, int BN_, int WM, int WN, int STAGES, bool YF32>
-struct BlockGemmB3D {
-  using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
+// hi = RNE(a), lo = RNE(a - hi) for two floats at once (packed bf16 pairs).
+__device__ __forceinline__ void split_pair(float a, float b, unsigned& h, unsigned& l) {
+  typedef float fl2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bh2 __attribute__((ext_vector_type(2)));
+  h = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){a, b}, bh2));
+  const float ha = __builtin_bit_cast(float, h << 16);
+  const float hb = __builtin_bit_cast(float, h & 0xffff0000u);
+  l = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){a - ha, b - hb}, bh2));
+}
+
+template <int BM_, int BN_, int WM, int WN>
+struct BlockGemmB3P {
+  using Ops = OpsB3F;
   static constexpr int BM = BM_, BN = BN_, BK = 32, NT = 64 * WM * WN;
   static constexpr int WAVES = WM * WN;
   static constexpr int WAVES_PER_EU = 1;
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
   static constexpr int KS = BK / 16;
-  static_assert(TM >= 1 && TN >= 1 && STAGES >= 2, "shape");
+  static_assert(TM >= 1 && TN >= 1 && KS == 2, "two 16-deep k-steps per K-tile");
   using PX = TileLoadB3<BM, NT, BK>;  // swizzle of the bf16 planes
-  using PY = TileLoadB3<BN, NT, BK>;
-  static constexpr int CPR = BK / 8;                        // 16-byte chunks per bf16 row
-  static constexpr int XQ = BM * CPR;                       // chunks per X plane
-  static constexpr int YQ = YF32 ? BN * (BK / 4) : BN * CPR;  // chunks per Y plane (1 or 2 planes)
-  static constexpr int YPLANES = YF32 ? 1 : 2;
-  static constexpr int STAGE_BYTES = (2 * XQ + YPLANES * YQ) * 16;
+  static constexpr int CPR = BK / 8;  // 16-byte chunks per bf16 row
+  static constexpr int XQ = BM * CPR; // chunks per X plane
+  static constexpr int YQ = BN * (BK / 4);  // chunks of the FP32 Y tile
+  static constexpr int STAGE_BYTES = (2 * XQ + YQ) * 16;
   static constexpr int MAIN_BYTES = 16;  // the stages are run()'s own LDS objects
-  static constexpr int XI = 2 * XQ / 64, YI = YPLANES * YQ / 64;  // wave-instructions per stage
-  static_assert((2 * XQ) % 64 == 0 && (YPLANES * YQ) % 64 == 0, "whole wave loads");
-  static_assert((XI + YI) % WAVES == 0, "loads split evenly over the waves");
+  static constexpr int XI = 2 * XQ / 64, YI = YQ / 64;  // wave-instructions per stage
+  static_assert((2 * XQ) % 64 == 0 && YQ % 64 == 0 && (XI + YI) % WAVES == 0, "load split");
   static constexpr int IPW = (XI + YI) / WAVES;  // loads per wave and stage
+  static constexpr int PER = 2 * TM + 2 * TN;   // 16-byte fragment reads per k-step
+  static constexpr int NR = KS * PER;
 
   floatx16 acc[TM][TN];
   int lane, wm, wn;
 
-  // Issue the loads of K-tile k0 into stage buffer st (this wave's share).
-  __device__ __forceinline__ void issue(const Ops& o, int64_t m0, int64_t n0, int64_t k0,
-                                       char* st, int w) const {
-#pragma unroll
-    for (int q = 0; q < IPW; ++q) {
-      const int ins = w + q * WAVES;  // wave-instruction index within the stage
-      const int pos = (ins % (XI + YI) < XI ? ins : ins - XI) * 64 + lane;
-      if (ins < XI) {
-        const int plane = pos / XQ, p = pos % XQ;
-        const int r = p / CPR, slot = p % CPR;
-        const int chunk = slot ^ ((r / PX::RG) & (CPR - 1));
-        const bf16_t* src = (plane ? o.Xl : o.Xh) + (m0 + r) * o.ldx + k0 + chunk * 8;
-        dma16(src, st + (size_t)ins * 1024);
-      } else {
-        char* dst = st + 2 * XQ * 16 + (size_t)(ins - XI) * 1024;
-        if constexpr (YF32) {
-          const int r = pos / (BK / 4), slot = pos % (BK / 4);
-          const int chunk = slot ^ (r & 7);
-          dma16(o.Y + (n0 + r) * o.ldy + k0 + chunk * 4, dst);
-        } else {
-          const int plane = pos / YQ, p = pos % YQ;
-          const int r = p / CPR, slot = p % CPR;
-          const int chunk = slot ^ ((r / PY::RG) & (CPR - 1));
-          dma16((plane ? o.Yl : o.Yh) + (n0 + r) * o.ldy + k0 + chunk * 8, dst);
-        }
-      }
-    }
-  }
+  struct Frag {  // operands of one K-tile
+    bf16x8 xh[KS][TM], xl[KS][TM], yh[KS][TN], yl[KS][TN];
+  };
+  struct Raw {
+    u4 r[NR];
+  };
+  // This wave's loads of one stage: wave-instruction q * WAVES + w of the
+  // stage, so which operand a load q reads is fixed at compile time.
+  static constexpr int XPW = XI / WAVES;        // X loads per wave (both planes)
+  static constexpr int XPP = XPW / 2;           // ... per plane
+  static_assert(XI % (2 * WAVES) == 0, "planes split evenly over the waves");
+  struct Dma {
+    const char* xh;  // uniform bases at K-tile 0 of the range
+    const char* xl;
+    const char* y;
+    unsigned voff[IPW];  // per lane
+    unsigned wofs;       // this wave's LDS offset within a stage
+  };
 
-  template <int N>
-  __device__ __forceinline__ static void wait_ahead(int ahead) {
-    // pending loads allowed: `ahead` later stages of IPW loads each
-    if constexpr (N <= 0) {
-      wait_vmem<0>();
-    } else {
-      if (ahead >= N) {
-        wait_vmem<N * IPW>();
-      } else {
-        wait_ahead<N - 1>(ahead);
-      }
-    }
-  }
-
-  // LDS byte address of a generic pointer into shared memory.
   __device__ __forceinline__ static unsigned lds_addr(const void* p) {
     return (unsigned)(size_t)(const __attribute__((address_space(3))) char*)p;
   }
 
-  __device__ __forceinline__ void compute(const char* st, int64_t n0, int64_t k0) {
-    static_assert(YF32 && KS == 2 && TM == 2 && (TN == 1 || TN == 2), "fragment reads written for these shapes");
-    constexpr int PER = 2 * TM + 2 * TN;  // fragments per k-step
-    constexpr int NR = KS * PER;
+  __device__ __forceinline__ void setup(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg, int w,
+                                        Dma& d) const {
+    d.xh = reinterpret_cast<const char*>(o.Xh + m0 * o.ldx + kbeg);
+    d.xl = reinterpret_cast<const char*>(o.Xl + m0 * o.ldx + kbeg);
+    d.y = reinterpret_cast<const char*>(o.Y + n0 * o.ldy + kbeg);
+    d.wofs = (unsigned)w * 1024u;
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) {
+      if (q < XPW) {
+        const int p = ((q % XPP) * WAVES + w) * 64 + lane;  // chunk within the plane
+        const int r = p / CPR, slot = p % CPR;
+        const int chunk = slot ^ ((r / PX::RG) & (CPR - 1));
+        // rows past the operand's end (M padded to the tile) re-read its last
+        // row; their outputs are never stored
+        const int64_t rr = (m0 + r < o.mrows ? m0 + r : o.mrows - 1) - m0;
+        d.voff[q] = (unsigned)((rr * o.ldx + chunk * 8) * 2);
+      } else {
+        const int p = ((q - XPW) * WAVES + w) * 64 + lane;
+        const int r = p / (BK / 4), slot = p % (BK / 4);
+        const int chunk = slot ^ ((r >> 1) & 7);
+        d.voff[q] = (unsigned)(((int64_t)r * o.ldy + chunk * 4) * 4);
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void issue(const Dma& d, int kt, const char* st) {
+    const unsigned sb = lds_addr(st) + d.wofs;
+    const char* xh = d.xh + (size_t)kt * (BK * 2);
+    const char* xl = d.xl + (size_t)kt * (BK * 2);
+    const char* y = d.y + (size_t)kt * (BK * 4);
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) {
+      const char* b = q < XPP ? xh : q < XPW ? xl : y;
+      lds_dma16(d.voff[q], b, sb + (unsigned)(q * WAVES) * 1024u);
+    }
+  }
+
+  // Byte offsets (within a stage) of this lane's 16 fragment reads.
+  __device__ __forceinline__ void read_offsets(unsigned (&ad)[NR]) const {
     const int mrow = wm * (BM / WM) + (lane & 31);
     const int khalf = lane >> 5;
-    const unsigned base = lds_addr(st);
-    const unsigned ybase = base + 2 * XQ * 16;
-    unsigned ad[NR];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int chunk = 2 * ks + khalf;
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const unsigned off = 2u * PX::swz(mrow + i * 32, chunk);
-        ad[PER * ks + 2 * i] = base + off;
-        ad[PER * ks + 2 * i + 1] = base + 2u * BM * BK + off;
+        ad[PER * ks + 2 * i] = off;
+        ad[PER * ks + 2 * i + 1] = 2u * BM * BK + off;
       }
       const int c0 = 4 * ks + 2 * khalf;
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int n = wn * (BN / WN) + j * 32 + (lane & 31);
-        ad[PER * ks + 2 * TM + 2 * j] = ybase + 4u * (n * BK + ((c0 ^ (n & 7)) << 2));
-        ad[PER * ks + 2 * TM + 2 * j + 1] = ybase + 4u * (n * BK + (((c0 + 1) ^ (n & 7)) << 2));
+        const unsigned yb = 2u * XQ * 16 + 4u * n * BK;
+        const int f = (n >> 1) & 7;  // rows n and n + 8 in different bank halves
+        ad[PER * ks + 2 * TM + 2 * j] = yb + 4u * ((c0 ^ f) << 2);
+        ad[PER * ks + 2 * TM + 2 * j + 1] = yb + 4u * (((c0 + 1) ^ f) << 2);
       }
     }
-    // All reads of the K-tile in one block that waits for them before it
-    // ends, so no read is left in flight when its result is used.
-    u4 r[NR];
-    if constexpr (NR == 12) {
-      asm volatile(
-          "ds_read_b128 %0, %12\n\tds_read_b128 %1, %13\n\tds_read_b128 %2, %14\n\t"
-          "ds_read_b128 %3, %15\n\tds_read_b128 %4, %16\n\tds_read_b128 %5, %17\n\t"
-          "ds_read_b128 %6, %18\n\tds_read_b128 %7, %19\n\tds_read_b128 %8, %20\n\t"
-          "ds_read_b128 %9, %21\n\tds_read_b128 %10, %22\n\tds_read_b128 %11, %23\n\t"
-          "s_waitcnt lgkmcnt(0)"
-          : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
-            "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11])
-          : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]), "v"(ad[6]),
-            "v"(ad[7]), "v"(ad[8]), "v"(ad[9]), "v"(ad[10]), "v"(ad[11]));
-    } else {
-      asm volatile(
-          "ds_read_b128 %0, %16\n\tds_read_b128 %1, %17\n\tds_read_b128 %2, %18\n\t"
-          "ds_read_b128 %3, %19\n\tds_read_b128 %4, %20\n\tds_read_b128 %5, %21\n\t"
-          "ds_read_b128 %6, %22\n\tds_read_b128 %7, %23\n\tds_read_b128 %8, %24\n\t"
-          "ds_read_b128 %9, %25\n\tds_read_b128 %10, %26\n\tds_read_b128 %11, %27\n\t"
-          "ds_read_b128 %12, %28\n\tds_read_b128 %13, %29\n\tds_read_b128 %14, %30\n\t"
-          "ds_read_b128 %15, %31\n\ts_waitcnt lgkmcnt(0)"
-          : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
-            "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11]),
-            "=&v"(r[12]), "=&v"(r[13]), "=&v"(r[14]), "=&v"(r[15])
-          : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]), "v"(ad[6]),
-            "v"(ad[7]), "v"(ad[8]), "v"(ad[9]), "v"(ad[10]), "v"(ad[11]), "v"(ad[12]),
-            "v"(ad[13]), "v"(ad[14]), "v"(ad[15]));
-    }
-    bf16x8 xh[KS][TM], xl[KS][TM], yh[KS][TN], yl[KS][TN];
+  }
+
+  __device__ __forceinline__ static void read(const char* st, const unsigned (&ad)[NR], Raw& rw) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) rw.r[i] = *reinterpret_cast<const u4*>(st + ad[i]);
+  }
+
+  __device__ __forceinline__ static void split(const Raw& rw, Frag& f) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        xh[ks][i] = __builtin_bit_cast(bf16x8, r[PER * ks + 2 * i]);
-        xl[ks][i] = __builtin_bit_cast(bf16x8, r[PER * ks + 2 * i + 1]);
+        f.xh[ks][i] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * i]);
+        f.xl[ks][i] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * i + 1]);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const f4 a = __builtin_bit_cast(f4, r[PER * ks + 2 * TM + 2 * j]);
-        const f4 b = __builtin_bit_cast(f4, r[PER * ks + 2 * TM + 2 * j + 1]);
-        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const __bf16 h = (__bf16)v[e];
-          yh[ks][j][e] = h;
-          yl[ks][j][e] = (__bf16)(v[e] - (float)h);
-        }
+        const f4 a = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j]);
+        const f4 b = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j + 1]);
+        unsigned h0, h1, h2, h3, l0, l1, l2, l3;
+        split_pair(a.x, a.y, h0, l0);
+        split_pair(a.z, a.w, h1, l1);
+        split_pair(b.x, b.y, h2, l2);
+        split_pair(b.z, b.w, h3, l3);
+        f.yh[ks][j] = __builtin_bit_cast(bf16x8, (u4){h0, h1, h2, h3});
+        f.yl[ks][j] = __builtin_bit_cast(bf16x8, (u4){l0, l1, l2, l3});
       }
     }
+  }
+
+  __device__ __forceinline__ void mfma(const Frag& f) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ks][i], yl[ks][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[ks][i], yh[ks][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[ks][i], yh[ks][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yl[ks][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xl[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
         }
   }
 
-  // One K-tile step: wait for stage `cur`, release stage `nxt`, start its
-  // loads (tile kt + STAGES - 1), compute on `cur`.  Stages are distinct
-  // LDS objects so that the compiler can tell the loads in flight from the
-  // stage being read and does not wait for them.
-  __device__ __forceinline__ void step(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
-                                       int kt, int nk, char* cur, char* nxt, int w) {
-    const int ahead = nk - 1 - kt < STAGES - 2 ? nk - 1 - kt : STAGES - 2;
-    wait_ahead<STAGES - 2>(ahead);
-    // Every wave has waited for its own loads of stage kt; the barrier alone
-    // (no memory fence, which would wait for the later stages too) makes
-    // stage kt complete for all and stage kt-1 free (its reads fed MFMAs).
-    __builtin_amdgcn_s_barrier();
-    if (kt + STAGES - 1 < nk) issue(o, m0, n0, kbeg + (int64_t)(kt + STAGES - 1) * BK, nxt, w);
-    compute(cur, n0, kbeg + (int64_t)kt * BK);
+  // One MFMA of a K-tile: m = ((ks * TM + i) * TN + j) * 3 + product, the
+  // order of mfma() (so results are the same bit for bit).
+  __device__ __forceinline__ void mfma_at(const Frag& f, int m) {
+    const int p = m % 3, j = (m / 3) % TN, i = (m / 3 / TN) % TM, ks = m / 3 / TN / TM;
+    if (p == 0)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yl[ks][j], acc[i][j], 0, 0, 0);
+    else if (p == 1)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xl[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
+    else
+      acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
+  }
+  // Split pair sp of the next tile's Y fragments (4 pairs per fragment).
+  __device__ __forceinline__ static void split_at(const Raw& rw, unsigned (&h)[KS][TN][4],
+                                                  unsigned (&l)[KS][TN][4], int sp) {
+    const int fi = sp / 4, pr = sp % 4, ks = fi / TN, j = fi % TN;
+    const f4 v = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j + pr / 2]);
+    if (pr % 2 == 0)
+      split_pair(v.x, v.y, h[ks][j][pr], l[ks][j][pr]);
+    else
+      split_pair(v.z, v.w, h[ks][j][pr], l[ks][j][pr]);
+    // keep the pair here, between its MFMAs (the compiler would otherwise sink
+    // it to the end of the K-tile, next to its first use)
+    asm volatile("" : "+v"(h[ks][j][pr]), "+v"(l[ks][j][pr]));
+  }
+
+  // K-tile kt whose three successors exist: stage `rd` holds tile kt + 1,
+  // stage `fr` held tile kt (already in registers) and takes tile kt + 3.
+  // The MFMAs of tile kt are issued one by one, each followed by work of
+  // the next tile that does not depend on them: first the direct loads of
+  // tile kt + 3 and the LDS reads of tile kt + 1, then the split of tile
+  // kt + 1's C fragments.  Scheduling barriers keep this order (the matrix
+  // core runs each MFMA while the wave issues what follows it).
+  __device__ __forceinline__ void full_step(const Dma& d, const unsigned (&ad)[NR], int kt,
+                                            const char* rd, const char* fr, Frag& cur) {
+    constexpr int NM = KS * TM * TN * 3;  // MFMAs per K-tile
+    constexpr int NSP = KS * TN * 4;      // split pairs per K-tile
+    constexpr int NRM = (NR + 1) / 2;     // MFMAs followed by reads
+    static_assert(IPW <= NM, "one direct load per MFMA slot at most");
+    wait_vmem<IPW>();  // tile kt + 1 landed (tile kt + 2 may be in flight)
+    wave_barrier_mem();
+    __builtin_amdgcn_sched_barrier(0);
+    const unsigned sb = lds_addr(fr) + d.wofs;
+    const char* xh = d.xh + (size_t)(kt + 3) * (BK * 2);
+    const char* xl = d.xl + (size_t)(kt + 3) * (BK * 2);
+    const char* y = d.y + (size_t)(kt + 3) * (BK * 4);
+    Raw rw;
+    unsigned h[KS][TN][4], l[KS][TN][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      mfma_at(cur, m);
+      if (m < IPW) {
+        const char* b = m < XPP ? xh : m < XPW ? xl : y;
+        lds_dma16(d.voff[m], b, sb + (unsigned)(m * WAVES) * 1024u);
+      }
+      if (m < NRM) {
+#pragma unroll
+        for (int r = 2 * m; r < 2 * m + 2 && r < NR; ++r)
+          rw.r[r] = *reinterpret_cast<const u4*>(rd + ad[r]);
+      } else if (m - NRM < NSP) {
+        split_at(rw, h, l, m - NRM);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = NM; m < NRM + NSP; ++m) {  // split pairs left over (none for these shapes)
+      split_at(rw, h, l, m - NRM);
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        cur.xh[ks][i] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * i]);
+        cur.xl[ks][i] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * i + 1]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        cur.yh[ks][j] = __builtin_bit_cast(bf16x8, (u4){h[ks][j][0], h[ks][j][1], h[ks][j][2], h[ks][j][3]});
+        cur.yl[ks][j] = __builtin_bit_cast(bf16x8, (u4){l[ks][j][0], l[ks][j][1], l[ks][j][2], l[ks][j][3]});
+      }
+    }
+  }
+
+  // Any K-tile (near the end of the range): the same with bounds.
+  __device__ __forceinline__ void tail_step(const Dma& d, const unsigned (&ad)[NR], int kt, int nk,
+                                            const char* rd, const char* fr, Frag& cur) {
+    if (kt + 1 < nk) {
+      if (kt + 2 < nk) wait_vmem<IPW>(); else wait_vmem<0>();
+      wave_barrier_mem();
+      if (kt + 3 < nk) issue(d, kt + 3, fr);
+      Raw rw;
+      read(rd, ad, rw);
+      mfma(cur);
+      split(rw, cur);
+    } else {
+      mfma(cur);
+    }
   }
 
   __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
                                       int64_t kend, char*) {
-    static_assert(STAGES == 3, "three stage buffers");
     __shared__ __align__(16) char s0[STAGE_BYTES];
     __shared__ __align__(16) char s1[STAGE_BYTES];
     __shared__ __align__(16) char s2[STAGE_BYTES];
-    const int t = threadIdx.x;
-    lane = t & 63;
-    const int w = t >> 6;
+    lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     wm = w % WM;
     wn = w / WM;
 #pragma unroll
@@ -709,18 +762,42 @@ struct BlockGemmB3D {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     const int nk = (int)((kend - kbeg) / BK);
-    wait_vmem<0>();   // only this tile's loads are counted below
-    __syncthreads();  // the previous tile's reads of every stage are done
-    if (nk > 0) issue(o, m0, n0, kbeg, s0, w);
-    if (nk > 1) issue(o, m0, n0, kbeg + BK, s1, w);
-    int kt = 0;
-    for (; kt + 3 <= nk; kt += 3) {
-      step(o, m0, n0, kbeg, kt, nk, s0, s2, w);
-      step(o, m0, n0, kbeg, kt + 1, nk, s1, s0, w);
-      step(o, m0, n0, kbeg, kt + 2, nk, s2, s1, w);
+    // Every wave of the block is done with the stages (its reads of the
+    // previous range fed MFMAs before its epilogue).
+    wait_vmem<0>();
+    wave_barrier_mem();
+    if (nk <= 0) return;
+    Dma d;
+    setup(o, m0, n0, kbeg, w, d);
+    unsigned ad[NR];
+    read_offsets(ad);
+    issue(d, 0, s0);
+    if (nk > 1) {
+      issue(d, 1, s1);
+      wait_vmem<IPW>();
+    } else {
+      wait_vmem<0>();
     }
-    if (kt < nk) step(o, m0, n0, kbeg, kt, nk, s0, s2, w);
-    if (kt + 1 < nk) step(o, m0, n0, kbeg, kt + 1, nk, s1, s0, w);
+    wave_barrier_mem();
+    if (nk > 2) issue(d, 2, s2);
+    Frag cur;
+    {
+      Raw rw;
+      read(s0, ad, rw);
+      split(rw, cur);
+    }
+    int kt = 0;
+    for (; kt + 5 < nk; kt += 3) {
+      full_step(d, ad, kt, s1, s0, cur);
+      full_step(d, ad, kt + 1, s2, s1, cur);
+      full_step(d, ad, kt + 2, s0, s2, cur);
+    }
+    for (; kt < nk; ++kt) {
+      const int ph = kt % 3;
+      const char* rd = ph == 0 ? s1 : ph == 1 ? s2 : s0;
+      const char* fr = ph == 0 ? s0 : ph == 1 ? s1 : s2;
+      tail_step(d, ad, kt, nk, rd, fr, cur);
+    }
   }
 
   __device__ __forceinline__ int row_of(int i, int r) const {
@@ -812,13 +889,16 @@ void k_rect_streamk(typename G::Ops ops, int64_t nMT,
 
 // Tail tiles whose K-steps were split between blocks: sum the partial
 // products in block order (deterministic) and run the same epilogue.
+// (1024 threads per tile: the epilogue's loads form a dependent chain per
+// element, so the fix-up runs as many waves per tile as a block holds.)
+constexpr int kFixThreads = 1024;
 template <class G, class Epi>
-__global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
-                                                         int64_t nb, int64_t nbt,
-                                                         const float* __restrict__ part, Epi epi,
-                                                         const int32_t* gate) {
+__global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
+                                                            int64_t nb, int64_t nbt,
+                                                            const float* __restrict__ part, Epi epi,
+                                                            const int32_t* gate) {
   if (gate && *gate == 0) return;
-  __shared__ double red[8];
+  __shared__ double red[kFixThreads / 64];
   const int64_t nFull = (nTiles / nb) * nb;
   const int64_t tile = nFull + blockIdx.x;
   if (tile >= nTiles) return;
@@ -828,14 +908,25 @@ __global__ __launch_bounds__(kThreads) void k_rect_fixup(int64_t nMT, int64_t nT
   if (lo == hi) return;  // finished inside one block
   const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
   constexpr int E = G::BM * G::BN;
-  for (int e = threadIdx.x; e < E; e += kThreads) {
-    float s = 0.0f;
-    for (int64_t L = lo; L <= hi; ++L) {
+  // partial slots of the contributing blocks, in block order (found once)
+  constexpr int kMaxParts = 16;
+  static_assert(kTailSplit + 2 <= kMaxParts, "a tail tile spans at most kTailSplit + 1 blocks");
+  __shared__ int64_t slot[kMaxParts];
+  __shared__ int nparts;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int64_t L = lo; L <= hi && n < kMaxParts; ++L) {
       const int64_t bL = sk_begin(L, total, nbt);
       if (bL == sk_begin(L + 1, total, nbt)) continue;  // empty range
-      const int64_t slot = 2 * L + ((L == lo && bL < tt * U) ? 1 : 0);
-      s += part[slot * E + e];
+      slot[n++] = (2 * L + ((L == lo && bL < tt * U) ? 1 : 0)) * E;
     }
+    nparts = n;
+  }
+  __syncthreads();
+  const int np = nparts;
+  for (int e = threadIdx.x; e < E; e += kFixThreads) {
+    float s = 0.0f;
+    for (int q = 0; q < np; ++q) s += part[slot[q] + e];
     epi.element(m0 + e / G::BN, n0 + e % G::BN, s);
   }
   epi.end_tile(tile, red);
@@ -865,6 +956,8 @@ hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64
   const int64_t nTiles = nMT * nNT, U = Kp / G::BK;
   int64_t nb = resident;
   if (nb > kMaxStreamKBlocks) nb = kMaxStreamKBlocks;
+  // the split-tile scratch holds 2 * kMaxStreamKBlocks tiles of 64 x 128
+  if (nb * G::BM * G::BN > kMaxStreamKBlocks * 64 * 128) nb = kMaxStreamKBlocks * 64 * 128 / (G::BM * G::BN);
   if (nb > nTiles) nb = nTiles;
   const int64_t tail = nTiles - (nTiles / nb) * nb;
   const int64_t nbt = tail * kTailSplit < nb ? tail * kTailSplit : nb;
@@ -873,8 +966,8 @@ hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tail == 0) return hipSuccess;
-  k_rect_fixup<G, Epi><<<dim3((unsigned)tail), dim3(kThreads), 0, s>>>(nMT, nTiles, U, nb, nbt,
-                                                                       part, epi, gate);
+  k_rect_fixup<G, Epi><<<dim3((unsigned)tail), dim3(kFixThreads), 0, s>>>(nMT, nTiles, U, nb, nbt,
+                                                                          part, epi, gate);
   return hipGetLastError();
 }
 

@@ -125,7 +125,7 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
     c->colscr = scr;
     c->splits = splits;
     c->hpart = hp;
-    c->nh = nh;
+    c->nh = b3 ? rect_tiles_b3(c->Nep, c->Nap) : nh;  // h partials the A + W tiling writes
     c->cstat = cs;
     c->csq = cq;
     c->zs = zs;

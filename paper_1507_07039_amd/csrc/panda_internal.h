@@ -49,6 +49,7 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // nx / ny are the FP64 squared norms of the rows of X / columns of Y.
 // part: rect_partial_floats() floats of split-tile scratch.
 int64_t rect_tiles(int64_t Mp, int64_t Np);
+int64_t rect_tiles_b3(int64_t Mp, int64_t Np);  // tiles of the split-BF16 A + W product
 size_t rect_partial_floats();
 
 // Out[i][j] = T(X, Y)_ij for i < M, j < N.  yd (optional): Y is square with

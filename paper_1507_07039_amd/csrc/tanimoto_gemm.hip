@@ -66,6 +66,9 @@ __global__ __launch_bounds__(kThreads) void k_coop_partial(typename G::Ops ops, 
 // ---------------------------------------------------------------- launch --
 
 int64_t rect_tiles(int64_t Mp, int64_t Np) { return (Mp / RectF32::BM) * (Np / RectF32::BN); }
+int64_t rect_tiles_b3(int64_t Mp, int64_t Np) {
+  return ((Mp + RectB3D::BM - 1) / RectB3D::BM) * (Np / RectB3D::BN);
+}
 size_t rect_partial_floats() {
   return (size_t)2 * (size_t)kMaxStreamKBlocks * RectF32::BM * RectF32::BN;
 }
@@ -118,7 +121,8 @@ hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const flo
                                    hipStream_t s) {
   EpiWUpdate epi{Wold, R, Wnew, ld, Ne, Na, nWrow, nC, dC, rule.alpha, rule.h_undamped, hpart, 0.0};
   // C is symmetric: its row n is the column n the product needs
-  return launch_rect<RectB3D>(OpsB3F{Wh, Wl, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
+  const int64_t Mp = (Nep + RectB3D::BM - 1) / RectB3D::BM * RectB3D::BM;
+  return launch_rect<RectB3D>(OpsB3F{Wh, Wl, ld, C, ld, Nep}, Mp, Nap, Nap, epi, part, gate, s);
 }
 
 int64_t coreg_slots(int64_t Nap) { return Nap / kCB; }
