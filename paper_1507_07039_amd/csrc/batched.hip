@@ -128,8 +128,7 @@ struct PhCoreg {
     const int64_t I = ij & 0xffff, J = ij >> 16;
     G g;
     g.run(OpsF32{W, d.Nap, W, d.Nap}, I * kCB, J * kCB, 0, d.Nep, smem);
-    coreg_epilogue<SIGT>(g, smem, I, J, d.C, d.Nap, d.Na, d.nWc, alpha, d.cstat, d.csq, d.Nap,
-                         nullptr, nullptr);
+    coreg_epilogue<SIGT>(g, smem, I, J, d.C, d.Nap, d.Na, d.nWc, alpha, d.cstat, d.csq, d.Nap);
   }
 };
 

@@ -118,57 +118,75 @@ __device__ __forceinline__ float coreg_sim(float acc, int64_t gr, int64_t gc, in
 }
 
 // Everything of the C update after the similarities of tile (I, J) are
-// known.  Each thread owns kPer entries; fi(f) calls f(q, rr, c) and fv(f)
-// calls f(q, rr, c, tsim) for its q-th entry.  The old values of all owned
-// entries are loaded before any is written (the loads cannot be reordered
-// past stores to the same array, so this keeps them in flight together).
-constexpr int kPer = kCB * kCB / kThreads;
+// known; fv(f) calls f(rr, c, tsim) for every entry the thread holds.  The
+// similarities are staged in LDS first, so that the read-modify-write of C
+// and its mirror image go to memory 16 bytes per lane, row-contiguous.
+constexpr int kC4 = kCB / 4;                     // float4 per tile row
+constexpr int kChunks = kCB * kC4 / kThreads;    // float4 per thread
 
-template <bool SIGT, int CHUNK, class FI, class FV>
-__device__ __forceinline__ void coreg_tile_update(FI&& fi, FV&& fv, char* smem, int64_t I, int64_t J,
+template <bool SIGT, class FV>
+__device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I, int64_t J,
                                                   float* __restrict__ C, int64_t ldc, int64_t Na,
                                                   double alpha, double2* __restrict__ cstat,
-                                                  double* __restrict__ csq, int64_t ldstat,
-                                                  bf16_t* __restrict__ Ch,
-                                                  bf16_t* __restrict__ Cl) {
-  static_assert(kPer % CHUNK == 0, "whole chunks");
+                                                  double* __restrict__ csq, int64_t ldstat) {
+  static_assert(kChunks * kThreads == kCB * kC4, "whole chunks");
   const int64_t m0 = I * kCB, n0 = J * kCB;
-  float* ts = reinterpret_cast<float*>(smem);  // updated values
+  float* ts = reinterpret_cast<float*>(smem);  // fresh T, then the updated values
   float* tt = ts + kCB * kSymLD;               // fresh T (SIGT only)
+  const int t = threadIdx.x;
+  fv([&](int rr, int c, float tsim) {
+    ts[rr * kSymLD + c] = tsim;
+    if constexpr (SIGT) tt[rr * kSymLD + c] = tsim;
+  });
+  __syncthreads();
   const float keep = (float)(1.0 - alpha), alf = (float)alpha;
+  f4 old[kChunks];
 #pragma unroll
-  for (int ch = 0; ch < kPer / CHUNK; ++ch) {  // CHUNK old values in flight at a time
-    float cold[CHUNK];
-    fi([&](int q, int rr, int c) {
-      if (q / CHUNK != ch) return;
-      const int64_t gr = m0 + rr, gc = n0 + c;
-      cold[q % CHUNK] = (gr < gc && gc < Na) ? C[gr * ldc + gc] : 0.0f;
-    });
-    fv([&](int q, int rr, int c, float tsim) {
-      if (q / CHUNK != ch) return;
-      const int64_t gr = m0 + rr, gc = n0 + c;
-      float v = 0.0f;
-      if (gr < gc && gc < Na) {
-        const int64_t o = gr * ldc + gc;
-        v = keep * cold[q % CHUNK] + alf * tsim;
-        C[o] = v;
-        if (Ch) split_bf16(v, Ch[o], Cl[o]);
-      }
-      ts[rr * kSymLD + c] = v;
-      if constexpr (SIGT) tt[rr * kSymLD + c] = tsim;
-    });
+  for (int k = 0; k < kChunks; ++k) {  // all old values in flight together
+    const int id = t + k * kThreads, rr = id / kC4, c = (id % kC4) * 4;
+    old[k] = *reinterpret_cast<const f4*>(C + (m0 + rr) * ldc + n0 + c);
+  }
+#pragma unroll
+  for (int k = 0; k < kChunks; ++k) {
+    const int id = t + k * kThreads, rr = id / kC4, c = (id % kC4) * 4;
+    const int64_t gr = m0 + rr, gc = n0 + c;
+    f4 nv;
+    bool upper[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      upper[e] = gr < gc + e && gc + e < Na;  // strictly upper and real
+      const float v = upper[e] ? keep * old[k][e] + alf * ts[rr * kSymLD + c + e] : 0.0f;
+      nv[e] = upper[e] ? v : old[k][e];
+      ts[rr * kSymLD + c + e] = v;
+    }
+    float* dst = C + gr * ldc + gc;
+    if (I != J) {
+      // every entry of an upper off-diagonal tile is strictly upper; padding
+      // columns keep their zeros
+      *reinterpret_cast<f4*>(dst) = nv;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (upper[e]) dst[e] = nv[e];
+    }
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  // mirror write: C[n0 + q][m0 + p] = ts[p][q] for global m0+p < n0+q
-  for (int e = t; e < kCB * kCB; e += kThreads) {
-    const int q = e / kCB, p = e % kCB;
-    const int64_t gi = m0 + p, gj = n0 + q;
-    if (gi < gj && gj < Na) {
-      const float v = ts[p * kSymLD + q];
-      const int64_t o = gj * ldc + gi;
-      C[o] = v;
-      if (Ch) split_bf16(v, Ch[o], Cl[o]);
+  // mirror: C[n0 + q][m0 + p] = ts[p][q] for the strictly-upper entries
+#pragma unroll 4
+  for (int k = 0; k < kChunks; ++k) {
+    const int id = t + k * kThreads, q = id / kC4, p = (id % kC4) * 4;
+    const int64_t gj = n0 + q, gi = m0 + p;
+    if (gj >= Na) continue;
+    f4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = ts[(p + e) * kSymLD + q];
+    float* dst = C + gj * ldc + gi;
+    if (gi + 3 < gj) {
+      *reinterpret_cast<f4*>(dst) = v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (gi + e < gj) dst[e] = v[e];
     }
   }
   // per-row partial sums of the off-diagonal entries
@@ -216,27 +234,16 @@ __device__ __forceinline__ void coreg_tile_update(FI&& fi, FV&& fv, char* smem, 
   }
 }
 
-// The C update of tile (I, J) from the accumulators of block GEMM g (each
-// thread owns TM * TN * 16 = kPer entries of the 128 x 128 tile).
+// The C update of tile (I, J) from the accumulators of block GEMM g.
 template <bool SIGT, class G>
 __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I, int64_t J,
                                                float* __restrict__ C, int64_t ldc, int64_t Na,
                                                const double* __restrict__ ncol, double alpha,
                                                double2* __restrict__ cstat,
-                                               double* __restrict__ csq, int64_t ldstat,
-                                               bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl) {
+                                               double* __restrict__ csq, int64_t ldstat) {
   static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
-  static_assert(G::TM * G::TN * 16 == kPer, "one accumulator per owned entry");
   const int64_t m0 = I * kCB, n0 = J * kCB;
-  coreg_tile_update<SIGT, 16>(
-      [&](auto&& f) {
-#pragma unroll
-        for (int i = 0; i < G::TM; ++i)
-#pragma unroll
-          for (int j = 0; j < G::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) f((i * G::TN + j) * 16 + r, g.row_of(i, r), g.col_of(j));
-      },
+  coreg_tile_update<SIGT>(
       [&](auto&& f) {
 #pragma unroll
         for (int i = 0; i < G::TM; ++i)
@@ -245,11 +252,10 @@ __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int rr = g.row_of(i, r), c = g.col_of(j);
-              f((i * G::TN + j) * 16 + r, rr, c,
-                coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, ncol));
+              f(rr, c, coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, ncol));
             }
       },
-      smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat, Ch, Cl);
+      smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat);
 }
 
 // Shared memory of the C update with block GEMM G: the larger of the main

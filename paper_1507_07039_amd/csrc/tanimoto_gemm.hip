@@ -23,8 +23,8 @@ template <class G, bool SIGT>
 __global__ __launch_bounds__(kThreads) void k_coreg_update(
     typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
     const double* __restrict__ ncol, double alpha, double2* __restrict__ cstat,
-    double* __restrict__ csq, int64_t ldstat, bf16_t* __restrict__ Ch, bf16_t* __restrict__ Cl,
-    const uint32_t* __restrict__ order, const int32_t* gate) {
+    double* __restrict__ csq, int64_t ldstat, const uint32_t* __restrict__ order,
+    const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ __align__(16) char smem[coreg_smem_bytes<G, SIGT>()];
   const uint32_t ij = order[xcd_tile(blockIdx.x, gridDim.x)];
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kThreads) void k_coreg_update(
   const int64_t m0 = I * kCB, n0 = J * kCB;
   G g;
   g.run(ops, m0, n0, 0, Kp, smem);
-  coreg_epilogue<SIGT>(g, smem, I, J, C, ldc, Na, ncol, alpha, cstat, csq, ldstat, Ch, Cl);
+  coreg_epilogue<SIGT>(g, smem, I, J, C, ldc, Na, ncol, alpha, cstat, csq, ldstat);
 }
 
 // ------------------------------------------------------------------------
@@ -141,17 +141,17 @@ void coreg_order_fill(int64_t Nap, int group, uint32_t* out) {
 template <class G>
 static hipError_t coreg_launch(const typename G::Ops& ops, int64_t Nep, float* C, int64_t ldc,
                                int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
-                               double2* cstat, double* csq, bf16_t* Ch, bf16_t* Cl,
-                               const uint32_t* order, const int32_t* gate, hipStream_t s) {
+                               double2* cstat, double* csq, const uint32_t* order,
+                               const int32_t* gate, hipStream_t s) {
   const unsigned nb = (unsigned)coreg_tiles(Nap);
   if (rule.sigma_from_T)
     k_coreg_update<G, true><<<dim3(nb), dim3(kThreads), 0, s>>>(ops, Nep, C, ldc, Na, nWcol,
-                                                                rule.alpha, cstat, csq, Nap, Ch,
-                                                                Cl, order, gate);
+                                                                rule.alpha, cstat, csq, Nap, order,
+                                                                gate);
   else
     k_coreg_update<G, false><<<dim3(nb), dim3(kThreads), 0, s>>>(ops, Nep, C, ldc, Na, nWcol,
-                                                                 rule.alpha, cstat, csq, Nap, Ch,
-                                                                 Cl, order, gate);
+                                                                 rule.alpha, cstat, csq, Nap, order,
+                                                                 gate);
   return hipGetLastError();
 }
 
@@ -161,7 +161,7 @@ hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* 
                                const int32_t* gate, hipStream_t s) {
   // X = W^T (gene m, tf k) = W[k][m]; Y = W (tf k, gene n) = W[k][n].
   return coreg_launch<SymF32>(OpsF32{W, ldw, W, ldw}, Nep, C, ldc, Nap, Na, nWcol, rule, cstat,
-                              csq, nullptr, nullptr, order, gate, s);
+                              csq, order, gate, s);
 }
 
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
@@ -171,7 +171,7 @@ hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t 
   // X = Yt = W^T stored gene-major: row m of W^T is column m of W.  Only the
   // FP32 C is written; the next A product splits it while staging.
   return coreg_launch<SymB3>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol,
-                             rule, cstat, csq, nullptr, nullptr, order, gate, s);
+                             rule, cstat, csq, order, gate, s);
 }
 
 int coop_splits(int64_t Nep, int64_t Nap) {
