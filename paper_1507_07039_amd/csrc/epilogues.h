@@ -87,7 +87,7 @@ using RectB3 = BlockGemmB3<64, 128, 1, 4>;
 // by clamped reads; the padded rows are computed and dropped.
 using RectB3D = BlockGemmB3P<256, 128, 4, 1>;
 using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
-using SymB3 = BlockGemmB3<128, 128, 2, 2>;
+using SymB3 = BlockGemmB3P<128, 128, 2, 2, false, 2>;  // direct-to-LDS, two stages (two blocks per CU)
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;
 using CoopB3 = BlockGemmB3<64, 64, 2, 2>;
 static_assert(RectF32::BM == RectB3::BM && RectF32::BN == RectB3::BN, "one tile grid");

@@ -497,9 +497,12 @@ __device__ __forceinline__ void split_pair(float a, float b, unsigned& h, unsign
   l = __builtin_bit_cast(unsigned, __builtin_convertvector((fl2){a - ha, b - hb}, bh2));
 }
 
-template <int BM_, int BN_, int WM, int WN>
+// YF32: Y is the FP32 symmetric matrix split as its fragments are read;
+// otherwise Y is given as bf16 hi/lo planes like X (no split arithmetic).
+// The STAGES stage buffers are carved from the caller's shared memory.
+template <int BM_, int BN_, int WM, int WN, bool YF32 = true, int STAGES = 3>
 struct BlockGemmB3P {
-  using Ops = OpsB3F;
+  using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
   static constexpr int BM = BM_, BN = BN_, BK = 32, NT = 64 * WM * WN;
   static constexpr int WAVES = WM * WN;
   static constexpr int WAVES_PER_EU = 1;
@@ -507,17 +510,27 @@ struct BlockGemmB3P {
   static constexpr int TN = BN / WN / 32;
   static constexpr int KS = BK / 16;
   static_assert(TM >= 1 && TN >= 1 && KS == 2, "two 16-deep k-steps per K-tile");
+  static_assert(STAGES == 2 || STAGES == 3, "two or three stages");
   using PX = TileLoadB3<BM, NT, BK>;  // swizzle of the bf16 planes
+  using PY = TileLoadB3<BN, NT, BK>;
   static constexpr int CPR = BK / 8;  // 16-byte chunks per bf16 row
   static constexpr int XQ = BM * CPR; // chunks per X plane
-  static constexpr int YQ = BN * (BK / 4);  // chunks of the FP32 Y tile
+  static constexpr int YQ = YF32 ? BN * (BK / 4) : 2 * BN * CPR;  // chunks of the Y tile
   static constexpr int STAGE_BYTES = (2 * XQ + YQ) * 16;
-  static constexpr int MAIN_BYTES = 16;  // the stages are run()'s own LDS objects
+  static constexpr int MAIN_BYTES = STAGES * STAGE_BYTES;
   static constexpr int XI = 2 * XQ / 64, YI = YQ / 64;  // wave-instructions per stage
   static_assert((2 * XQ) % 64 == 0 && YQ % 64 == 0 && (XI + YI) % WAVES == 0, "load split");
   static constexpr int IPW = (XI + YI) / WAVES;  // loads per wave and stage
   static constexpr int PER = 2 * TM + 2 * TN;   // 16-byte fragment reads per k-step
   static constexpr int NR = KS * PER;
+  // This wave's loads of one stage: wave-instruction q * WAVES + w of the
+  // stage, so which operand (and plane) a load q reads is fixed at compile
+  // time.
+  static constexpr int XPW = XI / WAVES;  // X loads per wave (both planes)
+  static constexpr int XPP = XPW / 2;     // ... per plane
+  static constexpr int YPP = YI / WAVES / 2;  // Y loads per wave and plane (bf16 Y)
+  static_assert(XI % (2 * WAVES) == 0, "X planes split evenly over the waves");
+  static_assert(YF32 || YI % (2 * WAVES) == 0, "Y planes split evenly over the waves");
 
   floatx16 acc[TM][TN];
   int lane, wm, wn;
@@ -528,18 +541,15 @@ struct BlockGemmB3P {
   struct Raw {
     u4 r[NR];
   };
-  // This wave's loads of one stage: wave-instruction q * WAVES + w of the
-  // stage, so which operand a load q reads is fixed at compile time.
-  static constexpr int XPW = XI / WAVES;        // X loads per wave (both planes)
-  static constexpr int XPP = XPW / 2;           // ... per plane
-  static_assert(XI % (2 * WAVES) == 0, "planes split evenly over the waves");
   struct Dma {
     const char* xh;  // uniform bases at K-tile 0 of the range
     const char* xl;
-    const char* y;
+    const char* yh;  // Y (FP32) or its hi plane
+    const char* yl;
     unsigned voff[IPW];  // per lane
     unsigned wofs;       // this wave's LDS offset within a stage
   };
+  static constexpr int YSTEP = YF32 ? BK * 4 : BK * 2;  // bytes per K-tile along a Y row
 
   __device__ __forceinline__ static unsigned lds_addr(const void* p) {
     return (unsigned)(size_t)(const __attribute__((address_space(3))) char*)p;
@@ -549,7 +559,13 @@ struct BlockGemmB3P {
                                         Dma& d) const {
     d.xh = reinterpret_cast<const char*>(o.Xh + m0 * o.ldx + kbeg);
     d.xl = reinterpret_cast<const char*>(o.Xl + m0 * o.ldx + kbeg);
-    d.y = reinterpret_cast<const char*>(o.Y + n0 * o.ldy + kbeg);
+    if constexpr (YF32) {
+      d.yh = reinterpret_cast<const char*>(o.Y + n0 * o.ldy + kbeg);
+      d.yl = d.yh;
+    } else {
+      d.yh = reinterpret_cast<const char*>(o.Yh + n0 * o.ldy + kbeg);
+      d.yl = reinterpret_cast<const char*>(o.Yl + n0 * o.ldy + kbeg);
+    }
     d.wofs = (unsigned)w * 1024u;
 #pragma unroll
     for (int q = 0; q < IPW; ++q) {
@@ -557,32 +573,47 @@ struct BlockGemmB3P {
         const int p = ((q % XPP) * WAVES + w) * 64 + lane;  // chunk within the plane
         const int r = p / CPR, slot = p % CPR;
         const int chunk = slot ^ ((r / PX::RG) & (CPR - 1));
-        // rows past the operand's end (M padded to the tile) re-read its last
-        // row; their outputs are never stored
-        const int64_t rr = (m0 + r < o.mrows ? m0 + r : o.mrows - 1) - m0;
+        int64_t rr = r;
+        if constexpr (YF32) {
+          // rows past the operand's end (M padded to the tile) re-read its
+          // last row; their outputs are never stored
+          rr = (m0 + r < o.mrows ? m0 + r : o.mrows - 1) - m0;
+        }
         d.voff[q] = (unsigned)((rr * o.ldx + chunk * 8) * 2);
-      } else {
+      } else if constexpr (YF32) {
         const int p = ((q - XPW) * WAVES + w) * 64 + lane;
         const int r = p / (BK / 4), slot = p % (BK / 4);
         const int chunk = slot ^ ((r >> 1) & 7);
         d.voff[q] = (unsigned)(((int64_t)r * o.ldy + chunk * 4) * 4);
+      } else {
+        const int p = (((q - XPW) % YPP) * WAVES + w) * 64 + lane;
+        const int r = p / CPR, slot = p % CPR;
+        const int chunk = slot ^ ((r / PY::RG) & (CPR - 1));
+        d.voff[q] = (unsigned)(((int64_t)r * o.ldy + chunk * 8) * 2);
       }
     }
   }
 
+  // Direct load q of K-tile kt into the stage at LDS address sb (this wave's
+  // part of it).
+  __device__ __forceinline__ static void dma_at(const Dma& d, int q, int kt, unsigned sb) {
+    const char* b;
+    if (q < XPP)
+      b = d.xh + (size_t)kt * (BK * 2);
+    else if (q < XPW)
+      b = d.xl + (size_t)kt * (BK * 2);
+    else if (YF32 || q < XPW + YPP)
+      b = d.yh + (size_t)kt * YSTEP;
+    else
+      b = d.yl + (size_t)kt * YSTEP;
+    lds_dma16(d.voff[q], b, sb + d.wofs + (unsigned)(q * WAVES) * 1024u);
+  }
   __device__ __forceinline__ static void issue(const Dma& d, int kt, const char* st) {
-    const unsigned sb = lds_addr(st) + d.wofs;
-    const char* xh = d.xh + (size_t)kt * (BK * 2);
-    const char* xl = d.xl + (size_t)kt * (BK * 2);
-    const char* y = d.y + (size_t)kt * (BK * 4);
 #pragma unroll
-    for (int q = 0; q < IPW; ++q) {
-      const char* b = q < XPP ? xh : q < XPW ? xl : y;
-      lds_dma16(d.voff[q], b, sb + (unsigned)(q * WAVES) * 1024u);
-    }
+    for (int q = 0; q < IPW; ++q) dma_at(d, q, kt, lds_addr(st));
   }
 
-  // Byte offsets (within a stage) of this lane's 16 fragment reads.
+  // Byte offsets (within a stage) of this lane's fragment reads.
   __device__ __forceinline__ void read_offsets(unsigned (&ad)[NR]) const {
     const int mrow = wm * (BM / WM) + (lane & 31);
     const int khalf = lane >> 5;
@@ -599,10 +630,16 @@ struct BlockGemmB3P {
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int n = wn * (BN / WN) + j * 32 + (lane & 31);
-        const unsigned yb = 2u * XQ * 16 + 4u * n * BK;
-        const int f = (n >> 1) & 7;  // rows n and n + 8 in different bank halves
-        ad[PER * ks + 2 * TM + 2 * j] = yb + 4u * ((c0 ^ f) << 2);
-        ad[PER * ks + 2 * TM + 2 * j + 1] = yb + 4u * (((c0 + 1) ^ f) << 2);
+        if constexpr (YF32) {
+          const unsigned yb = 2u * XQ * 16 + 4u * n * BK;
+          const int f = (n >> 1) & 7;  // rows n and n + 8 in different bank halves
+          ad[PER * ks + 2 * TM + 2 * j] = yb + 4u * ((c0 ^ f) << 2);
+          ad[PER * ks + 2 * TM + 2 * j + 1] = yb + 4u * (((c0 + 1) ^ f) << 2);
+        } else {
+          const unsigned off = 2u * XQ * 16 + 2u * PY::swz(n, chunk);
+          ad[PER * ks + 2 * TM + 2 * j] = off;                     // hi plane
+          ad[PER * ks + 2 * TM + 2 * j + 1] = off + 2u * BN * BK;  // lo plane
+        }
       }
     }
   }
@@ -612,7 +649,24 @@ struct BlockGemmB3P {
     for (int i = 0; i < NR; ++i) rw.r[i] = *reinterpret_cast<const u4*>(st + ad[i]);
   }
 
-  __device__ __forceinline__ static void split(const Raw& rw, Frag& f) {
+  // Split pair sp of the next tile's FP32 Y fragments (4 pairs per fragment).
+  __device__ __forceinline__ static void split_at(const Raw& rw, unsigned (&h)[KS][TN][4],
+                                                  unsigned (&l)[KS][TN][4], int sp) {
+    const int fi = sp / 4, pr = sp % 4, ks = fi / TN, j = fi % TN;
+    const f4 v = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j + pr / 2]);
+    if (pr % 2 == 0)
+      split_pair(v.x, v.y, h[ks][j][pr], l[ks][j][pr]);
+    else
+      split_pair(v.z, v.w, h[ks][j][pr], l[ks][j][pr]);
+    // keep the pair here, between its MFMAs (the compiler would otherwise sink
+    // it to the end of the K-tile, next to its first use)
+    asm volatile("" : "+v"(h[ks][j][pr]), "+v"(l[ks][j][pr]));
+  }
+  static constexpr int NSP = YF32 ? KS * TN * 4 : 0;  // split pairs per K-tile
+
+  // Fragments of a K-tile from its LDS reads (and split pairs).
+  __device__ __forceinline__ static void assemble(const Raw& rw, const unsigned (&h)[KS][TN][4],
+                                                  const unsigned (&l)[KS][TN][4], Frag& f) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
@@ -622,17 +676,21 @@ struct BlockGemmB3P {
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const f4 a = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j]);
-        const f4 b = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j + 1]);
-        unsigned h0, h1, h2, h3, l0, l1, l2, l3;
-        split_pair(a.x, a.y, h0, l0);
-        split_pair(a.z, a.w, h1, l1);
-        split_pair(b.x, b.y, h2, l2);
-        split_pair(b.z, b.w, h3, l3);
-        f.yh[ks][j] = __builtin_bit_cast(bf16x8, (u4){h0, h1, h2, h3});
-        f.yl[ks][j] = __builtin_bit_cast(bf16x8, (u4){l0, l1, l2, l3});
+        if constexpr (YF32) {
+          f.yh[ks][j] = __builtin_bit_cast(bf16x8, (u4){h[ks][j][0], h[ks][j][1], h[ks][j][2], h[ks][j][3]});
+          f.yl[ks][j] = __builtin_bit_cast(bf16x8, (u4){l[ks][j][0], l[ks][j][1], l[ks][j][2], l[ks][j][3]});
+        } else {
+          f.yh[ks][j] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * TM + 2 * j]);
+          f.yl[ks][j] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * TM + 2 * j + 1]);
+        }
       }
     }
+  }
+  __device__ __forceinline__ static void split(const Raw& rw, Frag& f) {
+    unsigned h[KS][TN][4], l[KS][TN][4];
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp) split_at(rw, h, l, sp);
+    assemble(rw, h, l, f);
   }
 
   __device__ __forceinline__ void mfma(const Frag& f) {
@@ -647,7 +705,6 @@ struct BlockGemmB3P {
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
         }
   }
-
   // One MFMA of a K-tile: m = ((ks * TM + i) * TN + j) * 3 + product, the
   // order of mfma() (so results are the same bit for bit).
   __device__ __forceinline__ void mfma_at(const Frag& f, int m) {
@@ -659,49 +716,29 @@ struct BlockGemmB3P {
     else
       acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
   }
-  // Split pair sp of the next tile's Y fragments (4 pairs per fragment).
-  __device__ __forceinline__ static void split_at(const Raw& rw, unsigned (&h)[KS][TN][4],
-                                                  unsigned (&l)[KS][TN][4], int sp) {
-    const int fi = sp / 4, pr = sp % 4, ks = fi / TN, j = fi % TN;
-    const f4 v = __builtin_bit_cast(f4, rw.r[PER * ks + 2 * TM + 2 * j + pr / 2]);
-    if (pr % 2 == 0)
-      split_pair(v.x, v.y, h[ks][j][pr], l[ks][j][pr]);
-    else
-      split_pair(v.z, v.w, h[ks][j][pr], l[ks][j][pr]);
-    // keep the pair here, between its MFMAs (the compiler would otherwise sink
-    // it to the end of the K-tile, next to its first use)
-    asm volatile("" : "+v"(h[ks][j][pr]), "+v"(l[ks][j][pr]));
-  }
 
-  // K-tile kt whose three successors exist: stage `rd` holds tile kt + 1,
-  // stage `fr` held tile kt (already in registers) and takes tile kt + 3.
-  // The MFMAs of tile kt are issued one by one, each followed by work of
-  // the next tile that does not depend on them: first the direct loads of
-  // tile kt + 3 and the LDS reads of tile kt + 1, then the split of tile
-  // kt + 1's C fragments.  Scheduling barriers keep this order (the matrix
-  // core runs each MFMA while the wave issues what follows it).
+  // K-tile kt whose STAGES successors exist: stage `rd` holds tile kt + 1,
+  // stage `fr` held tile kt (already in registers) and takes tile
+  // kt + STAGES.  The MFMAs of tile kt are issued one by one, each followed
+  // by work of the next tile that does not depend on them: first the direct
+  // loads of tile kt + STAGES and the LDS reads of tile kt + 1, then the
+  // split of tile kt + 1's C fragments.  Scheduling barriers keep this order
+  // (the matrix core runs each MFMA while the wave issues what follows it).
   __device__ __forceinline__ void full_step(const Dma& d, const unsigned (&ad)[NR], int kt,
                                             const char* rd, const char* fr, Frag& cur) {
     constexpr int NM = KS * TM * TN * 3;  // MFMAs per K-tile
-    constexpr int NSP = KS * TN * 4;      // split pairs per K-tile
     constexpr int NRM = (NR + 1) / 2;     // MFMAs followed by reads
     static_assert(IPW <= NM, "one direct load per MFMA slot at most");
-    wait_vmem<IPW>();  // tile kt + 1 landed (tile kt + 2 may be in flight)
+    wait_vmem<(STAGES - 2) * IPW>();  // tile kt + 1 landed (later ones may be in flight)
     wave_barrier_mem();
     __builtin_amdgcn_sched_barrier(0);
-    const unsigned sb = lds_addr(fr) + d.wofs;
-    const char* xh = d.xh + (size_t)(kt + 3) * (BK * 2);
-    const char* xl = d.xl + (size_t)(kt + 3) * (BK * 2);
-    const char* y = d.y + (size_t)(kt + 3) * (BK * 4);
+    const unsigned sb = lds_addr(fr);
     Raw rw;
     unsigned h[KS][TN][4], l[KS][TN][4];
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
       mfma_at(cur, m);
-      if (m < IPW) {
-        const char* b = m < XPP ? xh : m < XPW ? xl : y;
-        lds_dma16(d.voff[m], b, sb + (unsigned)(m * WAVES) * 1024u);
-      }
+      if (m < IPW) dma_at(d, m, kt + STAGES, sb);
       if (m < NRM) {
 #pragma unroll
         for (int r = 2 * m; r < 2 * m + 2 && r < NR; ++r)
@@ -712,31 +749,17 @@ struct BlockGemmB3P {
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int m = NM; m < NRM + NSP; ++m) {  // split pairs left over (none for these shapes)
-      split_at(rw, h, l, m - NRM);
-    }
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        cur.xh[ks][i] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * i]);
-        cur.xl[ks][i] = __builtin_bit_cast(bf16x8, rw.r[PER * ks + 2 * i + 1]);
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        cur.yh[ks][j] = __builtin_bit_cast(bf16x8, (u4){h[ks][j][0], h[ks][j][1], h[ks][j][2], h[ks][j][3]});
-        cur.yl[ks][j] = __builtin_bit_cast(bf16x8, (u4){l[ks][j][0], l[ks][j][1], l[ks][j][2], l[ks][j][3]});
-      }
-    }
+    for (int m = NM; m < NRM + NSP; ++m) split_at(rw, h, l, m - NRM);  // left over
+    assemble(rw, h, l, cur);
   }
 
   // Any K-tile (near the end of the range): the same with bounds.
   __device__ __forceinline__ void tail_step(const Dma& d, const unsigned (&ad)[NR], int kt, int nk,
                                             const char* rd, const char* fr, Frag& cur) {
     if (kt + 1 < nk) {
-      if (kt + 2 < nk) wait_vmem<IPW>(); else wait_vmem<0>();
+      if (STAGES == 3 && kt + 2 < nk) wait_vmem<IPW>(); else wait_vmem<0>();
       wave_barrier_mem();
-      if (kt + 3 < nk) issue(d, kt + 3, fr);
+      if (kt + STAGES < nk) issue(d, kt + STAGES, fr);
       Raw rw;
       read(rd, ad, rw);
       mfma(cur);
@@ -747,10 +770,10 @@ struct BlockGemmB3P {
   }
 
   __device__ __forceinline__ void run(const Ops& o, int64_t m0, int64_t n0, int64_t kbeg,
-                                      int64_t kend, char*) {
-    __shared__ __align__(16) char s0[STAGE_BYTES];
-    __shared__ __align__(16) char s1[STAGE_BYTES];
-    __shared__ __align__(16) char s2[STAGE_BYTES];
+                                      int64_t kend, char* smem) {
+    char* const s0 = smem;
+    char* const s1 = smem + STAGE_BYTES;
+    char* const s2 = smem + (STAGES == 3 ? 2 * STAGE_BYTES : 0);
     lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     wm = w % WM;
@@ -762,8 +785,8 @@ struct BlockGemmB3P {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     const int nk = (int)((kend - kbeg) / BK);
-    // Every wave of the block is done with the stages (its reads of the
-    // previous range fed MFMAs before its epilogue).
+    // Every wave of the block is done with the stages (and with whatever the
+    // caller kept in the same shared memory).
     wait_vmem<0>();
     wave_barrier_mem();
     if (nk <= 0) return;
@@ -779,7 +802,7 @@ struct BlockGemmB3P {
       wait_vmem<0>();
     }
     wave_barrier_mem();
-    if (nk > 2) issue(d, 2, s2);
+    if (STAGES == 3 && nk > 2) issue(d, 2, s2);
     Frag cur;
     {
       Raw rw;
@@ -787,17 +810,30 @@ struct BlockGemmB3P {
       split(rw, cur);
     }
     int kt = 0;
-    for (; kt + 5 < nk; kt += 3) {
-      full_step(d, ad, kt, s1, s0, cur);
-      full_step(d, ad, kt + 1, s2, s1, cur);
-      full_step(d, ad, kt + 2, s0, s2, cur);
+    if constexpr (STAGES == 3) {
+      for (; kt + 5 < nk; kt += 3) {
+        full_step(d, ad, kt, s1, s0, cur);
+        full_step(d, ad, kt + 1, s2, s1, cur);
+        full_step(d, ad, kt + 2, s0, s2, cur);
+      }
+      for (; kt < nk; ++kt) {
+        const int ph = kt % 3;
+        const char* rd = ph == 0 ? s1 : ph == 1 ? s2 : s0;
+        const char* fr = ph == 0 ? s0 : ph == 1 ? s1 : s2;
+        tail_step(d, ad, kt, nk, rd, fr, cur);
+      }
+    } else {
+      for (; kt + 3 < nk; kt += 2) {
+        full_step(d, ad, kt, s1, s0, cur);
+        full_step(d, ad, kt + 1, s0, s1, cur);
+      }
+      for (; kt < nk; ++kt) {
+        const bool ph = kt % 2;
+        tail_step(d, ad, kt, nk, ph ? s0 : s1, ph ? s1 : s0, cur);
+      }
     }
-    for (; kt < nk; ++kt) {
-      const int ph = kt % 3;
-      const char* rd = ph == 0 ? s1 : ph == 1 ? s2 : s0;
-      const char* fr = ph == 0 ? s0 : ph == 1 ? s1 : s2;
-      tail_step(d, ad, kt, nk, rd, fr, cur);
-    }
+    // the caller may reuse the shared memory once every wave has read its last stage
+    wave_barrier_mem();
   }
 
   __device__ __forceinline__ int row_of(int i, int r) const {

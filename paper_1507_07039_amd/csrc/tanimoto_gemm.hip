@@ -18,9 +18,10 @@ namespace {
 
 using namespace gemm;
 
-// The product of the tile, then the update in its epilogue.
+// The product of the tile, then the update in its epilogue (two blocks per
+// CU, so one block's epilogue overlaps the other's products).
 template <class G, bool SIGT>
-__global__ __launch_bounds__(kThreads) void k_coreg_update(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_coreg_update(
     typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
     const double* __restrict__ ncol, double alpha, double2* __restrict__ cstat,
     double* __restrict__ csq, int64_t ldstat, const uint32_t* __restrict__ order,
