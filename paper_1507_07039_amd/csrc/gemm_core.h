@@ -705,10 +705,12 @@ struct BlockGemmB3P {
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yh[ks][j], acc[i][j], 0, 0, 0);
         }
   }
-  // One MFMA of a K-tile: m = ((ks * TM + i) * TN + j) * 3 + product, the
-  // order of mfma() (so results are the same bit for bit).
+  // One MFMA of a K-tile: m = ((ks * 3 + product) * TM + i) * TN + j.  Each
+  // accumulator sees its products in the order of mfma() (so results are
+  // the same bit for bit), while consecutive MFMAs go to different
+  // accumulators and never wait for each other.
   __device__ __forceinline__ void mfma_at(const Frag& f, int m) {
-    const int p = m % 3, j = (m / 3) % TN, i = (m / 3 / TN) % TM, ks = m / 3 / TN / TM;
+    const int j = m % TN, i = (m / TN) % TM, p = (m / TN / TM) % 3, ks = m / TN / TM / 3;
     if (p == 0)
       acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[ks][i], f.yl[ks][j], acc[i][j], 0, 0, 0);
     else if (p == 1)

@@ -86,7 +86,7 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   double* nc = cv.take<double>((size_t)Nap);
   double* nwr = cv.take<double>((size_t)Nep);
   double* nwc = cv.take<double>((size_t)Nap);
-  double* scr = cv.take<double>((size_t)kColChunks * (size_t)Nap);
+  double* scr = cv.take<double>(w_norm_scratch_doubles(Nep, Nap));
   const int64_t nh = spec.hpart_tiles;
   double* hp = cv.take<double>((size_t)nh);
   double2* cs = cv.take<double2>((size_t)coreg_slots(Nap) * Nap);
@@ -253,11 +253,8 @@ panda_status enqueue_iteration(panda_ctx* c) {
   PANDA_TRY(mark(c, PANDA_PHASE_H));
   HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
   // squared norms (and split planes) of the new W
-  HIP_TRY(launch_row_sqnorms(Wnew, c->Ne, c->Na, c->Nap, c->nWr, run_pc, s));
-  HIP_TRY(launch_col_sqnorms(Wnew, c->Ne, c->Na, c->Nap, c->nWc, c->colscr, run_pc, s));
-  if (c->b3)
-    HIP_TRY(launch_w_shadows(Wnew, c->Ne, c->Na, c->Nap, c->Wh, c->Wl, c->Wth, c->Wtl, c->Nep,
-                             run_pc, s));
+  HIP_TRY(launch_w_norms(Wnew, c->Ne, c->Na, c->Nap, c->Nep, c->nWr, c->nWc, c->colscr, c->Wh,
+                         c->Wl, c->Wth, c->Wtl, c->Nep, run_pc, s));
   PANDA_TRY(mark(c, PANDA_PHASE_PPART));
   // Eq. 5, P: T(W_i., W_m.) of the new W
   if (c->b3)
@@ -497,8 +494,6 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
   HIP_TRY(hipMemsetAsync(c->nWc, 0, (size_t)Nap * 8, s));
   HIP_TRY(launch_row_sqnorms(c->P, Ne, Ne, Nep, c->nP, nullptr, s));
   HIP_TRY(launch_col_sqnorms(c->C, Na, Na, Nap, c->nC, c->colscr, nullptr, s));
-  HIP_TRY(launch_row_sqnorms(c->W[0], Ne, Na, Nap, c->nWr, nullptr, s));
-  HIP_TRY(launch_col_sqnorms(c->W[0], Ne, Na, Nap, c->nWc, c->colscr, nullptr, s));
   // the diagonals of P and C move to their FP64 vectors (zero in the matrices)
   HIP_TRY(launch_take_diag(c->P, Ne, Nep, c->dP, s));
   HIP_TRY(launch_take_diag(c->C, Na, Nap, c->dC, s));
@@ -511,9 +506,12 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
     HIP_TRY(hipMemsetAsync(c->Wtl, 0, nw * 2, s));
     HIP_TRY(hipMemsetAsync(c->Ph, 0, (size_t)Nep * Nep * 2, s));
     HIP_TRY(hipMemsetAsync(c->Pl, 0, (size_t)Nep * Nep * 2, s));
-    HIP_TRY(launch_w_shadows(c->W[0], Ne, Na, Nap, c->Wh, c->Wl, c->Wth, c->Wtl, Nep, nullptr, s));
     HIP_TRY(launch_split_offdiag(c->P, Ne, Nep, c->Ph, c->Pl, s));
   }
+  // norms (and planes) of W exactly as an iteration computes them, so a
+  // stored state resumes bit for bit
+  HIP_TRY(launch_w_norms(c->W[0], Ne, Na, Nap, Nep, c->nWr, c->nWc, c->colscr, c->Wh, c->Wl,
+                         c->Wth, c->Wtl, Nep, nullptr, s));
   PANDA_TRY(ctx_fill_order(c));
   HIP_TRY(launch_state_init(c->st, t, s));
   c->t0 = t;

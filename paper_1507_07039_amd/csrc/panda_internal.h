@@ -121,10 +121,6 @@ hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ld
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s);
 // hi/lo planes of W (Ne x Na, leading dimension ldw) row-major (ld ldw) and
-// transposed (Na x Ne, leading dimension ldt).
-hipError_t launch_w_shadows(const float* W, int64_t Ne, int64_t Na, int64_t ldw, bf16_t* Wh,
-                            bf16_t* Wl, bf16_t* Wth, bf16_t* Wtl, int64_t ldt, const int32_t* gate,
-                            hipStream_t s);
 // hi/lo planes of an n x n matrix with its diagonal left zero.
 hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* Mh, bf16_t* Ml,
                                 hipStream_t s);
@@ -154,6 +150,13 @@ hipError_t launch_put_diag(float* M, int64_t n, int64_t ld, const double* d, hip
 hipError_t launch_state_set(DevState* st, int32_t t, int32_t active, int32_t run_pc,
                             hipStream_t s);
 // Squared norms of the rows / columns of a rows x cols matrix with leading
+// Row and column squared norms of W (padded Nep x ldw, real Ne x Na) in one
+// pass over it, plus its bf16 planes (row-major and gene-major, leading
+// dimension ldt) when Wh is given.  scr holds w_norm_scratch_doubles().
+size_t w_norm_scratch_doubles(int64_t Nep, int64_t Nap);
+hipError_t launch_w_norms(const float* W, int64_t Ne, int64_t Na, int64_t ldw, int64_t Nep,
+                          double* nr, double* nc, double* scr, bf16_t* Wh, bf16_t* Wl, bf16_t* Wth,
+                          bf16_t* Wtl, int64_t ldt, const int32_t* gate, hipStream_t s);
 // dimension ld.  The column version needs kColChunks * cols doubles of scratch.
 hipError_t launch_row_sqnorms(const float* M, int64_t rows, int64_t cols, int64_t ld, double* out,
                               const int32_t* gate, hipStream_t s);

@@ -136,6 +136,24 @@ __device__ __forceinline__ void diag_p_row(int64_t i, const float* __restrict__ 
 
 // Eq. 6 for row r of C (one thread), from the per-slot (sum, sum of squares)
 // written by the C update (slot stride = ldc, the padded N_a): the new
+// Eq. 6 for C_rr from the sum s1 and the sum of squares s2 of the
+// off-diagonal entries of row r, and the sum of squares c2 of the updated
+// entries (the squared column norm without the diagonal).
+__device__ __forceinline__ void diag_c_finish(int64_t r, double s1, double s2, double c2,
+                                              double* __restrict__ dC, int64_t Ne, int64_t Na,
+                                              double* __restrict__ nC, const DiagRule& dr) {
+  double var = 0.0;
+  if (Na > 1) {
+    const double n = (double)(Na - 1), mean = s1 / n;
+    var = s2 / n - mean * mean;
+    if (var < 0.0) var = 0.0;
+  }
+  const double mult = dr.n_own ? (double)Na : (double)Ne;
+  const double dn = (double)(float)(dr.keep * dC[r] + dr.f * mult * sqrt(var) * dr.g);
+  dC[r] = dn;
+  nC[r] = c2 + dn * dn;
+}
+
 // diagonal dC[r] (FP64) and |C_.r|^2 for the next iteration.
 __device__ __forceinline__ void diag_c_row(int64_t r, double* __restrict__ dC, int64_t ldc,
                                            int64_t Ne, int64_t Na,
@@ -150,16 +168,7 @@ __device__ __forceinline__ void diag_c_row(int64_t r, double* __restrict__ dC, i
     if (csq) c2 += csq[sl * ldc + r];
   }
   if (!csq) c2 = s2;
-  double var = 0.0;
-  if (Na > 1) {
-    const double n = (double)(Na - 1), mean = s1 / n;
-    var = s2 / n - mean * mean;
-    if (var < 0.0) var = 0.0;
-  }
-  const double mult = dr.n_own ? (double)Na : (double)Ne;
-  const double dn = (double)(float)(dr.keep * dC[r] + dr.f * mult * sqrt(var) * dr.g);
-  dC[r] = dn;
-  nC[r] = c2 + dn * dn;
+  diag_c_finish(r, s1, s2, c2, dC, Ne, Na, nC, dr);
 }
 
 // |M_r.|^2 of one row (one block).

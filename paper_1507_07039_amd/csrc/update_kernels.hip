@@ -47,8 +47,31 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     upd::diag_p_row(blockIdx.x, P, ldp, dP, Ne, Na, Tside, nP, dr, red);
     return;
   }
-  const int64_t r = ((int64_t)blockIdx.x - Ne) * kRT + threadIdx.x;
-  if (r < Na) upd::diag_c_row(r, dC, ldc, Ne, Na, cstat, csq, nslots, nC, dr);
+  // C: 64 rows per block; wave w adds slots w, w + 4, ... and wave 0 adds
+  // the four partial sums in wave order
+  __shared__ double3 part[kRT / 64][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = ((int64_t)blockIdx.x - Ne) * 64 + lane;
+  double s1 = 0.0, s2 = 0.0, c2 = 0.0;
+  if (r < Na) {
+    for (int64_t sl = w; sl < nslots; sl += kRT / 64) {
+      const double2 v = cstat[sl * ldc + r];
+      s1 += v.x;
+      s2 += v.y;
+      if (csq) c2 += csq[sl * ldc + r];
+    }
+  }
+  part[w][lane] = make_double3(s1, s2, c2);
+  __syncthreads();
+  if (w == 0 && r < Na) {
+    double3 t = part[0][lane];
+    for (int k = 1; k < kRT / 64; ++k) {
+      t.x += part[k][lane].x;
+      t.y += part[k][lane].y;
+      t.z += part[k][lane].z;
+    }
+    upd::diag_c_finish(r, t.x, t.y, csq ? t.z : t.y, dC, Ne, Na, nC, dr);
+  }
 }
 
 // d[i] = M[i][i] and M[i][i] = 0: the diagonal moves to its FP64 vector.
@@ -68,43 +91,7 @@ __global__ __launch_bounds__(kRT) void k_put_diag(float* __restrict__ M, int64_t
 }
 
 // ---- split-BF16 operand planes ----------------------------------------------
-// 64 x 64 tiles of W through LDS: row-major planes written along rows, the
-// transposed planes along genes, both coalesced.  Only the real Ne x Na
-// region is written; the padding of the planes stays zero.
-__global__ __launch_bounds__(kRT) void k_w_shadows(const float* __restrict__ W, int64_t Ne,
-                                                   int64_t Na, int64_t ldw, bf16_t* __restrict__ Wh,
-                                                   bf16_t* __restrict__ Wl,
-                                                   bf16_t* __restrict__ Wth,
-                                                   bf16_t* __restrict__ Wtl, int64_t ldt,
-                                                   const int32_t* gate) {
-  __shared__ float tile[64][65];
-  if (gate && *gate == 0) return;
-  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr, c = c0 + tx;
-    float v = 0.0f;
-    if (r < Ne && c < Na) {
-      v = W[r * ldw + c];
-      bf16_t h, l;
-      split_bf16(v, h, l);
-      Wh[r * ldw + c] = h;
-      Wl[r * ldw + c] = l;
-    }
-    tile[rr][tx] = v;
-  }
-  __syncthreads();
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t c = c0 + cc, r = r0 + tx;
-    if (r < Ne && c < Na) {
-      bf16_t h, l;
-      split_bf16(tile[tx][cc], h, l);
-      Wth[c * ldt + r] = h;
-      Wtl[c * ldt + r] = l;
-    }
-  }
-}
-
+// Planes of P without its diagonal (which lives in its FP64 vector).
 __global__ __launch_bounds__(kRT) void k_split_offdiag(const float* __restrict__ M, int64_t n,
                                                        int64_t ld, bf16_t* __restrict__ Mh,
                                                        bf16_t* __restrict__ Ml) {
@@ -119,6 +106,92 @@ __global__ __launch_bounds__(kRT) void k_split_offdiag(const float* __restrict__
 }
 
 // ---- squared norms --------------------------------------------------------
+// Squared norms of the rows and columns of W in one pass (Eq. 9 needs
+// |W_i.|^2 and |W_.j|^2), and with SHADOW also its bf16 hi/lo planes,
+// row-major and gene-major (only the real Ne x Na region is written; the
+// padding of the planes stays zero).  Block (bx, by) takes the 64 x 64 tile
+// at rows 64 by, columns 64 bx and writes FP64 partial sums: rowpart[bx][r]
+// over its 64 columns, colpart[by][c] over its 64 rows; k_w_norms_sum adds
+// them up in block order (deterministic).
+template <bool SHADOW>
+__global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, int64_t Ne,
+                                                 int64_t Na, int64_t ldw, int64_t Nep,
+                                                 double* __restrict__ rowpart,
+                                                 double* __restrict__ colpart,
+                                                 bf16_t* __restrict__ Wh, bf16_t* __restrict__ Wl,
+                                                 bf16_t* __restrict__ Wth,
+                                                 bf16_t* __restrict__ Wtl, int64_t ldt,
+                                                 const int32_t* gate) {
+  __shared__ float tile[64][65];
+  __shared__ double cred[4][64];
+  if (gate && *gate == 0) return;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  double cs = 0.0;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    float v = 0.0f;
+    if (r < Ne && c < Na) {
+      v = W[r * ldw + c];
+      if constexpr (SHADOW) {
+        bf16_t h, l;
+        split_bf16(v, h, l);
+        Wh[r * ldw + c] = h;
+        Wl[r * ldw + c] = l;
+      }
+    }
+    if constexpr (SHADOW) tile[rr][tx] = v;
+    const double q = (double)v * (double)v;
+    cs += q;
+    double rs = q;  // this row's 64 entries sit in the 64 lanes of the wave
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rs += __shfl_xor(rs, off);
+    if (tx == 0) rowpart[(int64_t)blockIdx.x * Nep + r] = rs;
+  }
+  cred[ty][tx] = cs;
+  __syncthreads();
+  if (ty == 0)
+    colpart[(int64_t)blockIdx.y * gridDim.x * 64 + c0 + tx] =
+        ((cred[0][tx] + cred[1][tx]) + cred[2][tx]) + cred[3][tx];
+  if constexpr (SHADOW) {
+    for (int cc = ty; cc < 64; cc += 4) {
+      const int64_t c = c0 + cc, r = r0 + tx;
+      if (r < Ne && c < Na) {
+        bf16_t h, l;
+        split_bf16(tile[tx][cc], h, l);
+        Wth[c * ldt + r] = h;
+        Wtl[c * ldt + r] = l;
+      }
+    }
+  }
+}
+
+// Sums of the partials of k_w_norms: blocks [0, Nep) one row each, then
+// the columns, kRT per block.
+__global__ __launch_bounds__(kRT) void k_w_norms_sum(const double* __restrict__ rowpart,
+                                                     const double* __restrict__ colpart,
+                                                     int64_t Nep, int64_t Nap,
+                                                     double* __restrict__ nr,
+                                                     double* __restrict__ nc,
+                                                     const int32_t* gate) {
+  __shared__ double red[kRT / 64];
+  if (gate && *gate == 0) return;
+  const int64_t ncb = Nap / 64, nrb = Nep / 64;
+  if ((int64_t)blockIdx.x < Nep) {
+    const int64_t r = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < ncb; b += kRT) s += rowpart[b * Nep + r];
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) nr[r] = tot;
+    return;
+  }
+  const int64_t c = ((int64_t)blockIdx.x - Nep) * kRT + threadIdx.x;
+  if (c >= Nap) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nrb; ++b) s += colpart[b * Nap + c];
+  nc[c] = s;
+}
+
 __global__ __launch_bounds__(kRT) void k_row_sqnorms(const float* __restrict__ M, int64_t cols,
                                                      int64_t ld, double* __restrict__ out,
                                                      const int32_t* gate) {
@@ -260,14 +333,6 @@ hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, cons
   return hipGetLastError();
 }
 
-hipError_t launch_w_shadows(const float* W, int64_t Ne, int64_t Na, int64_t ldw, bf16_t* Wh,
-                            bf16_t* Wl, bf16_t* Wth, bf16_t* Wtl, int64_t ldt, const int32_t* gate,
-                            hipStream_t s) {
-  const dim3 grid((unsigned)((Na + 63) / 64), (unsigned)((Ne + 63) / 64));
-  k_w_shadows<<<grid, kRT, 0, s>>>(W, Ne, Na, ldw, Wh, Wl, Wth, Wtl, ldt, gate);
-  return hipGetLastError();
-}
-
 hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* Mh, bf16_t* Ml,
                                 hipStream_t s) {
   k_split_offdiag<<<grid_for(n * n, 8192), kRT, 0, s>>>(M, n, ld, Mh, Ml);
@@ -278,7 +343,7 @@ hipError_t launch_diagonals(const float* P, int64_t ldp, double* dP, int64_t Ne,
                             const float* Tside, double* nP, double* dC, int64_t ldc, int64_t Na,
                             const double2* cstat, const double* csq, int64_t nslots, double* nC,
                             Rule rule, const DevState* st, hipStream_t s) {
-  const int64_t nb = Ne + (Na + kRT - 1) / kRT;
+  const int64_t nb = Ne + (Na + 63) / 64;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
                                                  rule.n_own, st, 0, 0.0, 0.0);
@@ -290,7 +355,7 @@ hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, in
                                      int64_t Na, const double2* cstat, const double* csq,
                                      int64_t nslots, double* nC, Rule rule, double keep, double g,
                                      const DevState* st, hipStream_t s) {
-  const int64_t nb = Ne + (Na + kRT - 1) / kRT;
+  const int64_t nb = Ne + (Na + 63) / 64;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
                                                  rule.n_own, st, 1, keep, g);
@@ -310,6 +375,33 @@ hipError_t launch_put_diag(float* M, int64_t n, int64_t ld, const double* d, hip
 hipError_t launch_state_set(DevState* st, int32_t t, int32_t active, int32_t run_pc,
                             hipStream_t s) {
   k_state_set<<<1, 64, 0, s>>>(st, t, active, run_pc);
+  return hipGetLastError();
+}
+
+size_t w_norm_scratch_doubles(int64_t Nep, int64_t Nap) {
+  const size_t fused = (size_t)(Nap / 64) * (size_t)Nep + (size_t)(Nep / 64) * (size_t)Nap;
+  const size_t chunks = (size_t)kColChunks * (size_t)Nap;
+  return fused > chunks ? fused : chunks;
+}
+
+hipError_t launch_w_norms(const float* W, int64_t Ne, int64_t Na, int64_t ldw, int64_t Nep,
+                          double* nr, double* nc, double* scr, bf16_t* Wh, bf16_t* Wl, bf16_t* Wth,
+                          bf16_t* Wtl, int64_t ldt, const int32_t* gate, hipStream_t s) {
+  const int64_t Nap = ldw;
+  if (Nep % 64 || Nap % 64 || Ne > Nep || Na > Nap) return hipErrorInvalidValue;
+  double* rowpart = scr;
+  double* colpart = scr + (Nap / 64) * Nep;
+  const dim3 grid((unsigned)(Nap / 64), (unsigned)(Nep / 64));
+  if (Wh)
+    k_w_norms<true><<<grid, kRT, 0, s>>>(W, Ne, Na, ldw, Nep, rowpart, colpart, Wh, Wl, Wth, Wtl,
+                                         ldt, gate);
+  else
+    k_w_norms<false><<<grid, kRT, 0, s>>>(W, Ne, Na, ldw, Nep, rowpart, colpart, nullptr, nullptr,
+                                          nullptr, nullptr, ldt, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nb = Nep + (Nap + kRT - 1) / kRT;
+  k_w_norms_sum<<<dim3((unsigned)nb), kRT, 0, s>>>(rowpart, colpart, Nep, Nap, nr, nc, gate);
   return hipGetLastError();
 }
 

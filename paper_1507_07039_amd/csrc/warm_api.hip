@@ -190,10 +190,8 @@ panda_status panda_ws_init(panda_ctx* c, const float* Wpred, int32_t t0) {
   HIP_TRY(hipMemcpy2DAsync(c->W[0], (size_t)Nap * 4, Wpred, (size_t)Na * 4, (size_t)Na * 4,
                            (size_t)Ne, hipMemcpyDeviceToDevice, s));
   float* W = c->W[0];
-  HIP_TRY(launch_row_sqnorms(W, Ne, Na, Nap, c->nWr, nullptr, s));
-  HIP_TRY(launch_col_sqnorms(W, Ne, Na, Nap, c->nWc, c->colscr, nullptr, s));
-  if (c->b3)
-    HIP_TRY(launch_w_shadows(W, Ne, Na, Nap, c->Wh, c->Wl, c->Wth, c->Wtl, Nep, nullptr, s));
+  HIP_TRY(launch_w_norms(W, Ne, Na, Nap, Nep, c->nWr, c->nWc, c->colscr, c->Wh, c->Wl, c->Wth,
+                         c->Wtl, Nep, nullptr, s));
   HIP_TRY(launch_state_set(c->st, t0, 1, 1, s));
   const int32_t* run_pc = &c->st->run_pc;
   // off-diagonals: the update rule of Eq. 5 with alpha = 1 gives T itself
