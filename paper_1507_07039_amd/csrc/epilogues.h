@@ -80,7 +80,8 @@ struct EpiWUpdate {
 // Tile configurations.  Rectangular products: 64 x 128 tiles (N_e = 700 pads
 // to 704 = 11 x 64), 4 waves side by side.  Symmetric C product: 128 x 128.
 using RectF32 = BlockGemm<64, 128, 1, 4, true, false, 16>;
-using RectB3 = BlockGemmB3<64, 128, 1, 4>;
+using RectB3 = BlockGemmB3<64, 128, 1, 4>;  // R: K = N_e is short, register staging wins
+static_assert(RectF32::BM == RectB3::BM && RectF32::BN == RectB3::BN, "one tile grid");
 // The split-BF16 A product moves its operands by direct loads into LDS, and
 // that path bounds it: 256 x 128 tiles (4 waves of 64 x 128) move half the
 // bytes per MFMA of 64 x 128 ones.  N_e is padded to the tile (704 -> 768)
@@ -90,7 +91,6 @@ using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
 using SymB3 = BlockGemmB3P<128, 128, 2, 2, false, 2>;  // direct-to-LDS, two stages (two blocks per CU)
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;
 using CoopB3 = BlockGemmB3<64, 64, 2, 2>;
-static_assert(RectF32::BM == RectB3::BM && RectF32::BN == RectB3::BN, "one tile grid");
 static_assert(CoopF32::BK == CoopB3::BK, "one K split");
 
 // ------------------------------------------------------------------------

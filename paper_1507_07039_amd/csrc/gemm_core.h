@@ -262,6 +262,7 @@ struct OpsB3 {
   const bf16_t* Yh;
   const bf16_t* Yl;
   int64_t ldy;
+  int64_t mrows = INT64_MAX;  // rows of X that exist (loaders may clamp to them)
 };
 // The same with Y an FP32 symmetric matrix (Yt = Y, rows read K-contiguous)
 // that is split into hi/lo while it is staged.
@@ -573,12 +574,9 @@ struct BlockGemmB3P {
         const int p = ((q % XPP) * WAVES + w) * 64 + lane;  // chunk within the plane
         const int r = p / CPR, slot = p % CPR;
         const int chunk = slot ^ ((r / PX::RG) & (CPR - 1));
-        int64_t rr = r;
-        if constexpr (YF32) {
-          // rows past the operand's end (M padded to the tile) re-read its
-          // last row; their outputs are never stored
-          rr = (m0 + r < o.mrows ? m0 + r : o.mrows - 1) - m0;
-        }
+        // rows past the operand's end (M padded to the tile) re-read its last
+        // row; their outputs are never stored
+        const int64_t rr = (m0 + r < o.mrows ? m0 + r : o.mrows - 1) - m0;
         d.voff[q] = (unsigned)((rr * o.ldx + chunk * 8) * 2);
       } else if constexpr (YF32) {
         const int p = ((q - XPW) * WAVES + w) * 64 + lane;
