@@ -860,39 +860,29 @@ struct BlockGemmB3P {
 // tiles of U K-steps each in two parts:
 //   full rounds: with R = nTiles / nb, block L computes tiles L, L + nb, ...,
 //     L + (R-1) nb whole.  Consecutive tiles (M fastest, sharing a strip of
-//     the Y operand) run on one XCD at the same time, so that strip is
-//     fetched from memory about once per round.
-//   tail: the remaining nTiles - R nb tiles are split stream-K style over the
-//     first nbt <= nb blocks (at most kTailSplit blocks per tile, so the
-//     fix-up sums few partials): block L < nbt owns items
-//     [L*total/nbt, (L+1)*total/nbt) of their total = tail * U K-steps;
-//     tiles finished inside one block get their epilogue at once, tiles
-//     shared by blocks are summed in block order by the fix-up kernel
-//     (deterministic; no block ever waits for another).
+//     the Y operand) run on one XCD at the same time, so that strip and the
+//     X tiles they need are fetched from memory about once per round.
+//   tail: the T = nTiles - R nb remaining tiles are cut into S equal K-chunks
+//     each, and item i = c T + t (chunk c of tail tile t) goes to block i mod
+//     nb.  Items are numbered chunk first, so the blocks of one XCD work on
+//     the same K-chunk of neighbouring tiles at the same time and keep
+//     sharing operand strips in L2, as in a full round.  With S = 1 a block
+//     finishes the tile itself; otherwise it stores its partial product and
+//     the fix-up kernel adds the S partials of each tile in chunk order
+//     (deterministic; no block ever waits for another).  The host picks S
+//     to minimise the largest tail load of a block.
 // Logical block numbers are assigned XCD by XCD (the hardware hands block b to
 // XCD b % 8), so one XCD works on contiguous tiles.
-__device__ __forceinline__ int64_t sk_begin(int64_t L, int64_t total, int64_t G) {
-  return L * total / G;
-}
-// Logical block whose tail range holds item i (the largest L with begin <= i).
-__device__ __forceinline__ int64_t sk_owner(int64_t i, int64_t total, int64_t G) {
-  return ((i + 1) * G - 1) / total;
-}
-
-constexpr int64_t kTailSplit = 4;
-
 template <class G, class Epi>
 __global__ __launch_bounds__(G::NT) __attribute__((amdgpu_waves_per_eu(G::WAVES_PER_EU)))
-void k_rect_streamk(typename G::Ops ops, int64_t nMT,
-                                                        int64_t nTiles, int64_t U, int64_t nbt,
-                                                        Epi epi, float* __restrict__ part,
-                                                        const int32_t* gate) {
+void k_rect_streamk(typename G::Ops ops, int64_t nMT, int64_t nTiles, int64_t U, int64_t S,
+                    Epi epi, float* __restrict__ part, const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ __align__(16) char smem[G::MAIN_BYTES];
-  __shared__ double red[8];
+  __shared__ double red[G::NT / 64];
   const int64_t nb = gridDim.x;
   const int64_t L = xcd_tile(blockIdx.x, nb);
-  const int64_t R = nTiles / nb, nFull = R * nb;
+  const int64_t R = nTiles / nb, nFull = R * nb, T = nTiles - nFull;
   G g;
   for (int64_t r = 0; r < R; ++r) {
     const int64_t tile = r * nb + L;
@@ -901,68 +891,39 @@ void k_rect_streamk(typename G::Ops ops, int64_t nMT,
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
     epi.end_tile(tile, red);
   }
-  if (L >= nbt) return;
-  const int64_t total = (nTiles - nFull) * U;
-  const int64_t b = sk_begin(L, total, nbt), e = sk_begin(L + 1, total, nbt);
-  int64_t it = b;
-  while (it < e) {
-    const int64_t tt = it / U;  // tail tile
-    const int64_t k0 = it - tt * U;
-    const int64_t k1 = (e - tt * U < U) ? e - tt * U : U;
-    const int64_t tile = nFull + tt;
+  for (int64_t i = L; i < T * S; i += nb) {
+    const int64_t c = i / T, tile = nFull + i % T;
     const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
-    g.run(ops, m0, n0, k0 * G::BK, k1 * G::BK, smem);
-    if (k0 == 0 && k1 == U) {
-      g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
+    g.run(ops, m0, n0, c * U / S * G::BK, (c + 1) * U / S * G::BK, smem);
+    if (S == 1) {
+      g.for_each([&](int rr, int c2, float v) { epi.element(m0 + rr, n0 + c2, v); });
       epi.end_tile(tile, red);
     } else {
-      float* ps = part + (2 * L + (it == b ? 0 : 1)) * (int64_t)(G::BM * G::BN);
-      g.for_each([&](int rr, int c, float v) { ps[rr * G::BN + c] = v; });
+      float* ps = part + i * (int64_t)(G::BM * G::BN);
+      g.for_each([&](int rr, int c2, float v) { ps[rr * G::BN + c2] = v; });
     }
-    it = tt * U + k1;
   }
 }
 
-// Tail tiles whose K-steps were split between blocks: sum the partial
-// products in block order (deterministic) and run the same epilogue.
-// (1024 threads per tile: the epilogue's loads form a dependent chain per
-// element, so the fix-up runs as many waves per tile as a block holds.)
+// Tail tiles computed in S > 1 K-chunks: add the partial products in chunk
+// order (deterministic) and run the epilogue.  1024 threads per tile: the
+// epilogue's loads form a dependent chain per element, so the fix-up runs as
+// many waves per tile as a block holds.
 constexpr int kFixThreads = 1024;
 template <class G, class Epi>
-__global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t U,
-                                                            int64_t nb, int64_t nbt,
+__global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t nb,
+                                                            int64_t S,
                                                             const float* __restrict__ part, Epi epi,
                                                             const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ double red[kFixThreads / 64];
-  const int64_t nFull = (nTiles / nb) * nb;
-  const int64_t tile = nFull + blockIdx.x;
-  if (tile >= nTiles) return;
-  const int64_t tt = tile - nFull;
-  const int64_t total = (nTiles - nFull) * U;
-  const int64_t lo = sk_owner(tt * U, total, nbt), hi = sk_owner((tt + 1) * U - 1, total, nbt);
-  if (lo == hi) return;  // finished inside one block
+  const int64_t nFull = (nTiles / nb) * nb, T = nTiles - nFull;
+  const int64_t t = blockIdx.x, tile = nFull + t;
   const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
   constexpr int E = G::BM * G::BN;
-  // partial slots of the contributing blocks, in block order (found once)
-  constexpr int kMaxParts = 16;
-  static_assert(kTailSplit + 2 <= kMaxParts, "a tail tile spans at most kTailSplit + 1 blocks");
-  __shared__ int64_t slot[kMaxParts];
-  __shared__ int nparts;
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (int64_t L = lo; L <= hi && n < kMaxParts; ++L) {
-      const int64_t bL = sk_begin(L, total, nbt);
-      if (bL == sk_begin(L + 1, total, nbt)) continue;  // empty range
-      slot[n++] = (2 * L + ((L == lo && bL < tt * U) ? 1 : 0)) * E;
-    }
-    nparts = n;
-  }
-  __syncthreads();
-  const int np = nparts;
   for (int e = threadIdx.x; e < E; e += kFixThreads) {
-    float s = 0.0f;
-    for (int q = 0; q < np; ++q) s += part[slot[q] + e];
+    float s = part[t * E + e];
+    for (int64_t c = 1; c < S; ++c) s += part[(c * T + t) * E + e];
     epi.element(m0 + e / G::BN, n0 + e % G::BN, s);
   }
   epi.end_tile(tile, red);
@@ -991,19 +952,29 @@ hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64
   const int64_t nMT = Mp / G::BM, nNT = Np / G::BN;
   const int64_t nTiles = nMT * nNT, U = Kp / G::BK;
   int64_t nb = resident;
-  if (nb > kMaxStreamKBlocks) nb = kMaxStreamKBlocks;
-  // the split-tile scratch holds 2 * kMaxStreamKBlocks tiles of 64 x 128
-  if (nb * G::BM * G::BN > kMaxStreamKBlocks * 64 * 128) nb = kMaxStreamKBlocks * 64 * 128 / (G::BM * G::BN);
   if (nb > nTiles) nb = nTiles;
-  const int64_t tail = nTiles - (nTiles / nb) * nb;
-  const int64_t nbt = tail * kTailSplit < nb ? tail * kTailSplit : nb;
-  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(G::NT), 0, s>>>(ops, nMT, nTiles, U, nbt, epi,
+  const int64_t T = nTiles - (nTiles / nb) * nb;
+  // K-chunks per tail tile: the smallest S with the least cost, counted in
+  // K-steps: the largest block load (with start-up per item) plus the fix-up,
+  // which reads S partials per entry; the partials must fit the scratch
+  // (2 * kMaxStreamKBlocks tiles of 64 x 128)
+  const int64_t cap = 2 * kMaxStreamKBlocks * 64 * 128 / (G::BM * G::BN);
+  constexpr int64_t kItemCost = 8;
+  int64_t S = 1, best = T ? ((T + nb - 1) / nb) * (U + kItemCost) : 0;
+  for (int64_t c = 2; T && c <= 64 && c <= U && T * c <= cap; ++c) {
+    const int64_t load = ((T * c + nb - 1) / nb) * ((U + c - 1) / c + kItemCost) + c;
+    if (load < best) {
+      best = load;
+      S = c;
+    }
+  }
+  k_rect_streamk<G, Epi><<<dim3((unsigned)nb), dim3(G::NT), 0, s>>>(ops, nMT, nTiles, U, S, epi,
                                                                      part, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (tail == 0) return hipSuccess;
-  k_rect_fixup<G, Epi><<<dim3((unsigned)tail), dim3(kFixThreads), 0, s>>>(nMT, nTiles, U, nb, nbt,
-                                                                          part, epi, gate);
+  if (T == 0 || S == 1) return hipSuccess;
+  k_rect_fixup<G, Epi><<<dim3((unsigned)T), dim3(kFixThreads), 0, s>>>(nMT, nTiles, nb, S, part,
+                                                                       epi, gate);
   return hipGetLastError();
 }
 
