@@ -445,9 +445,9 @@ struct BlockGemmB3 {
 // image is swizzled for conflict-free fragment reads:
 //   bf16 planes: rows of BK bf16, slot s of row r holds chunk s ^ f(r) (as
 //     TileLoadB3);
-//   FP32 rows: BK floats = 8 chunks, slot s of row r holds chunk
-//     s ^ ((r / 2) % 8), so the 16 rows one read touches at a time cover all
-//     64 banks.
+//   FP32 rows: BK floats = BK / 4 chunks, slot s of row r holds chunk
+//     s ^ yswz(r), so the 16 rows one read touches at a time cover all 64
+//     banks.
 // The loop is also software-pipelined in registers: while the matrix cores
 // work on K-tile k, the wave issues the loads of K-tile k + 3, reads the
 // fragments of K-tile k + 1 from LDS and splits them.
@@ -501,16 +501,20 @@ __device__ __forceinline__ void split_pair(float a, float b, unsigned& h, unsign
 // YF32: Y is the FP32 symmetric matrix split as its fragments are read;
 // otherwise Y is given as bf16 hi/lo planes like X (no split arithmetic).
 // The STAGES stage buffers are carved from the caller's shared memory.
-template <int BM_, int BN_, int WM, int WN, bool YF32 = true, int STAGES = 3>
+template <int BM_, int BN_, int WM, int WN, bool YF32 = true, int STAGES = 3, int BK_ = 32>
 struct BlockGemmB3P {
   using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
-  static constexpr int BM = BM_, BN = BN_, BK = 32, NT = 64 * WM * WN;
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
   static constexpr int WAVES = WM * WN;
   static constexpr int WAVES_PER_EU = 1;
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
   static constexpr int KS = BK / 16;
-  static_assert(TM >= 1 && TN >= 1 && KS == 2, "two 16-deep k-steps per K-tile");
+  static_assert(TM >= 1 && TN >= 1 && (KS == 1 || KS == 2), "one or two 16-deep k-steps per K-tile");
+  // Swizzle of FP32 Y rows (BK floats = BK / 4 chunks): chunk s of row r sits
+  // in slot s ^ yswz(r), so the 16 rows a read touches at a time cover all
+  // 64 banks (256 bytes hold 64 / BK rows).
+  __device__ __forceinline__ static int yswz(int r) { return (r / (64 / BK)) % (BK / 4); }
   static_assert(STAGES == 2 || STAGES == 3, "two or three stages");
   using PX = TileLoadB3<BM, NT, BK>;  // swizzle of the bf16 planes
   using PY = TileLoadB3<BN, NT, BK>;
@@ -581,7 +585,7 @@ struct BlockGemmB3P {
       } else if constexpr (YF32) {
         const int p = ((q - XPW) * WAVES + w) * 64 + lane;
         const int r = p / (BK / 4), slot = p % (BK / 4);
-        const int chunk = slot ^ ((r >> 1) & 7);
+        const int chunk = slot ^ yswz(r);
         d.voff[q] = (unsigned)(((int64_t)r * o.ldy + chunk * 4) * 4);
       } else {
         const int p = (((q - XPW) % YPP) * WAVES + w) * 64 + lane;
@@ -630,7 +634,7 @@ struct BlockGemmB3P {
         const int n = wn * (BN / WN) + j * 32 + (lane & 31);
         if constexpr (YF32) {
           const unsigned yb = 2u * XQ * 16 + 4u * n * BK;
-          const int f = (n >> 1) & 7;  // rows n and n + 8 in different bank halves
+          const int f = yswz(n);
           ad[PER * ks + 2 * TM + 2 * j] = yb + 4u * ((c0 ^ f) << 2);
           ad[PER * ks + 2 * TM + 2 * j + 1] = yb + 4u * (((c0 + 1) ^ f) << 2);
         } else {
