@@ -440,8 +440,8 @@ struct BlockGemmB3 {
 // as its fragments are read; C is symmetric, so its row n is the column the
 // product needs).  Operand tiles move by direct global -> LDS loads
 // (global_load_lds_dwordx4: lane l of a wave writes its 16 bytes at LDS base
-// + 16 l) into three stages, so two K-tiles are in flight without holding
-// registers.  Which global chunk a lane fetches is chosen so that the LDS
+// + 16 l) into STAGES (two or three) stages, so STAGES - 1 K-tiles are in
+// flight without holding registers.  Which global chunk a lane fetches is chosen so that the LDS
 // image is swizzled for conflict-free fragment reads:
 //   bf16 planes: rows of BK bf16, slot s of row r holds chunk s ^ f(r) (as
 //     TileLoadB3);
@@ -449,8 +449,8 @@ struct BlockGemmB3 {
 //     s ^ yswz(r), so the 16 rows one read touches at a time cover all 64
 //     banks.
 // The loop is also software-pipelined in registers: while the matrix cores
-// work on K-tile k, the wave issues the loads of K-tile k + 3, reads the
-// fragments of K-tile k + 1 from LDS and splits them.
+// work on K-tile k, the wave issues the loads of K-tile k + STAGES, reads
+// the fragments of K-tile k + 1 from LDS and splits them.
 //
 // The direct loads are issued from inline assembly (no register results;
 // the LDS base goes through M0), so the compiler's own LDS reads are not
