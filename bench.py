@@ -251,7 +251,7 @@ def main():
             "speedup_per_iteration": s_iter / statistics.median(per3),
             "phase_ms": ms3, "phase_tflops_fp32_equivalent": rates3,
             "roofline": {"bound": "mfma",
-                         "kernel": "A+W: k_rect_streamk<BlockGemmB3P<256,128,4,1,FP32 C,3>, "
+                         "kernel": "A+W: k_rect_streamk<BlockGemmB3P<256,128,4,1,FP32 C,3,32>, "
                                    "EpiWUpdate> + k_rect_fixup",
                          "achieved": bf_rate, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                          "frac": bf_rate / PEAK_BF16_MFMA_TFLOPS,
