@@ -159,3 +159,41 @@ def test_full_size_run_against_plain(torch, pd):
             print(f"  t={t}: max|dW| = {dW:.3e}  max|W| = {sW:.3e}  rel {dW / max(1.0, sW):.2e}")
             assert dW <= 1e-3 * max(1.0, sW), (t, dW, sW)
             assert torch.equal(Pf, Pf.T) and torch.equal(Cf, Cf.T)
+
+
+def test_large_config_both_forms(torch, pd, oracle):
+    """T=1000, G=30000, the precision form's own configuration: both forms on
+    the same inputs.  W entries after one iteration against the FP64 host
+    recomputation of sampled entries (FP32 form within 1e-4, precision form
+    within 1e-3), then the two forms against each other after three
+    iterations (relative to max|W|, as at T=700, G=18000)."""
+    W0, P0, C0 = I.workload_priors(I.LARGE)
+    W, P, C = (np.ascontiguousarray(oracle.normalize(M).astype(np.float32)) for M in (W0, P0, C0))
+    del W0, P0, C0
+    Ne, Na = W.shape
+    rng = np.random.default_rng(30000)
+    r = rng.integers(0, Ne, size=1024)
+    c = rng.integers(0, Na, size=1024)
+    want = oracle.step_w_entries(W.astype(np.float64), P.astype(np.float64),
+                                 C.astype(np.float64), 0.1, r, c)
+    dev = [torch.from_numpy(a).cuda() for a in (W, P, C)]
+    del W, P, C
+    last = {}
+    for prec, tol in ((0, 1e-4), (1, 1e-3)):
+        ctx = pd.Context(Ne, Na, pd.default_options(precision=prec, tol=0.0))
+        ctx.load(*dev)
+        ctx.iterate()
+        err = np.abs(host(ctx.state()[0])[r, c] - want).max()
+        print(f"T=1000 G=30000 precision {prec}, t=1: max sampled |W - oracle| = {err:.2e}")
+        assert err <= tol
+        ctx.iterate()
+        ctx.iterate()
+        Wt, Pt, Ct = ctx.state()[:3]
+        assert torch.isfinite(Wt).all() and torch.isfinite(Ct).all()
+        assert torch.equal(Pt, Pt.T) and torch.equal(Ct, Ct.T)
+        last[prec] = host(Wt)
+        ctx.close()
+        del Wt, Pt, Ct
+    dW, sW = np.abs(last[1] - last[0]).max(), np.abs(last[0]).max()
+    print(f"T=1000 G=30000, t=3: max |W_split - W_fp32| = {dW:.3e} (max|W| = {sW:.3e})")
+    assert dW <= 1e-3 * max(1.0, sW)
