@@ -807,6 +807,18 @@ struct BlockGemmB3P {
     }
     wave_barrier_mem();
     if (STAGES == 3 && nk > 2) issue(d, 2, s2);
+    // A wave whose rows all lie past the operand's end (M padded to the tile)
+    // only takes its share of the loads and barriers: no reads, no MFMAs.
+    // (Only the A product pads M.)
+    if (YF32 && m0 + wm * (BM / WM) >= o.mrows) {
+      for (int kt = 0; kt + 1 < nk; ++kt) {
+        if (STAGES == 3 && kt + 2 < nk) wait_vmem<IPW>(); else wait_vmem<0>();
+        wave_barrier_mem();
+        if (kt + STAGES < nk) issue(d, kt + STAGES, kt % STAGES == 0 ? s0 : kt % STAGES == 1 ? s1 : s2);
+      }
+      wave_barrier_mem();
+      return;
+    }
     Frag cur;
     {
       Raw rw;
