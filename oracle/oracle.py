@@ -91,8 +91,11 @@ def _load():
                                    ct.POINTER(i32), dp, dp]
         lib.oracle_step_w_entries.argtypes = [dp, dp, dp, i64, i64, ct.c_double,
                                               lp, lp, i64, dp]
+        lib.oracle_pearson.argtypes = [dp, i64, i64, dp]
+        lib.oracle_pearson_entries.argtypes = [dp, i64, i64, lp, lp, i64, dp]
         for f in ("oracle_tanimoto", "oracle_tanimoto_entries", "oracle_normalize",
-                  "oracle_step", "oracle_run", "oracle_step_w_entries"):
+                  "oracle_step", "oracle_run", "oracle_step_w_entries",
+                  "oracle_pearson", "oracle_pearson_entries"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -215,6 +218,28 @@ def step_w_entries(W, P, C, alpha: float, rows, cols) -> np.ndarray:
     _check(_load().oracle_step_w_entries(_dp(W), _dp(P), _dp(C), Ne, Na, alpha,
                                          _lp(rows), _lp(cols), rows.size, _dp(out)),
            "step_w_entries")
+    return out
+
+
+def pearson(E) -> np.ndarray:
+    """Co-expression prior (Sec. II-A): Pearson correlation between the rows
+    (genes) of E (genes x samples), entry by entry; 0 against a constant row,
+    1 on the diagonal."""
+    E = _f64(E)
+    G, S = E.shape
+    out = np.empty((G, G), np.float64)
+    _check(_load().oracle_pearson(_dp(E), G, S, _dp(out)), "pearson")
+    return out
+
+
+def pearson_entries(E, rows, cols) -> np.ndarray:
+    E = _f64(E)
+    G, S = E.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.empty(rows.size, np.float64)
+    _check(_load().oracle_pearson_entries(_dp(E), G, S, _lp(rows), _lp(cols), rows.size,
+                                          _dp(out)), "pearson_entries")
     return out
 
 

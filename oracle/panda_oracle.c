@@ -291,3 +291,51 @@ int oracle_step_w_entries(const double* W, const double* P, const double* C,
   }
   return ORACLE_OK;
 }
+
+/* Pearson correlation between rows i and j of the expression matrix E
+ * (G genes x S samples, row-major): the co-expression prior of Sec. II-A,
+ * a correlation of two genes across all samples.  Straight from its
+ * definition: the two row means, then the sum of products of the centred
+ * entries over the square root of the product of the two centred sums of
+ * squares.  A constant row (centred sum of squares 0) has no defined
+ * correlation: it gets 0 with every other row.  The diagonal is 1. */
+static double pearson_pair(const double* E, int64_t S, int64_t i, int64_t j) {
+  if (i == j) return 1.0;
+  const double* x = E + i * S;
+  const double* y = E + j * S;
+  double sx = 0.0, sy = 0.0;
+  for (int64_t k = 0; k < S; ++k) {
+    sx += x[k];
+    sy += y[k];
+  }
+  double mx = sx / (double)S, my = sy / (double)S;
+  double sxy = 0.0, sxx = 0.0, syy = 0.0;
+  for (int64_t k = 0; k < S; ++k) {
+    double a = x[k] - mx, b = y[k] - my;
+    sxy += a * b;
+    sxx += a * a;
+    syy += b * b;
+  }
+  if (sxx == 0.0 || syy == 0.0) return 0.0;
+  return sxy / sqrt(sxx * syy);
+}
+
+/* C[i][j] = Pearson correlation of rows i and j of E, G x G. */
+int oracle_pearson(const double* E, int64_t G, int64_t S, double* C) {
+  if (G < 1 || S < 2 || !E || !C) return ORACLE_ERR_ARG;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < G; ++i)
+    for (int64_t j = 0; j < G; ++j) C[i * G + j] = pearson_pair(E, S, i, j);
+  return ORACLE_OK;
+}
+
+/* Sampled entries of the same matrix: Out[s] = C[rows[s]][cols[s]]. */
+int oracle_pearson_entries(const double* E, int64_t G, int64_t S, const int64_t* rows,
+                           const int64_t* cols, int64_t n, double* Out) {
+  if (G < 1 || S < 2 || !E) return ORACLE_ERR_ARG;
+  for (int64_t s = 0; s < n; ++s)
+    if (rows[s] < 0 || rows[s] >= G || cols[s] < 0 || cols[s] >= G) return ORACLE_ERR_ARG;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < n; ++s) Out[s] = pearson_pair(E, S, rows[s], cols[s]);
+  return ORACLE_OK;
+}

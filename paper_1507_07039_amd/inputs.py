@@ -57,8 +57,7 @@ def pearson_rows(E: np.ndarray) -> np.ndarray:
     return C
 
 
-def priors(seed: int, T: int, G: int, pW: float, pP: float, S: int, K: int):
-    """Raw (un-normalised) FP64 priors (W0, P0, C0) in the documented order."""
+def _draw(seed: int, T: int, G: int, pW: float, pP: float, S: int, K: int):
     rng = np.random.Generator(np.random.PCG64(seed))
     W0 = (rng.random((T, G)) < pW).astype(np.float64)
     U = np.triu((rng.random((T, T)) < pP).astype(np.float64), k=1)
@@ -66,12 +65,27 @@ def priors(seed: int, T: int, G: int, pW: float, pP: float, S: int, K: int):
     L = rng.normal(0.0, 0.5, size=(G, K))
     F = rng.normal(0.0, 1.0, size=(K, S))
     E = L @ F + rng.normal(0.0, 1.0, size=(G, S))
-    C0 = pearson_rows(E)
-    return W0, P0, C0
+    return W0, P0, E
+
+
+def priors(seed: int, T: int, G: int, pW: float, pP: float, S: int, K: int):
+    """Raw (un-normalised) FP64 priors (W0, P0, C0) in the documented order."""
+    W0, P0, E = _draw(seed, T, G, pW, pP, S, K)
+    return W0, P0, pearson_rows(E)
 
 
 def workload_priors(w: Workload):
     return priors(w.seed, w.T, w.G, w.pW, w.pP, w.S, w.K)
+
+
+def expression(seed: int, T: int, G: int, pW: float, pP: float, S: int, K: int) -> np.ndarray:
+    """The expression matrix E (G x S, FP64) that C0 of priors(...) is built
+    from (step 3 of the draw order)."""
+    return _draw(seed, T, G, pW, pP, S, K)[2]
+
+
+def workload_expression(w: Workload) -> np.ndarray:
+    return expression(w.seed, w.T, w.G, w.pW, w.pP, w.S, w.K)
 
 
 def random_dense(seed: int, shape, low: float = -1.0, high: float = 1.0) -> np.ndarray:
