@@ -109,6 +109,23 @@ size_t panda_tanimoto_workspace_bytes(int64_t M, int64_t K, int64_t N);
 panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K, int64_t N,
                             float* Out, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Co-expression prior of Sec. II-A: C[i][j] = Pearson correlation between
+ * rows i and j of the expression matrix E (G genes x S samples, row-major,
+ * leading dimension lde >= S, device memory); C is G x G with leading
+ * dimension ldc >= G (device memory, written; E is not modified; columns past
+ * G of each row are left alone).  Row means and centred sums of squares in
+ * FP64; the correlations as one FP32 MFMA product of the centred rows scaled
+ * to unit norm, computed on the upper triangle of 128 x 128 tiles and
+ * mirrored, so C is exactly symmetric.  C[i][i] = 1, and a constant row gets
+ * correlation 0 with every other row.  G >= 1, S >= 2.  Needs
+ * panda_pearson_workspace_bytes(G, S) bytes of workspace (256-byte aligned;
+ * 4 S G bytes plus padding).  The result is not z-scored: call
+ * panda_normalize on it, as on any prior.  Enqueued on the stream; returns
+ * without synchronising. */
+size_t panda_pearson_workspace_bytes(int64_t G, int64_t S);
+panda_status panda_pearson(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
+                           int64_t ldc, void* workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Workspace for a context or panda_run on an N_e x N_a problem. */
 size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt);
 

@@ -268,6 +268,38 @@ constexpr int coreg_smem_bytes() {
   return G::MAIN_BYTES > TILE ? G::MAIN_BYTES : TILE;
 }
 
+// Co-expression prior (Sec. II-A): upper tile (I, J) of Z Z^T, Z the
+// centred rows of the expression matrix scaled to unit norm, holds Pearson
+// correlations.  The tile goes through LDS so that both its own rows and,
+// off the diagonal, its mirror image at (J, I) are stored row-contiguous.
+// Only entries inside the G x G result are written; the diagonal is 1.
+template <class G>
+__device__ __forceinline__ void corr_sym_epilogue(const G& g, char* smem, int64_t I, int64_t J,
+                                                  float* __restrict__ C, int64_t ldc, int64_t n) {
+  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
+  constexpr int kRows = kThreads / kCB;  // tile rows stored per pass
+  float* ts = reinterpret_cast<float*>(smem);
+  g.for_each([&](int rr, int c, float v) { ts[rr * kSymLD + c] = v; });
+  __syncthreads();
+  const int64_t m0 = I * kCB, n0 = J * kCB;
+  const int c = threadIdx.x % kCB, r0 = threadIdx.x / kCB;
+  for (int rr = r0; rr < kCB; rr += kRows) {
+    const int64_t gr = m0 + rr, gc = n0 + c;
+    if (gr < n && gc < n) C[gr * ldc + gc] = gr == gc ? 1.0f : ts[rr * kSymLD + c];
+  }
+  if (I == J) return;  // a diagonal tile holds both triangles itself
+  for (int q = r0; q < kCB; q += kRows) {
+    const int64_t gr = n0 + q, gc = m0 + c;
+    if (gr < n && gc < n) C[gr * ldc + gc] = ts[c * kSymLD + q];
+  }
+}
+
+template <class G>
+constexpr int corr_smem_bytes() {
+  constexpr int TILE = kCB * kSymLD * 4;
+  return G::MAIN_BYTES > TILE ? G::MAIN_BYTES : TILE;
+}
+
 // P update, first half: W W^T is only N_e x N_e but has K = N_a, so its
 // upper tiles are split over K into partial products.
 constexpr int kPB = (int)kCoopTile;

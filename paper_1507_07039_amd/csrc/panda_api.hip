@@ -376,7 +376,7 @@ struct TaniLayout {
   float *Xp, *Yp, *Op, *part;
   double *nx, *ny, *scr;
 };
-size_t tanimoto_layout(int64_t M, int64_t K, int64_t N, char* base, TaniLayout* L) {
+static size_t tanimoto_layout(int64_t M, int64_t K, int64_t N, char* base, TaniLayout* L) {
   const int64_t Mp = round_up(M, kPadE), Kp = round_up(K, kPadK), Np = round_up(N, kPadA);
   Carver cv{base};
   float* xp = cv.take<float>((size_t)Mp * Kp);
@@ -419,6 +419,41 @@ panda_status panda_tanimoto(const float* X, const float* Y, int64_t M, int64_t K
                                 nullptr, s));
   HIP_TRY(hipMemcpy2DAsync(Out, (size_t)N * 4, L.Op, (size_t)Np * 4, (size_t)N * 4, (size_t)M,
                            hipMemcpyDeviceToDevice, s));
+  return PANDA_OK;
+}
+
+namespace {
+struct PearsonLayout {
+  double2* stat;
+  float* Zt;
+};
+static size_t pearson_layout(int64_t G, int64_t S, char* base, PearsonLayout* L) {
+  const int64_t Gp = round_up(G, kPadA), Sp = round_up(S, kPadK);
+  Carver cv{base};
+  double2* st = cv.take<double2>((size_t)G);
+  float* zt = cv.take<float>((size_t)Sp * Gp);
+  if (L) *L = PearsonLayout{st, zt};
+  return cv.off;
+}
+}  // namespace
+
+size_t panda_pearson_workspace_bytes(int64_t G, int64_t S) {
+  if (G < 1 || S < 2) return 0;
+  return pearson_layout(G, S, nullptr, nullptr);
+}
+
+panda_status panda_pearson(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
+                           int64_t ldc, void* workspace, size_t ws_bytes, hipStream_t s) {
+  if (!E || !C || G < 1 || S < 2 || G > (1 << 18) || S > (1 << 20) || lde < S || ldc < G)
+    return fail(PANDA_ERR_ARG, "pearson: bad arguments%s");
+  const size_t need = panda_pearson_workspace_bytes(G, S);
+  if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(PANDA_ERR_WORKSPACE, "pearson: workspace too small or misaligned%s");
+  const int64_t Gp = round_up(G, kPadA), Sp = round_up(S, kPadK);
+  PearsonLayout L;
+  pearson_layout(G, S, static_cast<char*>(workspace), &L);
+  HIP_TRY(launch_pearson_z(E, G, S, lde, L.stat, L.Zt, Gp, Sp, s));
+  HIP_TRY(launch_corr(L.Zt, Gp, Sp, G, C, ldc, s));
   return PANDA_OK;
 }
 

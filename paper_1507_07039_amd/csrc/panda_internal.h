@@ -170,6 +170,15 @@ hipError_t launch_zscore_stats(const float* M, int64_t rows, int64_t cols, int64
 hipError_t launch_zscore_apply(float* M, int64_t rows, int64_t cols, int64_t ld,
                                const double* scratch, hipStream_t s);
 hipError_t launch_fill_identity(float* M, int64_t n, int64_t ld, hipStream_t s);
+// Pearson correlation of the G rows of E (G x S, leading dimension lde):
+// row statistics, then the centred rows scaled to unit norm, stored
+// sample-major as Zt (Sp x Gp, zero-padded; Gp a multiple of 128, Sp of 16);
+// then C = Z Z^T on the upper 128 x 128 tiles, mirrored, 1 on the diagonal.
+hipError_t launch_pearson_z(const float* E, int64_t G, int64_t S, int64_t lde, double2* stat,
+                            float* Zt, int64_t Gp, int64_t Sp, hipStream_t s);
+hipError_t launch_corr(const float* Zt, int64_t Gp, int64_t Sp, int64_t G, float* C, int64_t ldc,
+                       hipStream_t s);
+
 hipError_t launch_state_init(DevState* st, int32_t t0, hipStream_t s);
 
 }  // namespace panda

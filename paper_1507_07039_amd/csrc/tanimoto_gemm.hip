@@ -36,6 +36,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   coreg_epilogue<SIGT>(g, smem, I, J, C, ldc, Na, ncol, alpha, cstat, csq, ldstat);
 }
 
+// Pearson correlations: one upper 128 x 128 tile of Z Z^T per block, both
+// operands read from Z^T (samples x genes), stored at the tile and mirrored.
+template <class G>
+__global__ __launch_bounds__(kThreads) void k_corr_sym(typename G::Ops ops, int64_t Kp,
+                                                       float* __restrict__ C, int64_t ldc,
+                                                       int64_t n) {
+  __shared__ __align__(16) char smem[corr_smem_bytes<G>()];
+  int64_t I, J;
+  tri_tile(xcd_tile(blockIdx.x, gridDim.x), I, J);
+  G g;
+  g.run(ops, I * kCB, J * kCB, 0, Kp, smem);
+  corr_sym_epilogue(g, smem, I, J, C, ldc, n);
+}
+
 // ------------------------------------------------------------------------
 // P update, first half: each block writes the partial product of one upper
 // tile over one K chunk.
@@ -86,6 +100,16 @@ hipError_t launch_tanimoto_store(const float* X, int64_t ldx, const float* Y, in
     epi.ldxv = ldx;
   }
   return launch_rect<RectF32>(OpsF32{X, ldx, Y, ldy}, Mp, Np, Kp, epi, part, gate, s);
+}
+
+hipError_t launch_corr(const float* Zt, int64_t Gp, int64_t Sp, int64_t G, float* C, int64_t ldc,
+                       hipStream_t s) {
+  // X = Z stored sample-major (Z^T), as W^T is read from W in the C update.
+  if (Gp % kCB || Sp % SymF32::BK || G > Gp) return hipErrorInvalidValue;
+  const int64_t nT = Gp / kCB;
+  k_corr_sym<SymF32><<<dim3((unsigned)(nT * (nT + 1) / 2)), dim3(kThreads), 0, s>>>(
+      OpsF32{Zt, Gp, Zt, Gp}, Sp, C, ldc, G);
+  return hipGetLastError();
 }
 
 hipError_t launch_resp(const float* P, int64_t ldp, const double* dP, const float* W, int64_t ldw,

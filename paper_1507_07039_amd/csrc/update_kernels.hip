@@ -90,6 +90,55 @@ __global__ __launch_bounds__(kRT) void k_put_diag(float* __restrict__ M, int64_t
   if (i < n) M[i * ld + i] = (float)d[i];
 }
 
+// ---- co-expression prior (Sec. II-A) ---------------------------------------
+// Pearson correlation between genes across samples.  Per row: mean and
+// centred sum of squares in FP64 (two passes), one wave per row.
+__global__ __launch_bounds__(kRT) void k_pearson_stats(const float* __restrict__ E, int64_t G,
+                                                       int64_t S, int64_t lde,
+                                                       double2* __restrict__ stat) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (kRT / 64) + (threadIdx.x >> 6);
+  if (i >= G) return;
+  const float* e = E + i * lde;
+  double s = 0.0;
+  for (int64_t k = lane; k < S; k += 64) s += (double)e[k];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  const double mean = s / (double)S;
+  double q = 0.0;
+  for (int64_t k = lane; k < S; k += 64) q += ((double)e[k] - mean) * ((double)e[k] - mean);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off);
+  // a constant row gets scale 0: its normalised entries are 0
+  if (lane == 0) stat[i] = make_double2(mean, q > 0.0 ? 1.0 / sqrt(q) : 0.0);
+}
+
+// Zt[k][i] = (E[i][k] - mean_i) / sqrt(ss_i), zero-padded, through a 64 x 64
+// tile in LDS so that E is read and Zt written along their rows.
+__global__ __launch_bounds__(kRT) void k_pearson_z(const float* __restrict__ E, int64_t G,
+                                                   int64_t S, int64_t lde,
+                                                   const double2* __restrict__ stat,
+                                                   float* __restrict__ Zt, int64_t Gp,
+                                                   int64_t Sp) {
+  __shared__ float tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    float v = 0.0f;
+    if (r < G && c < S) {
+      const double2 st = stat[r];
+      v = (float)(((double)E[r * lde + c] - st.x) * st.y);
+    }
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t c = c0 + cc, r = r0 + tx;
+    if (r < Gp && c < Sp) Zt[c * Gp + r] = tile[tx][cc];
+  }
+}
+
 // ---- split-BF16 operand planes ----------------------------------------------
 // Planes of P without its diagonal (which lives in its FP64 vector).
 __global__ __launch_bounds__(kRT) void k_split_offdiag(const float* __restrict__ M, int64_t n,
@@ -359,6 +408,18 @@ hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, in
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
                                                  rule.n_own, st, 1, keep, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_pearson_z(const float* E, int64_t G, int64_t S, int64_t lde, double2* stat,
+                            float* Zt, int64_t Gp, int64_t Sp, hipStream_t s) {
+  if (Gp % 128 || Sp % 16 || G > Gp || S > Sp) return hipErrorInvalidValue;
+  k_pearson_stats<<<dim3((unsigned)((G + kRT / 64 - 1) / (kRT / 64))), kRT, 0, s>>>(E, G, S, lde,
+                                                                                  stat);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_pearson_z<<<dim3((unsigned)((Sp + 63) / 64), (unsigned)(Gp / 64)), kRT, 0, s>>>(
+      E, G, S, lde, stat, Zt, Gp, Sp);
   return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ ERR_ARG, ERR_DEGENERATE, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4,
 # Every extern "C" entry point declared in include/panda.h.
 EXPORTS = (
     "panda_default_options", "panda_normalize_workspace_bytes", "panda_normalize",
-    "panda_tanimoto_workspace_bytes", "panda_tanimoto", "panda_workspace_bytes",
+    "panda_tanimoto_workspace_bytes", "panda_tanimoto",
+    "panda_pearson_workspace_bytes", "panda_pearson", "panda_workspace_bytes",
     "panda_ctx_create", "panda_ctx_load", "panda_iterate", "panda_ctx_store",
     "panda_ctx_destroy", "panda_run", "panda_ctx_set_timing", "panda_ctx_phase_times",
     "panda_batch_workspace_bytes", "panda_batch_create", "panda_batch_destroy",
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH):
         "panda_normalize": (ct.c_int, [vp, i64, i64, vp, sz, vp]),
         "panda_tanimoto_workspace_bytes": (sz, [i64, i64, i64]),
         "panda_tanimoto": (ct.c_int, [vp, vp, i64, i64, i64, vp, vp, sz, vp]),
+        "panda_pearson_workspace_bytes": (sz, [i64, i64]),
+        "panda_pearson": (ct.c_int, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
         "panda_workspace_bytes": (sz, [i64, i64, op]),
         "panda_ctx_create": (ct.c_int, [i64, i64, op, vp, sz, vp, ct.POINTER(vp)]),
         "panda_ctx_load": (ct.c_int, [vp, vp, vp, vp, i32]),
@@ -187,6 +190,20 @@ def tanimoto(X, Y):
     ws = workspace(lib.panda_tanimoto_workspace_bytes(M, K, N))
     _check(lib.panda_tanimoto(_dev(X, "X"), _dev(Y, "Y"), M, K, N, out.data_ptr(),
                               ws.data_ptr(), ws.numel(), _stream()))
+    return out
+
+
+def pearson(E):
+    """C = Pearson correlation between the rows of the expression matrix E
+    (genes x samples), the co-expression prior of Sec. II-A (panda_pearson).
+    Not z-scored: pass it through normalize like any other prior."""
+    torch = _torch()
+    lib = load_library()
+    G, S = E.shape
+    out = torch.empty((G, G), dtype=torch.float32, device="cuda")
+    ws = workspace(lib.panda_pearson_workspace_bytes(G, S))
+    _check(lib.panda_pearson(_dev(E, "E"), G, S, S, out.data_ptr(), G,
+                             ws.data_ptr(), ws.numel(), _stream()))
     return out
 
 

@@ -59,6 +59,26 @@ def test_workspace_sizes(lib):
     assert lib.panda_tanimoto_workspace_bytes(0, 1, 1) == 0
     assert lib.panda_tanimoto_workspace_bytes(3, 5, 7) > 0
     assert lib.panda_normalize_workspace_bytes() >= 8 * 1024
+    assert lib.panda_pearson_workspace_bytes(0, 5) == 0
+    assert lib.panda_pearson_workspace_bytes(10, 1) == 0
+    # the normalised E, sample-major and padded, plus 16 bytes of row
+    # statistics per gene
+    big = lib.panda_pearson_workspace_bytes(18000, 200)
+    assert 224 * 18048 * 4 + 16 * 18000 <= big < 224 * 18048 * 4 + 16 * 18000 + 4096
+
+
+def test_pearson_validation(lib):
+    fake = ct.c_void_p(256)  # never dereferenced: validation fails first
+    ws = lib.panda_pearson_workspace_bytes(100, 10)
+    ok = (fake, 100, 10, 10, fake, 100, fake, ws, None)
+    for k, v in ((1, 0), (2, 1), (3, 9), (5, 99), (0, None), (4, None)):
+        a = list(ok)
+        a[k] = v
+        assert lib.panda_pearson(*a) == panda.ERR_ARG, (k, v)
+    for k, v in ((6, None), (7, ws - 1), (6, ct.c_void_p(264))):
+        a = list(ok)
+        a[k] = v
+        assert lib.panda_pearson(*a) == panda.ERR_WORKSPACE, (k, v)
 
 
 def test_host_validation_rejects_before_device_work(lib):
