@@ -163,6 +163,44 @@ panda_status panda_run(const float* W0, const float* P0, const float* C0, int64_
                        void* workspace, size_t ws_bytes, const panda_options* opt,
                        int32_t* iters, double* h, hipStream_t stream);
 
+/* ---- Permutation null ----------------------------------------------------
+ * Node-label randomisation on input (an option of the paper's C
+ * implementation, Sec. III) as a null model for the edges of W.
+ *
+ * panda_permute_sym: out[i][j] = M[perm[i]][perm[j]] for an n x n matrix M
+ * (leading dimension ldm >= n; out ldo >= n; device memory, out must not
+ * alias M).  perm: n int32 in device memory, a permutation of 0 .. n-1
+ * (checked on the host: PANDA_ERR_ARG otherwise; the check synchronises the
+ * stream).  A z-scored network stays z-scored (same entries).
+ *
+ * panda_null: K null instances.  Instance k relabels the genes of C0 by row k
+ * of gene_perm (K x Na, device) and the TFs of P0 by row k of tf_perm (K x Ne,
+ * device); either may be NULL (no relabelling of that prior; an identity prior,
+ * P0 or C0 NULL, is unchanged by any relabelling), and W0 keeps its labels.  Each
+ * instance runs PANDA() from its normalised priors to convergence with the
+ * options opt (alpha, tol, max_iter, precision ...; NULL = defaults); the
+ * converged W of all K are folded into mean[i][j] and sd[i][j] (population
+ * standard deviation over the K instances; FP64 running sums, Welford's
+ * update; outputs FP32, Ne x Na, device).  iters (host, K entries, may be NULL)
+ * receives each instance's final t.  Returns PANDA_NOT_CONVERGED if any
+ * instance stopped at max_iter (its W is still counted).  Needs
+ * panda_null_workspace_bytes(Ne, Na, opt) bytes of workspace (256-byte
+ * aligned): a context's workspace, the relabelled priors and the FP64 sums.
+ * Blocks until the last instance has converged; mean and sd are enqueued on
+ * the stream after it.
+ *
+ * panda_null_zscore: z[i][j] = (W[i][j] - mean[i][j]) / sd[i][j], 0 where
+ * sd = 0 (all Ne x Na, device; z may alias W).  Enqueued on the stream. */
+panda_status panda_permute_sym(const float* M, int64_t n, int64_t ldm, const int32_t* perm,
+                               float* out, int64_t ldo, hipStream_t stream);
+size_t panda_null_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt);
+panda_status panda_null(const float* W0, const float* P0, const float* C0, int64_t Ne,
+                        int64_t Na, int32_t K, const int32_t* gene_perm, const int32_t* tf_perm,
+                        const panda_options* opt, void* workspace, size_t ws_bytes, float* mean,
+                        float* sd, int32_t* iters, hipStream_t stream);
+panda_status panda_null_zscore(const float* W, const float* mean, const float* sd, int64_t Ne,
+                               int64_t Na, float* z, hipStream_t stream);
+
 /* Per-phase timing of a context (the paper times the message-passing
  * procedure alone, Sec. II-D; this splits that time by step).  When enabled,
  * each phase of each iteration is bracketed by HIP events on the context's

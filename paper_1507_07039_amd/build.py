@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpanda.so")
 SOURCES = ["panda_api.hip", "batch_api.hip", "warm_api.hip", "tanimoto_gemm.hip",
-           "update_kernels.hip", "batched.hip", "warmstart.hip"]
+           "update_kernels.hip", "batched.hip", "warmstart.hip", "null.hip"]
 
 # Packed FP32 instructions are switched off for all device code; hipcc's host
 # pass warns that it does not know the feature, which is harmless.

@@ -47,6 +47,8 @@ constexpr int kMaxPending = 16;               // timed iterations between read-b
 
 Rule rule_of(const panda_options& o);
 panda_status check_options(const panda_options& o);
+// PANDA() from a loaded context until h < tol or max_iter (panda_run's loop).
+panda_status run_loaded(panda_ctx* c);
 bool dims_ok(int64_t Ne, int64_t Na);
 
 // Sizes of the buffers whose extent depends on the tile schedule.  The

@@ -296,6 +296,26 @@ panda_status copy_in(float* dst, int64_t ldd, const float* src, int64_t rows, in
 
 }  // namespace
 
+namespace panda {
+
+// Enqueue ahead and read h back every poll_every iterations; iterations
+// enqueued past convergence are no-ops on the device.
+panda_status run_loaded(panda_ctx* c) {
+  panda_status st = PANDA_OK;
+  const int64_t max_iter = c->opt.max_iter, poll = c->opt.poll_every;
+  while (st == PANDA_OK && c->enqueued < max_iter) {
+    st = enqueue_iteration(c);
+    if (st != PANDA_OK) break;
+    if (c->enqueued % poll == 0 || c->enqueued == max_iter) {
+      st = read_state(c);
+      if (st != PANDA_OK || !c->host->active) break;
+    }
+  }
+  return st;
+}
+
+}  // namespace panda
+
 extern "C" {
 
 void panda_default_options(panda_options* o) {
@@ -615,18 +635,7 @@ panda_status panda_run(const float* W0, const float* P0, const float* C0, int64_
   panda_status st = panda_ctx_create(Ne, Na, &o, workspace, ws_bytes, stream, &c);
   if (st != PANDA_OK) return st;
   st = panda_ctx_load(c, W0, P0, C0, 0);
-  if (st == PANDA_OK) {
-    // Enqueue ahead and read h back every poll_every iterations; iterations
-    // enqueued past convergence are no-ops on the device.
-    while (st == PANDA_OK && c->enqueued < o.max_iter) {
-      st = enqueue_iteration(c);
-      if (st != PANDA_OK) break;
-      if (c->enqueued % o.poll_every == 0 || c->enqueued == o.max_iter) {
-        st = read_state(c);
-        if (st != PANDA_OK || !c->host->active) break;
-      }
-    }
-  }
+  if (st == PANDA_OK) st = run_loaded(c);
   if (st == PANDA_OK) st = panda_ctx_store(c, W, P, C, h, iters);
   if (st == PANDA_OK && c->host->active) st = PANDA_NOT_CONVERGED;
   panda_ctx_destroy(c);

@@ -32,6 +32,7 @@ EXPORTS = (
     "panda_ws_features_workspace_bytes", "panda_ws_features", "panda_mlp_forward",
     "panda_mlp_grad_workspace_bytes", "panda_mlp_grad", "panda_mlp_adam", "panda_mlp_train_step",
     "panda_ws_target", "panda_ws_predict", "panda_ws_init",
+    "panda_permute_sym", "panda_null_workspace_bytes", "panda_null", "panda_null_zscore",
     "panda_status_string", "panda_last_error",
 )
 
@@ -114,6 +115,11 @@ def load_library(path: str = LIB_PATH):
         "panda_ws_target": (ct.c_int, [vp, vp, i64, i64, dbl, vp, vp]),
         "panda_ws_predict": (ct.c_int, [vp, vp, i64, i64, dbl, vp, vp]),
         "panda_ws_init": (ct.c_int, [vp, vp, i32]),
+        "panda_permute_sym": (ct.c_int, [vp, i64, i64, vp, vp, i64, vp]),
+        "panda_null_workspace_bytes": (sz, [i64, i64, op]),
+        "panda_null": (ct.c_int, [vp, vp, vp, i64, i64, i32, vp, vp, op, vp, sz, vp, vp,
+                                  ct.POINTER(i32), vp]),
+        "panda_null_zscore": (ct.c_int, [vp, vp, vp, i64, i64, vp, vp]),
         "panda_status_string": (ct.c_char_p, [ct.c_int]),
         "panda_last_error": (ct.c_char_p, []),
     }
@@ -328,6 +334,73 @@ def run(W0, P0=None, C0=None, alpha: float = 0.1, tol: float = 1e-3, max_iter: i
                          ct.byref(o), ct.byref(it), ct.byref(hv), _stream())
     _check(code, allow=(OK, NOT_CONVERGED))
     return RunResult(W, P, C, it.value, hv.value, code)
+
+
+def _perm_dev(perm, n, name):
+    torch = _torch()
+    if not isinstance(perm, torch.Tensor) or not perm.is_cuda or perm.dtype != torch.int32:
+        raise TypeError(f"{name} must be an int32 tensor on the GPU")
+    if not perm.is_contiguous() or perm.shape[-1] != n:
+        raise ValueError(f"{name} must be contiguous with rows of {n} entries")
+    return perm.data_ptr()
+
+
+def permute_sym(M, perm):
+    """out[i][j] = M[perm[i]][perm[j]] (panda_permute_sym)."""
+    torch = _torch()
+    n = M.shape[0]
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    _check(load_library().panda_permute_sym(_dev(M, "M", (n, n)), n, n, _perm_dev(perm, n, "perm"),
+                                            out.data_ptr(), n, _stream()))
+    return out
+
+
+@dataclass
+class NullResult:
+    mean: object  # Ne x Na, FP32, per-edge mean over the null instances
+    sd: object    # Ne x Na, FP32, population standard deviation
+    iters: list
+    status: int
+
+
+def null(W0, P0=None, C0=None, gene_perm=None, tf_perm=None, opts: Options | None = None,
+         ws=None) -> NullResult:
+    """panda_null: PANDA() on K relabelled copies of the priors (genes of C0
+    by the rows of gene_perm, TFs of P0 by the rows of tf_perm; int32 device
+    tensors K x Na and K x Ne), folded into a per-edge mean and sd."""
+    torch = _torch()
+    lib = load_library()
+    Ne, Na = W0.shape
+    o = opts or default_options()
+    perms = [p for p in (gene_perm, tf_perm) if p is not None]
+    K = perms[0].shape[0] if perms else 1
+    if any(p.shape[0] != K for p in perms):
+        raise ValueError("gene_perm and tf_perm must have the same number of rows")
+    mean = torch.empty((Ne, Na), dtype=torch.float32, device="cuda")
+    sd = torch.empty((Ne, Na), dtype=torch.float32, device="cuda")
+    if ws is None:
+        ws = workspace(lib.panda_null_workspace_bytes(Ne, Na, ct.byref(o)))
+    iters = (ct.c_int32 * K)()
+    code = lib.panda_null(_dev(W0, "W0", (Ne, Na)),
+                          None if P0 is None else _dev(P0, "P0", (Ne, Ne)),
+                          None if C0 is None else _dev(C0, "C0", (Na, Na)), Ne, Na, K,
+                          None if gene_perm is None else _perm_dev(gene_perm, Na, "gene_perm"),
+                          None if tf_perm is None else _perm_dev(tf_perm, Ne, "tf_perm"),
+                          ct.byref(o), ws.data_ptr(), ws.numel(), mean.data_ptr(), sd.data_ptr(),
+                          iters, _stream())
+    _check(code, allow=(OK, NOT_CONVERGED))
+    return NullResult(mean, sd, list(iters), code)
+
+
+def null_zscore(W, mean, sd):
+    """z = (W - mean) / sd per edge, 0 where sd = 0 (panda_null_zscore)."""
+    torch = _torch()
+    Ne, Na = W.shape
+    z = torch.empty((Ne, Na), dtype=torch.float32, device="cuda")
+    _check(load_library().panda_null_zscore(_dev(W, "W", (Ne, Na)), _dev(mean, "mean", (Ne, Na)),
+                                            _dev(sd, "sd", (Ne, Na)), Ne, Na, z.data_ptr(),
+                                            _stream()))
+    return z
 
 
 def _shape_arrays(shapes):

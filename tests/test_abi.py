@@ -67,6 +67,32 @@ def test_workspace_sizes(lib):
     assert 224 * 18048 * 4 + 16 * 18000 <= big < 224 * 18048 * 4 + 16 * 18000 + 4096
 
 
+def test_null_validation(lib):
+    o = panda.default_options()
+    fake = ct.c_void_p(256)  # never dereferenced: validation fails first
+    assert lib.panda_null_workspace_bytes(0, 5, ct.byref(o)) == 0
+    ws = lib.panda_null_workspace_bytes(40, 400, ct.byref(o))
+    # a context, both relabelled priors, W and two FP64 sums
+    assert ws >= lib.panda_workspace_bytes(40, 400, ct.byref(o)) + (400 * 400 + 40 * 400 * 5) * 4
+    it = (ct.c_int32 * 2)()
+    ok = [fake, None, fake, 40, 400, 2, fake, None, ct.byref(o), fake, ws, fake, fake, it, None]
+    for k, v in ((0, None), (3, 0), (4, 0), (5, 0), (11, None), (12, None)):
+        a = list(ok)
+        a[k] = v
+        assert lib.panda_null(*a) == panda.ERR_ARG, (k, v)
+    bad = panda.default_options(alpha=2.0)
+    a = list(ok)
+    a[8] = ct.byref(bad)
+    assert lib.panda_null(*a) == panda.ERR_ARG
+    for k, v in ((9, None), (10, ws - 1), (9, ct.c_void_p(264))):
+        a = list(ok)
+        a[k] = v
+        assert lib.panda_null(*a) == panda.ERR_WORKSPACE, (k, v)
+    assert lib.panda_permute_sym(fake, 0, 1, fake, fake, 1, None) == panda.ERR_ARG
+    assert lib.panda_permute_sym(fake, 5, 4, fake, fake, 5, None) == panda.ERR_ARG
+    assert lib.panda_null_zscore(None, fake, fake, 4, 5, fake, None) == panda.ERR_ARG
+
+
 def test_pearson_validation(lib):
     fake = ct.c_void_p(256)  # never dereferenced: validation fails first
     ws = lib.panda_pearson_workspace_bytes(100, 10)
