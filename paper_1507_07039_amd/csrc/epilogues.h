@@ -57,18 +57,29 @@ struct EpiWUpdate {
   int32_t h_undamped;
   double* hpart;
   double hsum;
-  __device__ __forceinline__ void element(int64_t r, int64_t c, float acc) {
+  // the entry's old W and R, fetched ahead by epi_tile where it can
+  using Pre = float2;
+  __device__ __forceinline__ Pre fetch(int64_t r, int64_t c) const {
     if (r < Ne && c < Na) {
       const int64_t o = r * ld + c;
-      const double w = Wold[o];
+      return make_float2(Wold[o], R[o]);
+    }
+    return make_float2(0.0f, 0.0f);
+  }
+  __device__ __forceinline__ void element_pre(int64_t r, int64_t c, float acc, Pre pre) {
+    if (r < Ne && c < Na) {
+      const double w = pre.x;
       double dot = (double)acc;
       dot += w * cd[c];
       const double a = tanimoto(dot, nx[r], ny[c]);
-      const double pred = 0.5 * (a + (double)R[o]);
+      const double pred = 0.5 * (a + (double)pre.y);
       const float wn = (float)((1.0 - alpha) * w + alpha * pred);
-      Wnew[o] = wn;
+      Wnew[r * ld + c] = wn;
       hsum += h_undamped ? fabs(pred - w) : fabs((double)wn - w);
     }
+  }
+  __device__ __forceinline__ void element(int64_t r, int64_t c, float acc) {
+    element_pre(r, c, acc, fetch(r, c));
   }
   __device__ __forceinline__ void end_tile(int64_t tile, double* red) {
     const double s = block_sum(hsum, red);

@@ -504,6 +504,9 @@ __device__ __forceinline__ void split_pair(float a, float b, unsigned& h, unsign
 template <int BM_, int BN_, int WM, int WN, bool YF32 = true, int STAGES = 3, int BK_ = 32>
 struct BlockGemmB3P {
   using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
+  // one block per CU and the accumulators in AGPRs: the epilogue has the
+  // VGPRs to fetch its per-entry operands 16 at a time (see epi_tile)
+  static constexpr bool kPrefetchEpi = true;
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
   static constexpr int WAVES = WM * WN;
   static constexpr int WAVES_PER_EU = 1;
@@ -889,6 +892,40 @@ struct BlockGemmB3P {
 //     to minimise the largest tail load of a block.
 // Logical block numbers are assigned XCD by XCD (the hardware hands block b to
 // XCD b % 8), so one XCD works on contiguous tiles.
+// The epilogue of a finished tile.  Where the block GEMM allows it
+// (kPrefetchEpi) and the epilogue reads operands of its own per entry
+// (fetch), those are loaded for the 16 entries of one accumulator block
+// before any is used, so the loads are in flight together instead of one
+// dependent load per entry.  Same arithmetic, same order, either way.
+template <class E, class = void>
+struct has_fetch : std::false_type {};
+template <class E>
+struct has_fetch<E, std::void_t<decltype(&E::fetch)>> : std::true_type {};
+template <class G, class = void>
+struct prefetch_epi : std::false_type {};
+template <class G>
+struct prefetch_epi<G, std::void_t<decltype(G::kPrefetchEpi)>>
+    : std::integral_constant<bool, G::kPrefetchEpi> {};
+
+template <class G, class Epi>
+__device__ __forceinline__ void epi_tile(const G& g, Epi& epi, int64_t m0, int64_t n0) {
+  if constexpr (has_fetch<Epi>::value && prefetch_epi<G>::value) {
+#pragma unroll
+    for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::TN; ++j) {
+        const int64_t c = n0 + g.col_of(j);
+        typename Epi::Pre pre[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) pre[r] = epi.fetch(m0 + g.row_of(i, r), c);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) epi.element_pre(m0 + g.row_of(i, r), c, g.acc[i][j][r], pre[r]);
+      }
+  } else {
+    g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
+  }
+}
+
 template <class G, class Epi>
 __global__ __launch_bounds__(G::NT) __attribute__((amdgpu_waves_per_eu(G::WAVES_PER_EU)))
 void k_rect_streamk(typename G::Ops ops, int64_t nMT, int64_t nTiles, int64_t U, int64_t S,
@@ -904,7 +941,7 @@ void k_rect_streamk(typename G::Ops ops, int64_t nMT, int64_t nTiles, int64_t U,
     const int64_t tile = r * nb + L;
     const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
     g.run(ops, m0, n0, 0, U * G::BK, smem);
-    g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
+    epi_tile(g, epi, m0, n0);
     epi.end_tile(tile, red);
   }
   for (int64_t i = L; i < T * S; i += nb) {
@@ -912,7 +949,7 @@ void k_rect_streamk(typename G::Ops ops, int64_t nMT, int64_t nTiles, int64_t U,
     const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
     g.run(ops, m0, n0, c * U / S * G::BK, (c + 1) * U / S * G::BK, smem);
     if (S == 1) {
-      g.for_each([&](int rr, int c2, float v) { epi.element(m0 + rr, n0 + c2, v); });
+      epi_tile(g, epi, m0, n0);
       epi.end_tile(tile, red);
     } else {
       float* ps = part + i * (int64_t)(G::BM * G::BN);
