@@ -974,10 +974,38 @@ __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t
   const int64_t t = blockIdx.x, tile = nFull + t;
   const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
   constexpr int E = G::BM * G::BN;
-  for (int e = threadIdx.x; e < E; e += kFixThreads) {
-    float s = part[t * E + e];
-    for (int64_t c = 1; c < S; ++c) s += part[(c * T + t) * E + e];
-    epi.element(m0 + e / G::BN, n0 + e % G::BN, s);
+  static_assert(E % kFixThreads == 0, "whole passes");
+  // entries e = threadIdx.x + q kFixThreads, taken GRP at a time: their
+  // partials (and the epilogue's own operands) are loaded together, then
+  // summed in chunk order and finished in the order of q
+  constexpr int PER = E / kFixThreads, GRP = PER < 8 ? PER : 8;
+  static_assert(PER % GRP == 0, "whole groups");
+  for (int q0 = 0; q0 < PER; q0 += GRP) {
+    float s[GRP];
+#pragma unroll
+    for (int q = 0; q < GRP; ++q) s[q] = part[t * E + threadIdx.x + (q0 + q) * kFixThreads];
+    for (int64_t c = 1; c < S; ++c)
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) s[q] += part[(c * T + t) * E + threadIdx.x + (q0 + q) * kFixThreads];
+    if constexpr (has_fetch<Epi>::value) {
+      typename Epi::Pre pre[GRP];
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = threadIdx.x + (q0 + q) * kFixThreads;
+        pre[q] = epi.fetch(m0 + e / G::BN, n0 + e % G::BN);
+      }
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = threadIdx.x + (q0 + q) * kFixThreads;
+        epi.element_pre(m0 + e / G::BN, n0 + e % G::BN, s[q], pre[q]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = threadIdx.x + (q0 + q) * kFixThreads;
+        epi.element(m0 + e / G::BN, n0 + e % G::BN, s[q]);
+      }
+    }
   }
   epi.end_tile(tile, red);
 }
