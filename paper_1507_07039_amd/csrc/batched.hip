@@ -126,9 +126,10 @@ struct PhCoreg {
     const float* W = d.W[st->wsel];
     const uint32_t ij = d.corder[local];
     const int64_t I = ij & 0xffff, J = ij >> 16;
+    const double nval = coreg_norm_load(d.nWc, I, J, d.Na);
     G g;
     g.run(OpsF32{W, d.Nap, W, d.Nap}, I * kCB, J * kCB, 0, d.Nep, smem);
-    coreg_epilogue<SIGT>(g, smem, I, J, d.C, d.Nap, d.Na, d.nWc, alpha, d.cstat, d.csq, d.Nap);
+    coreg_epilogue<SIGT>(g, smem, I, J, d.C, d.Nap, d.Na, nval, alpha, d.cstat, d.csq, d.Nap);
   }
 };
 

@@ -121,13 +121,24 @@ static_assert(CoopF32::BK == CoopB3::BK, "one K split");
 constexpr int kCB = 128;
 constexpr int kSymLD = kCB + 1;
 
-// Fresh similarity of one C-tile entry from its product (FP32 math, see
-// above); 0 outside the strictly-upper real part.
+// Fresh similarity of one C-tile entry from its product and the squared
+// norms nr = |W_.gr|^2, nc = |W_.gc|^2 (FP32 math, see above); 0 outside the
+// strictly-upper real part.
 __device__ __forceinline__ float coreg_sim(float acc, int64_t gr, int64_t gc, int64_t Na,
-                                           const double* __restrict__ ncol) {
+                                           double nr, double nc) {
   if (!(gr < gc && gc < Na)) return 0.0f;
-  const float den = (float)(ncol[gr] + ncol[gc] - fabs((double)acc));
+  const float den = (float)(nr + nc - fabs((double)acc));
   return den > 0.0f ? acc * __frsqrt_rn(den) : 0.0f;
+}
+
+// The squared norm this thread stages for tile (I, J): threads 0-127 the
+// tile's rows, 128-255 its columns.  Loaded before the tile's product (the
+// load is then long complete when the epilogue needs it).
+__device__ __forceinline__ double coreg_norm_load(const double* __restrict__ ncol, int64_t I,
+                                                  int64_t J, int64_t Na) {
+  const int t = threadIdx.x;
+  const int64_t k = t < kCB ? I * kCB + t : J * kCB + (t - kCB);
+  return k < Na ? ncol[k] : 0.0;
 }
 
 // Everything of the C update after the similarities of tile (I, J) are
@@ -247,15 +258,23 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
   }
 }
 
-// The C update of tile (I, J) from the accumulators of block GEMM g.
+// The C update of tile (I, J) from the accumulators of block GEMM g; nval
+// is this thread's coreg_norm_load, staged in LDS beside the tile.
+template <bool SIGT>
+constexpr int coreg_tile_bytes() {
+  return kCB * kSymLD * 4 * (SIGT ? 2 : 1);
+}
 template <bool SIGT, class G>
 __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I, int64_t J,
                                                float* __restrict__ C, int64_t ldc, int64_t Na,
-                                               const double* __restrict__ ncol, double alpha,
+                                               double nval, double alpha,
                                                double2* __restrict__ cstat,
                                                double* __restrict__ csq, int64_t ldstat) {
-  static_assert(G::BM == kCB && G::BN == kCB, "square tiles");
+  static_assert(G::BM == kCB && G::BN == kCB && kThreads == 2 * kCB, "square tiles");
   const int64_t m0 = I * kCB, n0 = J * kCB;
+  double* nsh = reinterpret_cast<double*>(smem + coreg_tile_bytes<SIGT>());
+  nsh[threadIdx.x] = nval;
+  __syncthreads();
   coreg_tile_update<SIGT>(
       [&](auto&& f) {
 #pragma unroll
@@ -265,17 +284,18 @@ __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int rr = g.row_of(i, r), c = g.col_of(j);
-              f(rr, c, coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, ncol));
+              f(rr, c, coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, nsh[rr], nsh[kCB + c]));
             }
       },
       smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat);
 }
 
 // Shared memory of the C update with block GEMM G: the larger of the main
-// loop's stages and the staged tile (two tiles with SIGT).
+// loop's stages and the staged tile (two tiles with SIGT) with the 256
+// staged norms.
 template <class G, bool SIGT>
 constexpr int coreg_smem_bytes() {
-  constexpr int TILE = kCB * kSymLD * 4 * (SIGT ? 2 : 1);
+  constexpr int TILE = coreg_tile_bytes<SIGT>() + 2 * kCB * 8;
   return G::MAIN_BYTES > TILE ? G::MAIN_BYTES : TILE;
 }
 

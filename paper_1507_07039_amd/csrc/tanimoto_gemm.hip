@@ -31,9 +31,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const uint32_t ij = order[xcd_tile(blockIdx.x, gridDim.x)];
   const int64_t I = ij & 0xffff, J = ij >> 16;
   const int64_t m0 = I * kCB, n0 = J * kCB;
+  const double nval = coreg_norm_load(ncol, I, J, Na);
   G g;
   g.run(ops, m0, n0, 0, Kp, smem);
-  coreg_epilogue<SIGT>(g, smem, I, J, C, ldc, Na, ncol, alpha, cstat, csq, ldstat);
+  coreg_epilogue<SIGT>(g, smem, I, J, C, ldc, Na, nval, alpha, cstat, csq, ldstat);
 }
 
 // Pearson correlations: one upper 128 x 128 tile of Z Z^T per block, both
