@@ -164,11 +164,14 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
   });
   __syncthreads();
   const float keep = (float)(1.0 - alpha), alf = (float)alpha;
+  // C (N_a^2 entries, far beyond the last-level cache) is read and written
+  // with non-temporal hints: no block reads it again before it is evicted.
   f4 old[kChunks];
 #pragma unroll
   for (int k = 0; k < kChunks; ++k) {  // all old values in flight together
     const int id = t + k * kThreads, rr = id / kC4, c = (id % kC4) * 4;
-    old[k] = *reinterpret_cast<const f4*>(C + (m0 + rr) * ldc + n0 + c);
+    old[k] = __builtin_nontemporal_load(
+        reinterpret_cast<const f4*>(C + (m0 + rr) * ldc + n0 + c));
   }
 #pragma unroll
   for (int k = 0; k < kChunks; ++k) {
@@ -187,7 +190,7 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
     if (I != J) {
       // every entry of an upper off-diagonal tile is strictly upper; padding
       // columns keep their zeros
-      *reinterpret_cast<f4*>(dst) = nv;
+      __builtin_nontemporal_store(nv, reinterpret_cast<f4*>(dst));
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -206,7 +209,7 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
     for (int e = 0; e < 4; ++e) v[e] = ts[(p + e) * kSymLD + q];
     float* dst = C + gj * ldc + gi;
     if (gi + 3 < gj) {
-      *reinterpret_cast<f4*>(dst) = v;
+      __builtin_nontemporal_store(v, reinterpret_cast<f4*>(dst));
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -316,12 +319,13 @@ __device__ __forceinline__ void corr_sym_epilogue(const G& g, char* smem, int64_
   const int c = threadIdx.x % kCB, r0 = threadIdx.x / kCB;
   for (int rr = r0; rr < kCB; rr += kRows) {
     const int64_t gr = m0 + rr, gc = n0 + c;
-    if (gr < n && gc < n) C[gr * ldc + gc] = gr == gc ? 1.0f : ts[rr * kSymLD + c];
+    if (gr < n && gc < n)
+      __builtin_nontemporal_store(gr == gc ? 1.0f : ts[rr * kSymLD + c], C + gr * ldc + gc);
   }
   if (I == J) return;  // a diagonal tile holds both triangles itself
   for (int q = r0; q < kCB; q += kRows) {
     const int64_t gr = n0 + q, gc = m0 + c;
-    if (gr < n && gc < n) C[gr * ldc + gc] = ts[c * kSymLD + q];
+    if (gr < n && gc < n) __builtin_nontemporal_store(ts[c * kSymLD + q], C + gr * ldc + gc);
   }
 }
 

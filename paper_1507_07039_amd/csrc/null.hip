@@ -46,7 +46,8 @@ __global__ __launch_bounds__(kPermNT) void k_permute_sym_lds(const float* __rest
     for (int64_t j = threadIdx.x; j < n; j += kPermNT) row[j] = src[j];
     __syncthreads();
     float* dst = out + i * ldo;
-    for (int64_t j = threadIdx.x; j < n; j += kPermNT) dst[j] = row[perm[j]];
+    for (int64_t j = threadIdx.x; j < n; j += kPermNT)
+      __builtin_nontemporal_store(row[perm[j]], dst + j);  // not read again here
   }
 }
 
