@@ -227,8 +227,11 @@ panda_status panda_ctx_phase_times(panda_ctx* ctx, double* total_ms, int64_t* co
  * all networks (persistent kernels over per-XCD work queues for the four
  * similarity products); a network stops being updated once its own h < tol
  * (its convergence mask), while the others go on.  One iteration can be
- * captured in a HIP graph and replayed.  FP32 arithmetic only (precision must
- * be PANDA_PREC_FP32).  All matrices are device pointers, row-major FP32.
+ * captured in a HIP graph and replayed.  precision PANDA_PREC_FP32 or
+ * PANDA_PREC_BF16X3 (the split-BF16 products of a context with the same
+ * option; such a batch has one tiling for R, A + W and the C update, tile
+ * choice 0, and the autotuner varies only the W W^T K chunk).  All matrices
+ * are device pointers, row-major FP32.
  *
  * Workspace: panda_batch_workspace_bytes(n, Ne, Na, opt) bytes, 256-byte
  * aligned, owned by the caller; it holds each network's state (about what a
@@ -244,8 +247,9 @@ panda_status panda_batch_create(int32_t n, const int64_t* Ne, const int64_t* Na,
 void panda_batch_destroy(panda_batch* b);
 
 /* Tile choices of the grouped products, one per entry of the enum below;
- * panda_batch_tile_candidates(phase) gives how many exist (choice in
- * [0, count)).  set_tiles validates every entry and rebuilds the work lists
+ * panda_batch_tile_candidates(phase) gives how many exist for an FP32 batch
+ * (choice in [0, count); a split-BF16 batch accepts only choice 0 for R, A + W
+ * and the C update).  set_tiles validates every entry and rebuilds the work lists
  * (synchronises the stream).  autotune times every candidate of every phase
  * on the batch's own shapes (reps timed launches each, best time wins) and
  * keeps the fastest; it overwrites the whole state, so it must precede

@@ -43,10 +43,11 @@ struct panda_batch {
     WorkList wl;
     int64_t nb;
   } lists[kNumLists];
-  // flat grids: norms (part, sum), P finalisation, diagonals
-  int64_t* d_flat[4];
-  std::vector<int64_t> h_flat[4];
-  FlatList flat[4];
+  // flat grids: norms (part, sum), P finalisation, diagonals, W planes
+  int64_t* d_flat[5];
+  std::vector<int64_t> h_flat[5];
+  FlatList flat[5];
+  bool b3;  // split-BF16 products
   int32_t* ctr;
   DevState* d_states;
   DevState* h_states;  // pinned
@@ -59,11 +60,12 @@ struct panda_batch {
 
 namespace {
 
-enum { kFlatPart = 0, kFlatSum = 1, kFlatPfin = 2, kFlatDiag = 3 };
+enum { kFlatPart = 0, kFlatSum = 1, kFlatPfin = 2, kFlatDiag = 3, kFlatPlanes = 4, kNumFlat = 5 };
 
 // Layout of the whole batch workspace: header (descriptors, work lists,
 // counters, state gather buffer), then each network's region.
-size_t batch_layout(int32_t n, const int64_t* Ne, const int64_t* Na, panda_batch* b, char* base) {
+size_t batch_layout(int32_t n, const int64_t* Ne, const int64_t* Na, int32_t precision,
+                    panda_batch* b, char* base) {
   Carver cv{base};
   BInst* di = cv.take<BInst>((size_t)n);
   int32_t* si[kNumLists];
@@ -72,8 +74,8 @@ size_t batch_layout(int32_t n, const int64_t* Ne, const int64_t* Na, panda_batch
     si[l] = cv.take<int32_t>((size_t)n);
     sf[l] = cv.take<int64_t>((size_t)n + 1);
   }
-  int64_t* fl[4];
-  for (int f = 0; f < 4; ++f) fl[f] = cv.take<int64_t>((size_t)n + 1);
+  int64_t* fl[kNumFlat];
+  for (int f = 0; f < kNumFlat; ++f) fl[f] = cv.take<int64_t>((size_t)n + 1);
   int32_t* ctr = cv.take<int32_t>((size_t)kCtrCount);
   DevState* ds = cv.take<DevState>((size_t)n);
   if (b) {
@@ -82,13 +84,13 @@ size_t batch_layout(int32_t n, const int64_t* Ne, const int64_t* Na, panda_batch
       b->lists[l].d_seg_inst = si[l];
       b->lists[l].d_seg_first = sf[l];
     }
-    for (int f = 0; f < 4; ++f) b->d_flat[f] = fl[f];
+    for (int f = 0; f < kNumFlat; ++f) b->d_flat[f] = fl[f];
     b->ctr = ctr;
     b->d_states = ds;
   }
   for (int32_t i = 0; i < n; ++i) {
     char* ib = base ? base + cv.off : nullptr;
-    const size_t sz = ctx_layout(Ne[i], Na[i], PANDA_PREC_FP32, batch_spec(Ne[i], Na[i]),
+    const size_t sz = ctx_layout(Ne[i], Na[i], precision, batch_spec(Ne[i], Na[i]),
                                  b ? &b->ctx[(size_t)i] : nullptr, ib);
     cv.off += align_up(sz);
   }
@@ -170,7 +172,7 @@ panda_status build_list(panda_batch* b, int phase) {
   wl.nseg = n;
   wl.ctr = b->ctr + (int64_t)phase * kNumXcd * kCtrStride;
   L.wl = wl;
-  L.nb = batch_grid(phase, b->tiles[phase], b->rule.sigma_from_T != 0);
+  L.nb = batch_grid(phase, b->tiles[phase], b->rule.sigma_from_T != 0, b->b3);
   HIP_TRY(hipMemcpyAsync(L.d_seg_inst, L.seg_inst.data(), (size_t)n * sizeof(int32_t),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(L.d_seg_first, L.seg_first.data(), ((size_t)n + 1) * sizeof(int64_t),
@@ -211,6 +213,12 @@ panda_status upload_insts(panda_batch* b) {
     d.csq = c.csq;
     d.corder = c.corder;
     d.st = c.st;
+    d.Wh = c.Wh;
+    d.Wl = c.Wl;
+    d.Wth = c.Wth;
+    d.Wtl = c.Wtl;
+    d.Ph = c.Ph;
+    d.Pl = c.Pl;
     d.nh = (c.Nep / bm) * (c.Nap / bn);
     d.chunk = chunk;
     d.splits = (c.Nap + chunk - 1) / chunk;
@@ -224,15 +232,17 @@ panda_status upload_insts(panda_batch* b) {
 // Flat grids (network order): blocks per network of each element phase.
 panda_status build_flat(panda_batch* b) {
   const int32_t n = b->n;
-  for (int f = 0; f < 4; ++f) b->h_flat[f].assign((size_t)n + 1, 0);
+  for (int f = 0; f < kNumFlat; ++f) b->h_flat[f].assign((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; ++i) {
     const panda_ctx& c = b->ctx[(size_t)i];
     const int64_t gx = (c.Na + upd::kUT - 1) / upd::kUT;
-    const int64_t cnt[4] = {c.Ne + gx * upd::col_chunks(c.Ne), gx,
-                            (c.Ne * c.Ne + upd::kUT - 1) / upd::kUT, c.Ne + gx};
-    for (int f = 0; f < 4; ++f) b->h_flat[f][(size_t)i + 1] = b->h_flat[f][(size_t)i] + cnt[f];
+    const int64_t cnt[kNumFlat] = {c.Ne + gx * upd::col_chunks(c.Ne), gx,
+                                   (c.Ne * c.Ne + upd::kUT - 1) / upd::kUT, c.Ne + gx,
+                                   b->b3 ? (c.Nep / 64) * (c.Nap / 64) : 0};
+    for (int f = 0; f < kNumFlat; ++f)
+      b->h_flat[f][(size_t)i + 1] = b->h_flat[f][(size_t)i] + cnt[f];
   }
-  for (int f = 0; f < 4; ++f) {
+  for (int f = 0; f < kNumFlat; ++f) {
     if (b->h_flat[f][(size_t)n] >= ((int64_t)1 << 31))
       return fail(PANDA_ERR_ARG, "batch: grid too large%s");
     b->flat[f] = FlatList{b->d_flat[f], n, b->h_flat[f][(size_t)n]};
@@ -246,12 +256,15 @@ panda_status build_flat(panda_batch* b) {
 panda_status launch_phase(panda_batch* b, int phase, hipStream_t s) {
   const auto& L = b->lists[phase];
   switch (phase) {
-    case kBTResp: HIP_TRY(launch_batch_resp(b->tiles[phase], b->d_inst, L.wl, L.nb, s)); break;
-    case kBTAvail:
-      HIP_TRY(launch_batch_avail(b->tiles[phase], b->d_inst, L.wl, b->rule, L.nb, s));
+    case kBTResp:
+      HIP_TRY(launch_batch_resp(b->tiles[phase], b->b3, b->d_inst, L.wl, L.nb, s));
       break;
-    case kBTCoop: HIP_TRY(launch_batch_coop_partial(b->d_inst, L.wl, L.nb, s)); break;
-    default: HIP_TRY(launch_batch_coreg(b->tiles[phase], b->d_inst, L.wl, b->rule, L.nb, s));
+    case kBTAvail:
+      HIP_TRY(launch_batch_avail(b->tiles[phase], b->b3, b->d_inst, L.wl, b->rule, L.nb, s));
+      break;
+    case kBTCoop: HIP_TRY(launch_batch_coop_partial(b->b3, b->d_inst, L.wl, L.nb, s)); break;
+    default:
+      HIP_TRY(launch_batch_coreg(b->tiles[phase], b->b3, b->d_inst, L.wl, b->rule, L.nb, s));
   }
   return PANDA_OK;
 }
@@ -264,6 +277,7 @@ panda_status enqueue_batch_iteration(panda_batch* b, hipStream_t s) {
   PANDA_TRY(launch_phase(b, kBTAvail, s));
   HIP_TRY(launch_batch_finish_h(b->d_inst, b->n, b->rule, s));
   HIP_TRY(launch_batch_norms(b->d_inst, b->flat[kFlatPart], b->flat[kFlatSum], s));
+  if (b->b3) HIP_TRY(launch_batch_planes(b->d_inst, b->flat[kFlatPlanes], s));
   PANDA_TRY(launch_phase(b, kBTCoop, s));
   HIP_TRY(launch_batch_coop_finalize(b->d_inst, b->flat[kFlatPfin], b->rule, s));
   PANDA_TRY(launch_phase(b, kBTCoreg, s));
@@ -329,9 +343,8 @@ extern "C" {
 
 size_t panda_batch_workspace_bytes(int32_t n, const int64_t* Ne, const int64_t* Na,
                                    const panda_options* opt) {
-  (void)opt;
   if (check_shapes(n, Ne, Na) != PANDA_OK) return 0;
-  return batch_layout(n, Ne, Na, nullptr, nullptr);
+  return batch_layout(n, Ne, Na, opt ? opt->precision : PANDA_PREC_FP32, nullptr, nullptr);
 }
 
 panda_status panda_batch_create(int32_t n, const int64_t* Ne, const int64_t* Na,
@@ -346,9 +359,7 @@ panda_status panda_batch_create(int32_t n, const int64_t* Ne, const int64_t* Na,
   else
     panda_default_options(&o);
   PANDA_TRY(check_options(o));
-  if (o.precision != PANDA_PREC_FP32)
-    return fail(PANDA_ERR_ARG, "batch_create: the batched form computes in FP32 only%s");
-  if (!workspace || ws_bytes < batch_layout(n, Ne, Na, nullptr, nullptr) ||
+  if (!workspace || ws_bytes < batch_layout(n, Ne, Na, o.precision, nullptr, nullptr) ||
       (reinterpret_cast<uintptr_t>(workspace) % kAlign))
     return fail(PANDA_ERR_WORKSPACE, "batch_create: workspace too small or misaligned%s");
   panda_batch* b = new (std::nothrow) panda_batch();
@@ -357,8 +368,9 @@ panda_status panda_batch_create(int32_t n, const int64_t* Ne, const int64_t* Na,
   b->opt = o;
   b->rule = rule_of(o);
   b->stream = stream;
+  b->b3 = o.precision == PANDA_PREC_BF16X3;
   b->ctx.resize((size_t)n);
-  batch_layout(n, Ne, Na, b, static_cast<char*>(workspace));
+  batch_layout(n, Ne, Na, o.precision, b, static_cast<char*>(workspace));
   panda_status st = PANDA_OK;
   for (int32_t i = 0; i < n && st == PANDA_OK; ++i) {
     char* ib = reinterpret_cast<char*>(b->ctx[(size_t)i].W[0]);  // start of network i's region
@@ -402,7 +414,7 @@ panda_status panda_batch_get_tiles(const panda_batch* b, int32_t* choice) {
 panda_status panda_batch_set_tiles(panda_batch* b, const int32_t* choice) {
   if (!b || !choice) return fail(PANDA_ERR_ARG, "batch_set_tiles: NULL argument%s");
   for (int l = 0; l < kNumLists; ++l)
-    if (choice[l] < 0 || choice[l] >= batch_tile_candidates(l))
+    if (choice[l] < 0 || choice[l] >= batch_tile_candidates(l, b->b3))
       return fail(PANDA_ERR_ARG, "batch_set_tiles: choice out of range%s");
   for (int l = 0; l < kNumLists; ++l) b->tiles[l] = choice[l];
   return apply_tiles(b);
@@ -413,7 +425,7 @@ panda_status panda_batch_autotune(panda_batch* b, int32_t reps, float* best_ms) 
   hipStream_t s = b->stream;
   // zero state: every network's region (the order tables are written again)
   for (auto& c : b->ctx) {
-    const size_t bytes = ctx_layout(c.Ne, c.Na, PANDA_PREC_FP32, batch_spec(c.Ne, c.Na), nullptr,
+    const size_t bytes = ctx_layout(c.Ne, c.Na, b->opt.precision, batch_spec(c.Ne, c.Na), nullptr,
                                     nullptr);
     HIP_TRY(hipMemsetAsync(c.W[0], 0, bytes, s));
     c.loaded = false;
@@ -428,7 +440,7 @@ panda_status panda_batch_autotune(panda_batch* b, int32_t reps, float* best_ms) 
   for (int phase = 0; phase < kNumLists && st == PANDA_OK; ++phase) {
     float best = 1e30f;
     int bestc = 0;
-    for (int c = 0; c < batch_tile_candidates(phase) && st == PANDA_OK; ++c) {
+    for (int c = 0; c < batch_tile_candidates(phase, b->b3) && st == PANDA_OK; ++c) {
       b->tiles[phase] = c;
       st = build_list(b, phase);
       if (st == PANDA_OK) st = upload_insts(b);

@@ -29,6 +29,9 @@ struct BInst {
   double* csq;
   const uint32_t* corder;
   DevState* st;
+  // split-BF16 batches: operand planes of W (row-major, and gene-major as
+  // W^T) and of P's off-diagonal part; null in FP32 batches
+  bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl;
   int64_t nh;      // h partials written by the chosen A + W tiling
   int64_t splits;  // K splits of the W W^T partials for the chosen chunk
   int64_t chunk;   // K columns per split
@@ -58,22 +61,27 @@ struct FlatList {
 };
 
 // Tile candidates of the grouped products (the autotuner picks one each).
+// A split-BF16 batch (b3) has one tiling for R, A + W and the C update (the
+// shapes of candidate 0) and the same K chunks for W W^T.
 enum BatchTile { kBTResp = 0, kBTAvail = 1, kBTCoop = 2, kBTCoreg = 3, kBTNum = 4 };
-int batch_tile_candidates(int phase);
+int batch_tile_candidates(int phase, bool b3 = false);
 void rect_tile_shape(int choice, int64_t* bm, int64_t* bn);  // R and A + W tiles
 int64_t coop_chunk_of(int choice);                           // K chunk of W W^T
 // Persistent grid of a grouped product with candidate `choice` (sigT: the
 // C-update variant that keeps the similarity sums).
-int64_t batch_grid(int phase, int choice, bool sigT);
+int64_t batch_grid(int phase, int choice, bool sigT, bool b3);
 
-hipError_t launch_batch_resp(int choice, const BInst* bi, const WorkList& wl, int64_t nb,
+hipError_t launch_batch_resp(int choice, bool b3, const BInst* bi, const WorkList& wl, int64_t nb,
                              hipStream_t s);
-hipError_t launch_batch_avail(int choice, const BInst* bi, const WorkList& wl, Rule rule,
+hipError_t launch_batch_avail(int choice, bool b3, const BInst* bi, const WorkList& wl, Rule rule,
                               int64_t nb, hipStream_t s);
-hipError_t launch_batch_coop_partial(const BInst* bi, const WorkList& wl, int64_t nb,
+hipError_t launch_batch_coop_partial(bool b3, const BInst* bi, const WorkList& wl, int64_t nb,
                                      hipStream_t s);
-hipError_t launch_batch_coreg(int choice, const BInst* bi, const WorkList& wl, Rule rule,
+hipError_t launch_batch_coreg(int choice, bool b3, const BInst* bi, const WorkList& wl, Rule rule,
                               int64_t nb, hipStream_t s);
+// bf16 planes of the new W (split-BF16 batches): (Nep / 64) x (Nap / 64)
+// blocks per network.
+hipError_t launch_batch_planes(const BInst* bi, const FlatList& fl, hipStream_t s);
 hipError_t launch_batch_finish_h(const BInst* bi, int32_t n, Rule rule, hipStream_t s);
 // norms of the new W: part = Ne row blocks + (col groups x row chunks) per
 // network; sum = col groups per network.

@@ -29,6 +29,15 @@ using SymT1 = BlockGemm<128, 128, 2, 2, false, false, 32>;
 using SymT2 = BlockGemm<128, 128, 1, 4, false, false, 16>;
 using CoopT = BlockGemm<64, 64, 2, 2, true, true, 32>;
 constexpr int64_t kCoopChunks[4] = {512, 1024, 2048, 4096};
+// Split-BF16 batches: the tilings of candidate 0 on the split-BF16 block
+// GEMMs of the single-network form (R register-staged; A + W with direct
+// loads and C split as it is read, 64 x 128 so that the item lists are those
+// of candidate 0; W W^T and the C update as in the single-network form).
+using RectB3A = BlockGemmB3P<64, 128, 1, 4, true, 3>;
+static_assert(RectB3::BM == RectT0::BM && RectB3::BN == RectT0::BN &&
+                  RectB3A::BM == RectT0::BM && RectB3A::BN == RectT0::BN &&
+                  SymB3::BM == SymT0::BM && CoopB3::BM == CoopT::BM && CoopB3::BK == CoopT::BK,
+              "split-BF16 tiles share the work lists of candidate 0");
 
 // Largest s with seg_first[s] <= it.
 __device__ __forceinline__ int find_segment(const int64_t* __restrict__ first, int nseg,
@@ -45,7 +54,9 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ first, i
 }
 
 // --------------------------------------------------------------- phases --
-// R = T(P, W) (Eq. 3) for one tile.
+// R = T(P, W) (Eq. 3) for one tile.  B3: split-BF16 products on the planes
+// of P and of W^T.
+template <bool B3>
 struct PhResp {
   template <class G>
   static constexpr int smem_bytes() { return G::MAIN_BYTES; }
@@ -57,14 +68,18 @@ struct PhResp {
     const int64_t nMT = d.Nep / G::BM;
     const int64_t m0 = (local % nMT) * G::BM, n0 = (local / nMT) * G::BN;
     G g;
-    g.run(OpsF32{d.P, d.Nep, W, d.Nap}, m0, n0, 0, d.Nep, smem);
+    if constexpr (B3)
+      g.run(OpsB3{d.Ph, d.Pl, d.Nep, d.Wth, d.Wtl, d.Nep}, m0, n0, 0, d.Nep, smem);
+    else
+      g.run(OpsF32{d.P, d.Nep, W, d.Nap}, m0, n0, 0, d.Nep, smem);
     EpiStoreT epi{d.R, d.Nap, d.Ne, d.Na, d.nP, d.nWc, d.dP, W, d.Nap};
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
   }
 };
 
 // A = T(W, C) (Eq. 4) fused with the W update (Eq. 2) and the tile's h
-// partial (Eq. 7).
+// partial (Eq. 7).  B3: W's planes against C split as it is read.
+template <bool B3>
 struct PhAvail {
   double alpha;
   int32_t h_undamped;
@@ -80,7 +95,10 @@ struct PhAvail {
     const int64_t nMT = d.Nep / G::BM;
     const int64_t m0 = (local % nMT) * G::BM, n0 = (local / nMT) * G::BN;
     G g;
-    g.run(OpsF32{Wold, d.Nap, d.C, d.Nap}, m0, n0, 0, d.Nap, smem);
+    if constexpr (B3)
+      g.run(OpsB3F{d.Wh, d.Wl, d.Nap, d.C, d.Nap, d.Nep}, m0, n0, 0, d.Nap, smem);
+    else
+      g.run(OpsF32{Wold, d.Nap, d.C, d.Nap}, m0, n0, 0, d.Nap, smem);
     EpiWUpdate epi{Wold, d.R,   d.W[ws ^ 1], d.Nap, d.Ne,       d.Na,    d.nWr,
                    d.nC, d.dC,  alpha,       h_undamped, d.hpart, 0.0};
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
@@ -89,7 +107,8 @@ struct PhAvail {
 };
 
 // W W^T partial product of one upper 64 x 64 tile over one K chunk (first
-// half of the P update, Eq. 5).
+// half of the P update, Eq. 5).  B3: on W's planes.
+template <bool B3>
 struct PhCoop {
   template <class G>
   static constexpr int smem_bytes() { return G::MAIN_BYTES; }
@@ -106,15 +125,18 @@ struct PhCoop {
     int64_t kb = sp * d.chunk, ke = kb + d.chunk;
     if (ke > d.Nap) ke = d.Nap;
     G g;
-    g.run(OpsF32{W, d.Nap, W, d.Nap}, m0, n0, kb, ke, smem);
+    if constexpr (B3)
+      g.run(OpsB3{d.Wh, d.Wl, d.Nap, d.Wh, d.Wl, d.Nap}, m0, n0, kb, ke, smem);
+    else
+      g.run(OpsF32{W, d.Nap, W, d.Nap}, m0, n0, kb, ke, smem);
     float* ps = d.ppart + sp * d.Nep * d.Nep;
     g.for_each([&](int r, int c, float v) { ps[(m0 + r) * d.Nep + n0 + c] = v; });
   }
 };
 
 // C update (Eq. 5) of one upper 128 x 128 tile, mirrored, with the row sums
-// for the sigma of Eq. 6.
-template <bool SIGT>
+// for the sigma of Eq. 6.  B3: on the planes of W^T.
+template <bool SIGT, bool B3>
 struct PhCoreg {
   double alpha;
   template <class G>
@@ -128,7 +150,10 @@ struct PhCoreg {
     const int64_t I = ij & 0xffff, J = ij >> 16;
     const double nval = coreg_norm_load(d.nWc, I, J, d.Na);
     G g;
-    g.run(OpsF32{W, d.Nap, W, d.Nap}, I * kCB, J * kCB, 0, d.Nep, smem);
+    if constexpr (B3)
+      g.run(OpsB3{d.Wth, d.Wtl, d.Nep, d.Wth, d.Wtl, d.Nep}, I * kCB, J * kCB, 0, d.Nep, smem);
+    else
+      g.run(OpsF32{W, d.Nap, W, d.Nap}, I * kCB, J * kCB, 0, d.Nep, smem);
     coreg_epilogue<SIGT>(g, smem, I, J, d.C, d.Nap, d.Na, nval, alpha, d.cstat, d.csq, d.Nap);
   }
 };
@@ -209,6 +234,42 @@ __global__ __launch_bounds__(kUT) void k_batch_norms_sum(const BInst* __restrict
   d.nWc[j] = s;
 }
 
+// bf16 planes of the new W, one 64 x 64 tile per block: row-major (read
+// along rows) and, through LDS, gene-major (written along its rows).  Only
+// the real Ne x Na region is written; the padding stays zero from the load.
+__global__ __launch_bounds__(kUT) void k_batch_planes(const BInst* __restrict__ bi, FlatList fl) {
+  __shared__ float tile[64][65];
+  const int seg = find_segment(fl.seg_first, fl.nseg, blockIdx.x);
+  const BInst& d = bi[seg];
+  if (d.st->run_pc == 0) return;
+  const float* W = d.W[d.st->wsel];
+  const int64_t q = (int64_t)blockIdx.x - fl.seg_first[seg], nbx = d.Nap / 64;
+  const int64_t r0 = (q / nbx) * 64, c0 = (q % nbx) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int rr = ty; rr < 64; rr += kUT / 64) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    float v = 0.0f;
+    if (r < d.Ne && c < d.Na) {
+      v = W[r * d.Nap + c];
+      bf16_t h, l;
+      upd::split_bf16(v, h, l);
+      d.Wh[r * d.Nap + c] = h;
+      d.Wl[r * d.Nap + c] = l;
+    }
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 64; cc += kUT / 64) {
+    const int64_t c = c0 + cc, r = r0 + tx;
+    if (r < d.Ne && c < d.Na) {
+      bf16_t h, l;
+      upd::split_bf16(tile[tx][cc], h, l);
+      d.Wth[c * d.Nep + r] = h;
+      d.Wtl[c * d.Nep + r] = l;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kUT) void k_batch_coop_finalize(const BInst* __restrict__ bi,
                                                              FlatList fl, double alpha,
                                                              int32_t sigma_from_T) {
@@ -217,7 +278,7 @@ __global__ __launch_bounds__(kUT) void k_batch_coop_finalize(const BInst* __rest
   if (d.st->run_pc == 0) return;
   const int64_t e = ((int64_t)blockIdx.x - fl.seg_first[seg]) * kUT + threadIdx.x;
   upd::coop_finalize_entry(e, d.ppart, (int)d.splits, d.Nep, d.nWr, d.P, d.Nep, d.Ne, alpha,
-                           sigma_from_T ? d.Tside : nullptr, nullptr, nullptr);
+                           sigma_from_T ? d.Tside : nullptr, d.Ph, d.Pl);
 }
 
 // Eq. 6: blocks [0, Ne) are rows of P, the rest cover the rows of C, one
@@ -284,11 +345,11 @@ int64_t group_grid() {
 
 // ------------------------------------------------------------ launchers --
 
-int batch_tile_candidates(int phase) {
+int batch_tile_candidates(int phase, bool b3) {
   switch (phase) {
     case kBTResp:
     case kBTAvail:
-    case kBTCoreg: return 3;
+    case kBTCoreg: return b3 ? 1 : 3;
     case kBTCoop: return 4;
   }
   return 0;
@@ -304,62 +365,87 @@ void rect_tile_shape(int choice, int64_t* bm, int64_t* bn) {
 
 int64_t coop_chunk_of(int choice) { return kCoopChunks[choice < 0 || choice > 3 ? 0 : choice]; }
 
-int64_t batch_grid(int phase, int choice, bool sigT) {
+int64_t batch_grid(int phase, int choice, bool sigT, bool b3) {
+  if (b3) {
+    switch (phase) {
+      case kBTResp: return group_grid<RectB3, PhResp<true>>();
+      case kBTAvail: return group_grid<RectB3A, PhAvail<true>>();
+      case kBTCoop: return group_grid<CoopB3, PhCoop<true>>();
+      case kBTCoreg:
+        return sigT ? group_grid<SymB3, PhCoreg<true, true>>()
+                    : group_grid<SymB3, PhCoreg<false, true>>();
+    }
+    return 0;
+  }
   switch (phase) {
     case kBTResp:
-      if (choice == 1) return group_grid<RectT1, PhResp>();
-      if (choice == 2) return group_grid<RectT2, PhResp>();
-      return group_grid<RectT0, PhResp>();
+      if (choice == 1) return group_grid<RectT1, PhResp<false>>();
+      if (choice == 2) return group_grid<RectT2, PhResp<false>>();
+      return group_grid<RectT0, PhResp<false>>();
     case kBTAvail:
-      if (choice == 1) return group_grid<RectT1, PhAvail>();
-      if (choice == 2) return group_grid<RectT2, PhAvail>();
-      return group_grid<RectT0, PhAvail>();
-    case kBTCoop: return group_grid<CoopT, PhCoop>();
+      if (choice == 1) return group_grid<RectT1, PhAvail<false>>();
+      if (choice == 2) return group_grid<RectT2, PhAvail<false>>();
+      return group_grid<RectT0, PhAvail<false>>();
+    case kBTCoop: return group_grid<CoopT, PhCoop<false>>();
     case kBTCoreg:
       if (sigT) {
-        if (choice == 1) return group_grid<SymT1, PhCoreg<true>>();
-        if (choice == 2) return group_grid<SymT2, PhCoreg<true>>();
-        return group_grid<SymT0, PhCoreg<true>>();
+        if (choice == 1) return group_grid<SymT1, PhCoreg<true, false>>();
+        if (choice == 2) return group_grid<SymT2, PhCoreg<true, false>>();
+        return group_grid<SymT0, PhCoreg<true, false>>();
       }
-      if (choice == 1) return group_grid<SymT1, PhCoreg<false>>();
-      if (choice == 2) return group_grid<SymT2, PhCoreg<false>>();
-      return group_grid<SymT0, PhCoreg<false>>();
+      if (choice == 1) return group_grid<SymT1, PhCoreg<false, false>>();
+      if (choice == 2) return group_grid<SymT2, PhCoreg<false, false>>();
+      return group_grid<SymT0, PhCoreg<false, false>>();
   }
   return 0;
 }
 
-hipError_t launch_batch_resp(int choice, const BInst* bi, const WorkList& wl, int64_t nb,
+hipError_t launch_batch_resp(int choice, bool b3, const BInst* bi, const WorkList& wl, int64_t nb,
                              hipStream_t s) {
-  if (choice == 1) return group_launch<RectT1>(bi, wl, PhResp{}, nb, s);
-  if (choice == 2) return group_launch<RectT2>(bi, wl, PhResp{}, nb, s);
-  return group_launch<RectT0>(bi, wl, PhResp{}, nb, s);
+  if (b3) return group_launch<RectB3>(bi, wl, PhResp<true>{}, nb, s);
+  if (choice == 1) return group_launch<RectT1>(bi, wl, PhResp<false>{}, nb, s);
+  if (choice == 2) return group_launch<RectT2>(bi, wl, PhResp<false>{}, nb, s);
+  return group_launch<RectT0>(bi, wl, PhResp<false>{}, nb, s);
 }
 
-hipError_t launch_batch_avail(int choice, const BInst* bi, const WorkList& wl, Rule rule,
+hipError_t launch_batch_avail(int choice, bool b3, const BInst* bi, const WorkList& wl, Rule rule,
                               int64_t nb, hipStream_t s) {
-  const PhAvail ph{rule.alpha, rule.h_undamped};
+  if (b3) return group_launch<RectB3A>(bi, wl, PhAvail<true>{rule.alpha, rule.h_undamped}, nb, s);
+  const PhAvail<false> ph{rule.alpha, rule.h_undamped};
   if (choice == 1) return group_launch<RectT1>(bi, wl, ph, nb, s);
   if (choice == 2) return group_launch<RectT2>(bi, wl, ph, nb, s);
   return group_launch<RectT0>(bi, wl, ph, nb, s);
 }
 
-hipError_t launch_batch_coop_partial(const BInst* bi, const WorkList& wl, int64_t nb,
+hipError_t launch_batch_coop_partial(bool b3, const BInst* bi, const WorkList& wl, int64_t nb,
                                      hipStream_t s) {
-  return group_launch<CoopT>(bi, wl, PhCoop{}, nb, s);
+  if (b3) return group_launch<CoopB3>(bi, wl, PhCoop<true>{}, nb, s);
+  return group_launch<CoopT>(bi, wl, PhCoop<false>{}, nb, s);
 }
 
-hipError_t launch_batch_coreg(int choice, const BInst* bi, const WorkList& wl, Rule rule,
+hipError_t launch_batch_coreg(int choice, bool b3, const BInst* bi, const WorkList& wl, Rule rule,
                               int64_t nb, hipStream_t s) {
+  if (b3) {
+    if (rule.sigma_from_T)
+      return group_launch<SymB3>(bi, wl, PhCoreg<true, true>{rule.alpha}, nb, s);
+    return group_launch<SymB3>(bi, wl, PhCoreg<false, true>{rule.alpha}, nb, s);
+  }
   if (rule.sigma_from_T) {
-    const PhCoreg<true> ph{rule.alpha};
+    const PhCoreg<true, false> ph{rule.alpha};
     if (choice == 1) return group_launch<SymT1>(bi, wl, ph, nb, s);
     if (choice == 2) return group_launch<SymT2>(bi, wl, ph, nb, s);
     return group_launch<SymT0>(bi, wl, ph, nb, s);
   }
-  const PhCoreg<false> ph{rule.alpha};
+  const PhCoreg<false, false> ph{rule.alpha};
   if (choice == 1) return group_launch<SymT1>(bi, wl, ph, nb, s);
   if (choice == 2) return group_launch<SymT2>(bi, wl, ph, nb, s);
   return group_launch<SymT0>(bi, wl, ph, nb, s);
+}
+
+hipError_t launch_batch_planes(const BInst* bi, const FlatList& fl, hipStream_t s) {
+  if (fl.total == 0) return hipSuccess;
+  k_batch_planes<<<dim3((unsigned)fl.total), dim3(kUT), 0, s>>>(bi, fl);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_finish_h(const BInst* bi, int32_t n, Rule rule, hipStream_t s) {

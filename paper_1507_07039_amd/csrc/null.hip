@@ -7,6 +7,7 @@
 // Welford's update), against which the real network's edges are z-scored.
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "host_internal.h"

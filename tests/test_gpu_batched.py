@@ -212,6 +212,7 @@ def test_48_networks_full_size(torch, pd, oracle):
     assert status == pd.OK
     t_single = 0.0
     worst = 0.0
+    refs = []
     for i, d in enumerate(dev):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -223,5 +224,92 @@ def test_48_networks_full_size(torch, pd, oracle):
         rel = (Wg - ref.W).abs().max().item() / max(1.0, ref.W.abs().max().item())
         worst = max(worst, rel)
         assert rel <= 1e-3, (i, rel)
+        refs.append((ref.W, ref.iters))
     print(f"  batched run {t_batch:.3f} s ({steps} steps) vs {t_single:.3f} s for the 48 "
           f"networks one by one; worst max|dW|/max|W| = {worst:.2e}")
+    b.close()
+    del b
+    # the split-BF16 option on the same 48 networks, against the plain runs
+    b3 = pd.Batch([(T, G) for T, G, _ in shapes], pd.default_options(precision=1))
+    for i, d in enumerate(dev):
+        b3.load(i, *d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, steps3 = b3.run(graph=True)
+    torch.cuda.synchronize()
+    t_b3 = time.perf_counter() - t0
+    assert status == pd.OK
+    o3 = pd.default_options(precision=1)
+    worst3, worst_plain = 0.0, (0.0, -1)
+    for i, (Wref, itref) in enumerate(refs):
+        ref3 = pd.run(*dev[i], opts=o3)
+        Wg, _, _, _, tg = b3.state(i)
+        assert abs(tg - ref3.iters) <= 2, (i, tg, ref3.iters)
+        rel = (Wg - ref3.W).abs().max().item() / max(1.0, ref3.W.abs().max().item())
+        worst3 = max(worst3, rel)
+        assert rel <= 1e-3, (i, rel)
+        relp = (Wg - Wref).abs().max().item() / max(1.0, Wref.abs().max().item())
+        worst_plain = max(worst_plain, (relp, i))
+    print(f"  split-BF16 batched run {t_b3:.3f} s ({steps3} steps); worst max|dW|/max|W| "
+          f"against the split-BF16 single runs = {worst3:.2e}, against the plain runs = "
+          f"{worst_plain[0]:.2e} (network {worst_plain[1]}, {shapes[worst_plain[1]][:2]})")
+    b3.close()
+
+
+# ------------------------------------------------------ split-BF16 option --
+# Same error model and bounds as the single-network precision form
+# (tests/test_gpu_precision.py): W, P and C off the diagonal within 1e-3 of the
+# FP64 oracle per step, the diagonals within 1e-4 relative, h within 1e-3.
+
+def test_split_bf16_batch_matches_oracle(torch, pd, oracle):
+    nets = [prep(oracle, *I.workload_priors(I.SMALL)), ragged(65, 300), ragged(70, 257),
+            ragged(3, 5), small_like(oracle, 21, 130, 1000)]
+    b = new_batch(torch, pd, nets, tol=0.0, precision=1)
+    assert b.tiles[0] == 0 and b.tiles[1] == 0 and b.tiles[3] == 0
+    o = oracle.Options(tol=0.0)
+    refs = [list(n) for n in nets]
+    for t in range(1, 6):
+        assert b.iterate(1) == len(nets)
+        for i in range(len(nets)):
+            Wo, Po, Co, ho, _ = oracle.step(*refs[i], t, o)
+            refs[i] = [Wo, Po, Co]
+            Wg, Pg, Cg, hg, tg = b.state(i)
+            Wg, Pg, Cg = host(Wg), host(Pg), host(Cg)
+            Ne, Na = Wo.shape
+            assert tg == t
+            eW = np.abs(Wg - Wo).max()
+            eP = np.abs(Pg - Po)[~np.eye(Ne, dtype=bool)].max() if Ne > 1 else 0.0
+            eC = np.abs(Cg - Co)[~np.eye(Na, dtype=bool)].max()
+            assert eW <= 1e-3 and eP <= 1e-3 and eC <= 1e-3, (i, t, eW, eP, eC)
+            dP = np.abs(np.diag(Pg) - np.diag(Po)) / np.maximum(1, np.abs(np.diag(Po)))
+            dC = np.abs(np.diag(Cg) - np.diag(Co)) / np.maximum(1, np.abs(np.diag(Co)))
+            assert dP.max() <= 1e-4 and dC.max() <= 1e-4, (i, t)
+            assert np.array_equal(Pg, Pg.T) and np.array_equal(Cg, Cg.T)
+            assert abs(hg - ho) <= 1e-3 * ho, (i, t, hg, ho)
+    b.close()
+
+
+def test_split_bf16_batch_runs_like_single_networks(torch, pd, oracle):
+    """Whole runs with graph replays against each network run alone in the
+    split-BF16 form; the autotuner only chooses among the W W^T K chunks."""
+    nets = [small_like(oracle, s) for s in (1507, 11)] + [ragged(65, 300),
+                                                          small_like(oracle, 13, 130, 1000)]
+    b = new_batch(torch, pd, nets, precision=1)
+    with pytest.raises(pd.PandaError):
+        b.tiles = [1, 0, 0, 0]
+    best = b.autotune(reps=1)
+    assert b.tiles[0] == 0 and b.tiles[1] == 0 and b.tiles[3] == 0
+    for i, (W, P, C) in enumerate(nets):
+        b.load(i, cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    status, steps = b.run(graph=True)
+    assert status == pd.OK
+    o = pd.default_options(precision=1)
+    for i, (W, P, C) in enumerate(nets):
+        ref = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C), opts=o)
+        Wg, _, _, _, tg = b.state(i)
+        assert abs(tg - ref.iters) <= 2, (i, tg, ref.iters)
+        rel = (Wg - ref.W).abs().max().item() / max(1.0, ref.W.abs().max().item())
+        print(f"  split-BF16 net {i} {W.shape}: batch t={tg}, single t={ref.iters}, "
+              f"max|dW|/max|W| = {rel:.2e}; tiles {b.tiles}, best {best}")
+        assert rel <= 1e-3, (i, rel)
+    b.close()
