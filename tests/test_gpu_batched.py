@@ -59,10 +59,11 @@ def new_batch(torch, pd, nets, tiles=None, **kw):
     return b
 
 
-def check_steps(torch, pd, oracle, nets, steps, tiles=None, what=""):
-    """Iterate the batch one step at a time next to the oracle on every network."""
-    b = new_batch(torch, pd, nets, tiles, tol=0.0)
-    o = oracle.Options(tol=0.0)
+def check_steps(torch, pd, oracle, nets, steps, tiles=None, what="", **kw):
+    """Iterate the batch one step at a time next to the oracle on every network
+    (kw: reading flags, given to both)."""
+    b = new_batch(torch, pd, nets, tiles, tol=0.0, **kw)
+    o = oracle.Options(tol=0.0, **kw)
     refs = [list(n) for n in nets]
     for t in range(1, steps + 1):
         assert b.iterate(1) == len(nets)
@@ -79,6 +80,13 @@ def check_steps(torch, pd, oracle, nets, steps, tiles=None, what=""):
 def test_batch_matches_oracle_per_network(torch, pd, oracle):
     nets = [prep(oracle, *I.workload_priors(I.SMALL))] + [ragged(*s) for s in RAGGED]
     check_steps(torch, pd, oracle, nets, 6, what="default tiles")
+
+
+@pytest.mark.parametrize("kw", [{"sigma_from_T": True}, {"n_own": True, "diag_alpha": False},
+                                {"h_undamped": True, "update_last": True}])
+def test_batch_reading_flags(torch, pd, oracle, kw):
+    nets = [prep(oracle, *I.workload_priors(I.SMALL)), ragged(65, 300)]
+    check_steps(torch, pd, oracle, nets, 4, what=f"flags {kw}", **kw)
 
 
 @pytest.mark.parametrize("phase", [0, 1, 2, 3])
@@ -261,12 +269,13 @@ def test_48_networks_full_size(torch, pd, oracle):
 # (tests/test_gpu_precision.py): W, P and C off the diagonal within 1e-3 of the
 # FP64 oracle per step, the diagonals within 1e-4 relative, h within 1e-3.
 
-def test_split_bf16_batch_matches_oracle(torch, pd, oracle):
+@pytest.mark.parametrize("kw", [{}, {"sigma_from_T": True}])
+def test_split_bf16_batch_matches_oracle(torch, pd, oracle, kw):
     nets = [prep(oracle, *I.workload_priors(I.SMALL)), ragged(65, 300), ragged(70, 257),
             ragged(3, 5), small_like(oracle, 21, 130, 1000)]
-    b = new_batch(torch, pd, nets, tol=0.0, precision=1)
+    b = new_batch(torch, pd, nets, tol=0.0, precision=1, **kw)
     assert b.tiles[0] == 0 and b.tiles[1] == 0 and b.tiles[3] == 0
-    o = oracle.Options(tol=0.0)
+    o = oracle.Options(tol=0.0, **kw)
     refs = [list(n) for n in nets]
     for t in range(1, 6):
         assert b.iterate(1) == len(nets)

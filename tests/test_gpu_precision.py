@@ -88,6 +88,33 @@ def test_small_workload_matched_iterations(torch, pd, oracle):
     print(f"precision form, small workload: max |W - oracle| over the run = {worst:.2e}")
 
 
+@pytest.mark.parametrize("kw", [{"sigma_from_T": True}, {"n_own": True, "diag_alpha": False},
+                                {"h_undamped": True}])
+def test_reading_flags(torch, pd, oracle, kw):
+    """The readings of the paper (option flags) in the split-BF16 form, per
+    step against the FP64 oracle with the same flags."""
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    Ne, Na = W.shape
+    ctx = pd.Context(Ne, Na, b3(pd, tol=0.0, **kw))
+    ctx.load(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    Wo, Po, Co = W, P, C
+    o = oracle.Options(tol=0.0, **kw)
+    for t in range(1, 9):
+        Wo, Po, Co, ho, _ = oracle.step(Wo, Po, Co, t, o)
+        hg, tg = ctx.iterate()
+        assert tg == t
+        Wg, Pg, Cg, _, _ = ctx.state()
+        Wg, Pg, Cg = host(Wg), host(Pg), host(Cg)
+        assert np.abs(Wg - Wo).max() <= 1e-3, (kw, t)
+        assert np.abs(Cg - Co)[~np.eye(Na, dtype=bool)].max() <= 1e-3, (kw, t)
+        assert np.abs(Pg - Po)[~np.eye(Ne, dtype=bool)].max() <= 1e-3, (kw, t)
+        dC = np.abs(np.diag(Cg) - np.diag(Co)) / np.maximum(1, np.abs(np.diag(Co)))
+        dP = np.abs(np.diag(Pg) - np.diag(Po)) / np.maximum(1, np.abs(np.diag(Po)))
+        assert dP.max() <= 1e-4 and dC.max() <= 1e-4, (kw, t)
+        assert abs(hg - ho) <= 1e-3 * ho, (kw, t, hg, ho)
+    ctx.close()
+
+
 @pytest.mark.parametrize("Ne,Na", [(3, 5), (65, 300), (70, 257)])
 def test_ragged_shapes(torch, pd, oracle, Ne, Na):
     rng = np.random.default_rng(Ne * 31 + Na)
