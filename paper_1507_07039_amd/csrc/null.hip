@@ -98,14 +98,11 @@ hipError_t launch_permute_sym(const float* M, int64_t n, int64_t ldm, const int3
                               float* out, int64_t ldo, hipStream_t s) {
   const unsigned g = (unsigned)(n < 16384 ? n : 16384);
   if (n <= kRowLds) {
-    static bool attr = false;
-    if (!attr) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_permute_sym_lds),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(kRowLds * 4));
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    // set on every call: the attribute belongs to the current device
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_permute_sym_lds),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(kRowLds * 4));
+    if (e != hipSuccess) return e;
     k_permute_sym_lds<<<dim3(g), dim3(kPermNT), (size_t)n * 4, s>>>(M, n, ldm, perm, out, ldo);
   } else {
     k_permute_sym<<<dim3(g), dim3(kNT), 0, s>>>(M, n, ldm, perm, out, ldo);

@@ -157,11 +157,12 @@ __global__ __launch_bounds__(kRT) void k_split_offdiag(const float* __restrict__
 // ---- squared norms --------------------------------------------------------
 // Squared norms of the rows and columns of W in one pass (Eq. 9 needs
 // |W_i.|^2 and |W_.j|^2), and with SHADOW also its bf16 hi/lo planes,
-// row-major and gene-major (only the real Ne x Na region is written; the
-// padding of the planes stays zero).  Block (bx, by) takes the 64 x 64 tile
-// at rows 64 by, columns 64 bx and writes FP64 partial sums: rowpart[bx][r]
-// over its 64 columns, colpart[by][c] over its 64 rows; k_w_norms_sum adds
-// them up in block order (deterministic).
+// row-major and gene-major.  Block (bx, by) takes the 64 x 64 tile at rows
+// 64 by, columns 64 bx and writes FP64 partial sums: rowpart[bx][r] over its
+// 64 columns, colpart[by][c] over its 64 rows; k_w_norms_sum adds them up in
+// block order (deterministic).  The planes are written whole tiles at a time
+// from the tile staged in LDS, 8 entries (16 bytes) per store; entries past
+// Ne x Na are zero in the tile, so the padding of the planes stays zero.
 template <bool SHADOW>
 __global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, int64_t Ne,
                                                  int64_t Na, int64_t ldw, int64_t Nep,
@@ -179,16 +180,7 @@ __global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, in
   double cs = 0.0;
   for (int rr = ty; rr < 64; rr += 4) {
     const int64_t r = r0 + rr, c = c0 + tx;
-    float v = 0.0f;
-    if (r < Ne && c < Na) {
-      v = W[r * ldw + c];
-      if constexpr (SHADOW) {
-        bf16_t h, l;
-        split_bf16(v, h, l);
-        Wh[r * ldw + c] = h;
-        Wl[r * ldw + c] = l;
-      }
-    }
+    const float v = (r < Ne && c < Na) ? W[r * ldw + c] : 0.0f;
     if constexpr (SHADOW) tile[rr][tx] = v;
     const double q = (double)v * (double)v;
     cs += q;
@@ -203,14 +195,30 @@ __global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, in
     colpart[(int64_t)blockIdx.y * gridDim.x * 64 + c0 + tx] =
         ((cred[0][tx] + cred[1][tx]) + cred[2][tx]) + cred[3][tx];
   if constexpr (SHADOW) {
-    for (int cc = ty; cc < 64; cc += 4) {
-      const int64_t c = c0 + cc, r = r0 + tx;
-      if (r < Ne && c < Na) {
-        bf16_t h, l;
-        split_bf16(tile[tx][cc], h, l);
-        Wth[c * ldt + r] = h;
-        Wtl[c * ldt + r] = l;
+    // thread t: line t / 8 (+ 32 in the second pass), entries 8 (t % 8) .. +7
+    const int q = threadIdx.x & 7;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int line = (int)(threadIdx.x >> 3) + 32 * pass;
+      unsigned rh[4], rl[4], th[4], tl[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        bf16_t h0, l0, h1, l1;
+        split_bf16(tile[line][8 * q + 2 * e], h0, l0);  // row line, along the columns
+        split_bf16(tile[line][8 * q + 2 * e + 1], h1, l1);
+        rh[e] = (unsigned)h0 | ((unsigned)h1 << 16);
+        rl[e] = (unsigned)l0 | ((unsigned)l1 << 16);
+        split_bf16(tile[8 * q + 2 * e][line], h0, l0);  // column line, along the rows
+        split_bf16(tile[8 * q + 2 * e + 1][line], h1, l1);
+        th[e] = (unsigned)h0 | ((unsigned)h1 << 16);
+        tl[e] = (unsigned)l0 | ((unsigned)l1 << 16);
       }
+      const int64_t ro = (r0 + line) * ldw + c0 + 8 * q;  // rows < Nep, columns < ldw
+      const int64_t to = (c0 + line) * ldt + r0 + 8 * q;  // columns < ldw, rows < ldt
+      *reinterpret_cast<uint4*>(Wh + ro) = make_uint4(rh[0], rh[1], rh[2], rh[3]);
+      *reinterpret_cast<uint4*>(Wl + ro) = make_uint4(rl[0], rl[1], rl[2], rl[3]);
+      *reinterpret_cast<uint4*>(Wth + to) = make_uint4(th[0], th[1], th[2], th[3]);
+      *reinterpret_cast<uint4*>(Wtl + to) = make_uint4(tl[0], tl[1], tl[2], tl[3]);
     }
   }
 }
@@ -450,6 +458,7 @@ hipError_t launch_w_norms(const float* W, int64_t Ne, int64_t Na, int64_t ldw, i
                           bf16_t* Wtl, int64_t ldt, const int32_t* gate, hipStream_t s) {
   const int64_t Nap = ldw;
   if (Nep % 64 || Nap % 64 || Ne > Nep || Na > Nap) return hipErrorInvalidValue;
+  if (Wh && (ldt < Nep || ldt % 8)) return hipErrorInvalidValue;  // 16-byte plane stores
   double* rowpart = scr;
   double* colpart = scr + (Nap / 64) * Nep;
   const dim3 grid((unsigned)(Nap / 64), (unsigned)(Nep / 64));
