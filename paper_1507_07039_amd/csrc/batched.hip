@@ -336,8 +336,9 @@ hipError_t group_launch(const BInst* bi, const WorkList& wl, const Ph& ph, int64
 
 template <class G, class Ph>
 int64_t group_grid() {
-  static int64_t nb = 0;
-  if (!nb) nb = resident_blocks(reinterpret_cast<const void*>(&k_group_gemm<G, Ph>), G::NT);
+  // computed once per kernel (a function-local static: thread-safe initialisation)
+  static const int64_t nb =
+      resident_blocks(reinterpret_cast<const void*>(&k_group_gemm<G, Ph>), G::NT);
   return nb;
 }
 

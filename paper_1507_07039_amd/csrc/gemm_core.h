@@ -1034,9 +1034,9 @@ inline int64_t resident_blocks(const void* fn, int nt = kThreads) {
 template <class G, class Epi>
 hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64_t Kp, Epi epi,
                        float* part, const int32_t* gate, hipStream_t s) {
-  static int64_t resident = 0;
-  if (!resident)
-    resident = resident_blocks(reinterpret_cast<const void*>(&k_rect_streamk<G, Epi>), G::NT);
+  // computed once per kernel (a function-local static: thread-safe initialisation)
+  static const int64_t resident =
+      resident_blocks(reinterpret_cast<const void*>(&k_rect_streamk<G, Epi>), G::NT);
   const int64_t nMT = Mp / G::BM, nNT = Np / G::BN;
   const int64_t nTiles = nMT * nNT, U = Kp / G::BK;
   int64_t nb = resident;
