@@ -55,6 +55,22 @@ def test_permute_sym_exact(torch, pd, n):
     assert np.array_equal(out, N.permute_sym(M, p).astype(np.float32))
 
 
+@pytest.mark.parametrize("n", [40960, 40961])
+def test_permute_sym_row_staging_limit(torch, pd, n):
+    """Both sides of the largest row the kernel stages in LDS (160 KB = 40960
+    floats; longer rows take the kernel that gathers from global memory):
+    bit for bit against torch's own indexing of the same device matrix."""
+    g = torch.Generator(device="cuda").manual_seed(n)
+    M = torch.randn((n, n), generator=g, device="cuda", dtype=torch.float32)
+    p = torch.randperm(n, generator=g, device="cuda").to(torch.int32)
+    out = pd.permute_sym(M, p)
+    pl = p.long()
+    want = M.index_select(0, pl).index_select(1, pl)
+    assert torch.equal(out, want)
+    del M, out, want
+    torch.cuda.empty_cache()
+
+
 def test_permute_sym_rejects_non_permutations(torch, pd):
     lib = pd.load_library()
     M = torch.zeros((5, 5), dtype=torch.float32, device="cuda")
