@@ -24,6 +24,9 @@
  *     normalisation) synchronise that stream before returning.
  *   - Arguments are validated on the host before any device work; a failed
  *     validation returns PANDA_ERR_ARG and enqueues nothing.
+ *   - Network sizes: 1 <= N_e <= 65536 TFs and 1 <= N_a <= 262144 genes (so
+ *     every grid and tile index stays in range); outside them the calls
+ *     return PANDA_ERR_ARG and the *_workspace_bytes() calls return 0.
  *   - Errors are returned as panda_status; no exception or abort crosses the
  *     ABI.  panda_last_error() gives a thread-local message for the last
  *     failure on the calling thread.

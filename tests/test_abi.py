@@ -67,6 +67,22 @@ def test_workspace_sizes(lib):
     assert 224 * 18048 * 4 + 16 * 18000 <= big < 224 * 18048 * 4 + 16 * 18000 + 4096
 
 
+def test_size_limits(lib):
+    """N_e up to 65536 and N_a up to 262144 are accepted (the sizes are only
+    computed here, nothing is allocated); one past either limit is rejected."""
+    o = panda.default_options()
+    out = ct.c_void_p()
+    fake = ct.c_void_p(256)  # never dereferenced: validation fails first
+    assert lib.panda_workspace_bytes(65536, 1, ct.byref(o)) > 0
+    assert lib.panda_workspace_bytes(1, 262144, ct.byref(o)) >= 262144 * 262144 * 4
+    assert lib.panda_workspace_bytes(65537, 1, ct.byref(o)) == 0
+    assert lib.panda_workspace_bytes(1, 262145, ct.byref(o)) == 0
+    assert lib.panda_null_workspace_bytes(65537, 1, ct.byref(o)) == 0
+    for Ne, Na in ((65537, 1), (1, 262145), (-1, 5), (5, -1)):
+        assert lib.panda_ctx_create(Ne, Na, ct.byref(o), fake, 1 << 62, None,
+                                    ct.byref(out)) == panda.ERR_ARG, (Ne, Na)
+
+
 def test_null_validation(lib):
     o = panda.default_options()
     fake = ct.c_void_p(256)  # never dereferenced: validation fails first
