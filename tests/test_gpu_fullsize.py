@@ -142,3 +142,19 @@ def test_trajectory_matches_stored_oracle_run(torch, pd, human):
         # the oracle's h at the earlier of the two stops is within tolerance of tol
         h_o = g["h_trace"][min(res.iters, iters) - 1]
         assert abs(h_o - 1e-3) <= 2e-3 * h_o, h_o
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_runs_repeat_bit_for_bit(torch, pd, human, precision):
+    """Two converged runs of the same inputs, in the benchmark's launch
+    configuration, give the same W, P, C and iteration count bit for bit (no
+    atomics: stream-K partials and h partials are summed in a fixed order)."""
+    (W, P, C), _ = human
+    dev = [torch.from_numpy(a).cuda() for a in (W, P, C)]
+    opts = pd.default_options(precision=precision)
+    a = pd.run(*dev, opts=opts)
+    b = pd.run(*dev, opts=opts)
+    assert a.status == pd.OK and b.status == pd.OK
+    assert a.iters == b.iters and a.h == b.h
+    assert torch.equal(a.W, b.W) and torch.equal(a.P, b.P) and torch.equal(a.C, b.C)
+    print(f"precision {precision}: {a.iters} iterations, repeated bit for bit")
