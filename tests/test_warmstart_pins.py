@@ -175,3 +175,81 @@ def test_warm_state_structure():
                 assert abs(C[k, j] - O.T(W[:, k], W[:, j])) <= 1e-14 * (1 + abs(C[k, j]))
     sP = np.array([np.delete(P[i], i).std() for i in range(Ne)])
     assert np.allclose(np.diag(P), WS.diag_schedule(np.diag(P0), sP, Na, 12), rtol=1e-13)
+
+
+def test_target_scale_is_the_population_std():
+    # S - W0 = (0, 0, 0, 4): mean 1, population variance 3 (the sample
+    # variance would be 4), so tau = sqrt(3)
+    W0 = np.array([[1.0, -2.0], [0.5, 3.0]])
+    S = W0 + np.array([[0.0, 0.0], [0.0, 4.0]])
+    assert WS.target_scale(W0, S) == pytest.approx(np.sqrt(3.0), rel=1e-15)
+    # one entry differs from all others equally: D = (5, 0, 0, 0, 0, 0, 0, 0),
+    # population std = 5 sqrt(7) / 8
+    D = np.zeros((2, 4)); D[0, 0] = 5.0
+    assert WS.target_scale(np.zeros((2, 4)), D) == pytest.approx(5 * np.sqrt(7) / 8, rel=1e-15)
+
+
+def _rounding_net():
+    """A network whose output depends on every bf16 rounding point of the
+    GPU's forward pass; all values are exact binary fractions.
+      X  = (1, 2^-9, 1 + 2^-8 + 2^-9, 1): X_2 rounds up to 1 + 2^-7
+      z1_0 = X_0 + X_1 = 1 + 2^-9                -> h1 rounds it to 1
+      z1_1 = X_2 - X_3 = 2^-7 (X rounded), 3 2^-9 if X were not rounded
+      z1_2 = W1_20 X_0 - X_3, W1_20 = 1 + 2^-8 + 2^-9 rounds to 1 + 2^-7:
+             2^-7 (W1 rounded), 3 2^-9 if not
+      z2_0 = W2_00 h1_0 + 2^-3 h1_1 + 2^-5 h1_2, W2_00 = 1 + 2^-9 rounds to 1
+      z2_1 = 2^-9 h1_0
+      y    = w3_0 h2_0 + h2_1 + 1/4, w3_0 = 1 + 2^-9 rounds to 1."""
+    W1 = np.zeros((64, 16)); b1 = np.zeros(64)
+    W2 = np.zeros((64, 64)); b2 = np.zeros(64)
+    w3 = np.zeros(64)
+    W1[0, 0] = 1.0; W1[0, 1] = 1.0
+    W1[1, 2] = 1.0; W1[1, 3] = -1.0
+    W1[2, 0] = 1 + 2.0 ** -8 + 2.0 ** -9; W1[2, 3] = -1.0
+    W2[0, 0] = 1 + 2.0 ** -9; W2[0, 1] = 2.0 ** -3; W2[0, 2] = 2.0 ** -5
+    W2[1, 0] = 2.0 ** -9
+    w3[0] = 1 + 2.0 ** -9; w3[1] = 1.0
+    p = WS.pack(W1, b1, W2, b2, w3, 0.25)
+    X = np.zeros((1, 16)); X[0, :4] = [1.0, 2.0 ** -9, 1 + 2.0 ** -8 + 2.0 ** -9, 1.0]
+    return p, X
+
+
+def test_forward_bf16_rounding_points_bit_exact():
+    """Inputs, weights and the first hidden layer are rounded to bf16; the
+    second layer's pre-activations and the output are not.  Leaving out any
+    rounding, or adding one after the second layer, changes y."""
+    p, X = _rounding_net()
+    y, (Xq, z1, h1q, z2, h2, W1q, W2q, w3q) = WS.forward(p, X, bf16_mode=True)
+    assert h1q[0, :3].tolist() == [1.0, 2.0 ** -7, 2.0 ** -7]
+    assert z2[0, :2].tolist() == [1 + 2.0 ** -10 + 2.0 ** -12, 2.0 ** -9]
+    assert y[0] == 1.25 + 2.0 ** -9 + 2.0 ** -10 + 2.0 ** -12
+    # the exact network differs at every one of those points
+    ye, (_, z1e, _, _, _, _, _, _) = WS.forward(p, X)
+    assert z1e[0, :3].tolist() == [1 + 2.0 ** -9, 3 * 2.0 ** -9, 3 * 2.0 ** -9]
+    z2e0 = (1 + 2.0 ** -9) ** 2 + 3 * 2.0 ** -9 * 2.0 ** -3 + 3 * 2.0 ** -9 * 2.0 ** -5
+    assert ye[0] == z2e0 * (1 + 2.0 ** -9) + (1 + 2.0 ** -9) * 2.0 ** -9 + 0.25
+
+
+def test_gradient_bf16_rounding_points_bit_exact():
+    """In the backward pass dz2 and dz1 enter the weight and input-gradient
+    products rounded to bf16 (with the rounded h1, X and W2 of the forward
+    pass), while the bias gradients and dw3 take them unrounded.  The target
+    makes dy = 1 + 2^-9, so dz2_0 = dz2_1 = 1 + 2^-9 (rounds to 1) and
+    dh1_0 = dz2q_0 W2q_00 + dz2q_1 W2q_10 = 1 + 2^-9 (rounds to 1)."""
+    p, X = _rounding_net()
+    y = 1.25 + 2.0 ** -9 + 2.0 ** -10 + 2.0 ** -12
+    target = np.array([y - (0.5 + 2.0 ** -10)])  # e = (1 + 2^-9) / 2, n = 1
+    loss, g = WS.loss_grad(p, X, target, bf16_mode=True)
+    assert loss == (0.5 + 2.0 ** -10) ** 2
+    dW1, db1, dW2, db2, dw3, db3 = WS.unpack(g)
+    dy = 1 + 2.0 ** -9
+    assert db3 == dy
+    assert dw3[:2].tolist() == [(1 + 2.0 ** -10 + 2.0 ** -12) * dy, 2.0 ** -9 * dy]
+    assert db2[:2].tolist() == [dy, dy]                                  # unrounded dz2
+    assert dW2[0, :3].tolist() == [1.0, 2.0 ** -7, 2.0 ** -7]          # bf16(dz2) h1q
+    assert dW2[1, :3].tolist() == [1.0, 2.0 ** -7, 2.0 ** -7]
+    # dh1 = bf16(dz2) W2q: unit 0 gets 1 + 2^-9, units 1 and 2 get 2^-3, 2^-5
+    assert db1[:3].tolist() == [1 + 2.0 ** -9, 2.0 ** -3, 2.0 ** -5]   # unrounded dz1
+    assert dW1[0, :4].tolist() == [1.0, 2.0 ** -9, 1 + 2.0 ** -7, 1.0]  # bf16(dz1) Xq
+    assert dW1[1, :4].tolist() == [2.0 ** -3, 2.0 ** -12, 2.0 ** -3 * (1 + 2.0 ** -7), 2.0 ** -3]
+    assert np.count_nonzero(dW1[3:]) == 0 and np.count_nonzero(dW2[2:]) == 0
