@@ -40,7 +40,8 @@ class _Opts(ct.Structure):
     _fields_ = [("alpha", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("diag_alpha", ct.c_int32),
                 ("sigma_from_T", ct.c_int32), ("n_own", ct.c_int32),
-                ("h_undamped", ct.c_int32), ("update_last", ct.c_int32)]
+                ("h_undamped", ct.c_int32), ("update_last", ct.c_int32),
+                ("sigma_ddof", ct.c_int32)]
 
 
 @dataclass
@@ -52,6 +53,7 @@ class Options:
     n_own        [False] Eq. 6 multiplier is the network's own dimension.
     h_undamped   [False] h = mean|(A+R)/2 - W| instead of Eq. 7 literal.
     update_last  [False] update P and C also on the converging iteration.
+    sigma_ddof   [0]     Eq. 6 sigma: 0 population std, 1 sample std.
     """
     alpha: float = 0.1
     tol: float = 1e-3
@@ -61,11 +63,12 @@ class Options:
     n_own: bool = False
     h_undamped: bool = False
     update_last: bool = False
+    sigma_ddof: int = 0
 
     def _c(self) -> _Opts:
         return _Opts(self.alpha, self.tol, self.max_iter, int(self.diag_alpha),
                      int(self.sigma_from_T), int(self.n_own),
-                     int(self.h_undamped), int(self.update_last))
+                     int(self.h_undamped), int(self.update_last), int(self.sigma_ddof))
 
 
 _lib = None
@@ -85,6 +88,7 @@ def _load():
         lib.oracle_tanimoto.argtypes = [dp, dp, i64, i64, i64, dp]
         lib.oracle_tanimoto_entries.argtypes = [dp, dp, i64, i64, i64, lp, lp, i64, dp]
         lib.oracle_normalize.argtypes = [dp, i64]
+        lib.oracle_normalize_ex.argtypes = [dp, i64, i64, i32, i32]
         lib.oracle_step.argtypes = [dp, dp, dp, i64, i64, i32, ct.POINTER(_Opts),
                                     dp, ct.POINTER(i32)]
         lib.oracle_run.argtypes = [dp, dp, dp, i64, i64, i32, ct.POINTER(_Opts),
@@ -94,6 +98,7 @@ def _load():
         lib.oracle_pearson.argtypes = [dp, i64, i64, dp]
         lib.oracle_pearson_entries.argtypes = [dp, i64, i64, lp, lp, i64, dp]
         for f in ("oracle_tanimoto", "oracle_tanimoto_entries", "oracle_normalize",
+                  "oracle_normalize_ex",
                   "oracle_step", "oracle_run", "oracle_step_w_entries",
                   "oracle_pearson", "oracle_pearson_entries"):
             getattr(lib, f).restype = ct.c_int
@@ -161,6 +166,18 @@ def normalize(M) -> np.ndarray:
     """Global z-score (mean and population std over all entries)."""
     out = _f64(M).copy()
     _check(_load().oracle_normalize(_dp(out), out.size), "normalize")
+    return out
+
+
+ZSCORE_GLOBAL, ZSCORE_ROW, ZSCORE_ROWCOL = 0, 1, 2
+
+
+def normalize_ex(M, mode: int = ZSCORE_GLOBAL, ddof: int = 0) -> np.ndarray:
+    """Z-score with a scope (all entries / per row / row and column) and a
+    standard-deviation normaliser (ddof 0 population, 1 sample)."""
+    out = _f64(M).copy()
+    rows, cols = out.shape
+    _check(_load().oracle_normalize_ex(_dp(out), rows, cols, mode, ddof), "normalize_ex")
     return out
 
 

@@ -22,7 +22,11 @@
  *   - Eq. 6 diagonal: increment multiplied by alpha (D1) by default; the
  *     literal form without alpha (D0) behind diag_alpha = 0.
  *   - sigma: population standard deviation of the off-diagonal entries of the
- *     damped row (Sec. II-B text after Eq. 6); fresh T row behind sigma_from_T.
+ *     damped row (Sec. II-B text after Eq. 6); fresh T row behind sigma_from_T;
+ *     the sample standard deviation (divisor n - 1) behind sigma_ddof = 1.
+ *   - z-score (Sec. II-A): mean and standard deviation over all entries of a
+ *     network; per row, or the sum of the row and the column z-scores over
+ *     sqrt 2, behind the zscore mode of oracle_normalize_ex.
  *   - multiplier: N_a for P and N_e for C as printed in Eq. 6; own dimension
  *     behind n_own.
  *   - h: Eq. 7 literal (damped difference); undamped "predicted" form behind
@@ -53,6 +57,7 @@ typedef struct {
   int32_t n_own;
   int32_t h_undamped;
   int32_t update_last;
+  int32_t sigma_ddof; /* 0: population std in Eq. 6; 1: sample std */
 } oracle_opts;
 
 /* Eq. 1: T(x, y) = x.y / sqrt(|x|^2 + |y|^2 - |x.y|), x and y given with
@@ -128,10 +133,70 @@ int oracle_normalize(double* Mat, int64_t n) {
   return ORACLE_OK;
 }
 
-/* Population standard deviation of the off-diagonal entries of row i of the
- * n x n matrix S (Eq. 6 and the sentence after it).  An empty set gives 0. */
-static double offdiag_row_std(const double* S, int64_t n, int64_t i) {
-  if (n < 2) return 0.0;
+/* Z-score with a choice of scope and normaliser (readings of the single
+ * sentence of Sec. II-A): mode 0 = mean and standard deviation over all
+ * entries (what oracle_normalize does); mode 1 = each row by its own mean
+ * and standard deviation; mode 2 = (Zr + Zc) / sqrt(2), Zr the per-row and
+ * Zc the per-column z-score of the same input.  ddof 0 divides the sum of
+ * squared deviations by the count n (population), ddof 1 by n - 1 (sample).
+ * A set with zero spread, or with n - ddof < 1, is ORACLE_ERR_DEGENERATE;
+ * NaN/Inf is ORACLE_ERR_NONFINITE; on an error M is left untouched. */
+static int mean_sd(const double* x, int64_t n, int64_t stride, int32_t ddof, double* mean,
+                   double* sd) {
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) s += x[k * stride];
+  *mean = s / (double)n;
+  double q = 0.0;
+  for (int64_t k = 0; k < n; ++k) q += (x[k * stride] - *mean) * (x[k * stride] - *mean);
+  if (n - ddof < 1) return ORACLE_ERR_DEGENERATE;
+  *sd = sqrt(q / (double)(n - ddof));
+  return *sd > 0.0 ? ORACLE_OK : ORACLE_ERR_DEGENERATE;
+}
+
+int oracle_normalize_ex(double* Mat, int64_t rows, int64_t cols, int32_t mode, int32_t ddof) {
+  if (!Mat || rows < 1 || cols < 1 || mode < 0 || mode > 2 || ddof < 0 || ddof > 1)
+    return ORACLE_ERR_ARG;
+  const int64_t n = rows * cols;
+  for (int64_t k = 0; k < n; ++k)
+    if (!isfinite(Mat[k])) return ORACLE_ERR_NONFINITE;
+  if (mode == 0) {
+    double mean, sd;
+    int st = mean_sd(Mat, n, 1, ddof, &mean, &sd);
+    if (st != ORACLE_OK) return st;
+    for (int64_t k = 0; k < n; ++k) Mat[k] = (Mat[k] - mean) / sd;
+    return ORACLE_OK;
+  }
+  double* rm = (double*)malloc(sizeof(double) * (size_t)rows * 2);
+  double* cm = (double*)malloc(sizeof(double) * (size_t)cols * 2);
+  if (!rm || !cm) {
+    free(rm);
+    free(cm);
+    return ORACLE_ERR_NOMEM;
+  }
+  int st = ORACLE_OK;
+  for (int64_t i = 0; i < rows && st == ORACLE_OK; ++i)
+    st = mean_sd(Mat + i * cols, cols, 1, ddof, &rm[2 * i], &rm[2 * i + 1]);
+  if (mode == 2)
+    for (int64_t j = 0; j < cols && st == ORACLE_OK; ++j)
+      st = mean_sd(Mat + j, rows, cols, ddof, &cm[2 * j], &cm[2 * j + 1]);
+  if (st == ORACLE_OK) {
+    for (int64_t i = 0; i < rows; ++i)
+      for (int64_t j = 0; j < cols; ++j) {
+        double x = Mat[i * cols + j];
+        double zr = (x - rm[2 * i]) / rm[2 * i + 1];
+        Mat[i * cols + j] = mode == 1 ? zr : (zr + (x - cm[2 * j]) / cm[2 * j + 1]) / sqrt(2.0);
+      }
+  }
+  free(rm);
+  free(cm);
+  return st;
+}
+
+/* Standard deviation of the off-diagonal entries of row i of the n x n
+ * matrix S (Eq. 6 and the sentence after it): population (ddof 0) or sample
+ * (ddof 1).  Fewer than ddof + 1 entries give 0. */
+static double offdiag_row_std(const double* S, int64_t n, int64_t i, int32_t ddof) {
+  if (n - 1 - ddof < 1) return 0.0;
   double s = 0.0;
   for (int64_t m = 0; m < n; ++m)
     if (m != i) s += S[i * n + m];
@@ -139,7 +204,7 @@ static double offdiag_row_std(const double* S, int64_t n, int64_t i) {
   double q = 0.0;
   for (int64_t m = 0; m < n; ++m)
     if (m != i) q += (S[i * n + m] - mean) * (S[i * n + m] - mean);
-  return sqrt(q / (double)(n - 1));
+  return sqrt(q / (double)(n - 1 - ddof));
 }
 
 /* W-side of one iteration: Wn = (1-alpha) W + alpha/2 (A + R) with
@@ -187,7 +252,8 @@ static void sym_update(double* S, const double* Tm, int64_t n, double mult,
   for (int64_t i = 0; i < n; ++i)
     for (int64_t m = 0; m < n; ++m)
       Sn[i * n + m] = (i == m) ? S[i * n + m] : (1.0 - a) * S[i * n + m] + a * Tm[i * n + m];
-  for (int64_t i = 0; i < n; ++i) sig[i] = offdiag_row_std(o->sigma_from_T ? Tm : Sn, n, i);
+  for (int64_t i = 0; i < n; ++i)
+    sig[i] = offdiag_row_std(o->sigma_from_T ? Tm : Sn, n, i, o->sigma_ddof);
   double g = exp(2.0 * a * (double)t);
   for (int64_t i = 0; i < n; ++i) {
     double inc = mult * sig[i] * g;
@@ -257,7 +323,8 @@ int oracle_step(double* W, double* P, double* C, int64_t Ne, int64_t Na,
 int oracle_run(double* W, double* P, double* C, int64_t Ne, int64_t Na,
                int32_t t0, const oracle_opts* o, int32_t* iters, double* h,
                double* h_trace) {
-  if (!o || o->max_iter < 1 || !(o->alpha > 0.0) || o->alpha > 1.0 || !(o->tol >= 0.0) || t0 < 0)
+  if (!o || o->max_iter < 1 || !(o->alpha > 0.0) || o->alpha > 1.0 || !(o->tol >= 0.0) || t0 < 0 ||
+      o->sigma_ddof < 0 || o->sigma_ddof > 1)
     return ORACLE_ERR_ARG;
   double hv = 0.0;
   int32_t conv = 0, t = t0;

@@ -124,6 +124,87 @@ def test_normalize_errors(oracle):
     assert e.value.code == oracle.ERR_NONFINITE
 
 
+@pytest.mark.parametrize("ddof", [0, 1])
+def test_normalize_ex_global_matches_numpy(oracle, ddof):
+    M = RNG.gamma(2.0, size=(13, 29)) - 1.5
+    Z = oracle.normalize_ex(M, oracle.ZSCORE_GLOBAL, ddof)
+    np.testing.assert_allclose(Z, (M - M.mean()) / M.std(ddof=ddof), rtol=1e-13, atol=1e-14)
+    if ddof == 0:
+        assert np.array_equal(Z, oracle.normalize(M))
+    else:  # sample std = population std * sqrt(n / (n - 1))
+        n = M.size
+        np.testing.assert_allclose(Z * np.sqrt(n / (n - 1)), oracle.normalize(M), rtol=1e-13)
+
+
+@pytest.mark.parametrize("ddof", [0, 1])
+def test_normalize_ex_rows(oracle, ddof):
+    M = RNG.normal(size=(9, 17)) * RNG.uniform(0.5, 3, size=(9, 1)) + RNG.normal(size=(9, 1))
+    Z = oracle.normalize_ex(M, oracle.ZSCORE_ROW, ddof)
+    np.testing.assert_allclose(Z.mean(axis=1), 0.0, atol=1e-14)
+    np.testing.assert_allclose(Z.std(axis=1, ddof=ddof), 1.0, rtol=1e-13)
+    mu, sd = M.mean(axis=1, keepdims=True), M.std(axis=1, ddof=ddof, keepdims=True)
+    np.testing.assert_allclose(Z, (M - mu) / sd, rtol=1e-13, atol=1e-14)
+    # each row is invariant under its own positive affine map
+    a, b = RNG.uniform(0.1, 4, size=(9, 1)), RNG.normal(size=(9, 1))
+    np.testing.assert_allclose(oracle.normalize_ex(a * M + b, oracle.ZSCORE_ROW, ddof), Z,
+                               atol=1e-12)
+    # identity rows: one 1 among n entries, mean 1/n; sum of squared deviations (n-1)/n
+    n = 6
+    Zi = oracle.normalize_ex(np.eye(n), oracle.ZSCORE_ROW, ddof)
+    sd = np.sqrt((n - 1) / n / (n - ddof))
+    np.testing.assert_allclose(np.diag(Zi), (1 - 1 / n) / sd, rtol=1e-14)
+    np.testing.assert_allclose(Zi[~np.eye(n, dtype=bool)], -1 / n / sd, rtol=1e-14)
+
+
+def test_normalize_ex_rowcol(oracle):
+    # closed form: [[0, 1], [1, 0]]: every row and column is (0, 1) up to order,
+    # z = -+1 (population) or -+1/sqrt(2) (sample), so Z = sqrt(2) (row z)
+    # resp. Z = row z (sample)
+    M = np.array([[0.0, 1.0], [1.0, 0.0]])
+    want = np.array([[-1.0, 1.0], [1.0, -1.0]])
+    np.testing.assert_allclose(oracle.normalize_ex(M, oracle.ZSCORE_ROWCOL, 0), np.sqrt(2) * want,
+                               rtol=1e-15)
+    np.testing.assert_allclose(oracle.normalize_ex(M, oracle.ZSCORE_ROWCOL, 1), want, rtol=1e-15)
+    # general case against numpy's per-axis moments
+    X = RNG.exponential(size=(11, 7)) + np.arange(7)[None, :]
+    for ddof in (0, 1):
+        Zr = (X - X.mean(axis=1, keepdims=True)) / X.std(axis=1, ddof=ddof, keepdims=True)
+        Zc = (X - X.mean(axis=0, keepdims=True)) / X.std(axis=0, ddof=ddof, keepdims=True)
+        np.testing.assert_allclose(oracle.normalize_ex(X, oracle.ZSCORE_ROWCOL, ddof),
+                                   (Zr + Zc) / np.sqrt(2), rtol=1e-13, atol=1e-14)
+    # a symmetric network stays exactly symmetric
+    S = I.random_symmetric(5, 23)
+    Zs = oracle.normalize_ex(S, oracle.ZSCORE_ROWCOL, 0)
+    np.testing.assert_allclose(Zs, Zs.T, atol=1e-14)
+    # invariant under one positive affine map of the whole network
+    np.testing.assert_allclose(oracle.normalize_ex(2.5 * X + 4, oracle.ZSCORE_ROWCOL, 0),
+                               oracle.normalize_ex(X, oracle.ZSCORE_ROWCOL, 0), atol=1e-12)
+
+
+def test_normalize_ex_errors(oracle):
+    M = RNG.normal(size=(4, 5))
+    M[2] = 7.0  # constant row: fine for the global and the column z-score
+    oracle.normalize_ex(M, oracle.ZSCORE_GLOBAL, 0)
+    for mode in (oracle.ZSCORE_ROW, oracle.ZSCORE_ROWCOL):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.normalize_ex(M, mode, 0)
+        assert e.value.code == oracle.ERR_DEGENERATE
+    M = RNG.normal(size=(4, 5))
+    M[:, 3] = -1.0  # constant column: only the row + column form fails
+    oracle.normalize_ex(M, oracle.ZSCORE_ROW, 1)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.normalize_ex(M, oracle.ZSCORE_ROWCOL, 1)
+    assert e.value.code == oracle.ERR_DEGENERATE
+    # one entry per row: the sample std has no degrees of freedom
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.normalize_ex(RNG.normal(size=(3, 1)), oracle.ZSCORE_ROW, 1)
+    assert e.value.code == oracle.ERR_DEGENERATE
+    M[1, 1] = np.inf
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.normalize_ex(M, oracle.ZSCORE_ROW, 0)
+    assert e.value.code == oracle.ERR_NONFINITE
+
+
 # --------------------------------------- one iteration: closed forms -----
 
 def test_step_scaled_identity_closed_form(oracle):
@@ -163,7 +244,8 @@ def _offdiag(S):
     return S[~np.eye(n, dtype=bool)].reshape(n, n - 1)
 
 
-@pytest.mark.parametrize("kw", [{}, {"diag_alpha": False}, {"n_own": True}, {"sigma_from_T": True}])
+@pytest.mark.parametrize("kw", [{}, {"diag_alpha": False}, {"n_own": True}, {"sigma_from_T": True},
+                                {"sigma_ddof": 1}, {"sigma_ddof": 1, "sigma_from_T": True}])
 def test_step_pc_update_against_recast(oracle, kw):
     """Eq. 5 off-diagonals against the matrix recast of the NEW W, and Eq. 6
     diagonals against numpy's population std of the updated off-diagonals."""
@@ -179,8 +261,9 @@ def test_step_pc_update_against_recast(oracle, kw):
     offC = ~np.eye(Na, dtype=bool)
     np.testing.assert_allclose(Pn[offP], ((1 - a) * P + a * TP)[offP], rtol=1e-12, atol=1e-13)
     np.testing.assert_allclose(Cn[offC], ((1 - a) * C + a * TC)[offC], rtol=1e-12, atol=1e-13)
-    sP = np.std(_offdiag(TP if kw.get("sigma_from_T") else Pn), axis=1)
-    sC = np.std(_offdiag(TC if kw.get("sigma_from_T") else Cn), axis=1)
+    dd = kw.get("sigma_ddof", 0)
+    sP = np.std(_offdiag(TP if kw.get("sigma_from_T") else Pn), axis=1, ddof=dd)
+    sC = np.std(_offdiag(TC if kw.get("sigma_from_T") else Cn), axis=1, ddof=dd)
     mP = Ne if kw.get("n_own") else Na   # Eq. 6 as printed: N_a for P, N_e for C
     mC = Na if kw.get("n_own") else Ne
     g = np.exp(2 * a * t)
