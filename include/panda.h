@@ -70,6 +70,18 @@ typedef enum {
  *                      W (two layouts) and P, about 4 * Ne * Na * 2 bytes. */
 enum { PANDA_PREC_FP32 = 0, PANDA_PREC_BF16X3 = 1 };
 
+/* Scope of the z-score of Sec. II-A (the paper says only that each network
+ * is z-score normalised):
+ *   PANDA_ZSCORE_GLOBAL  one mean and standard deviation over all entries
+ *   PANDA_ZSCORE_ROW     each row by its own mean and standard deviation
+ *                        (for W: per transcription factor; it does not keep
+ *                        a symmetric network symmetric, so it is not meant
+ *                        for P and C, which the iteration takes symmetric)
+ *   PANDA_ZSCORE_ROWCOL  (Zr + Zc) / sqrt(2), Zr the per-row and Zc the
+ *                        per-column z-score of the same input (symmetric in,
+ *                        symmetric out) */
+enum { PANDA_ZSCORE_GLOBAL = 0, PANDA_ZSCORE_ROW = 1, PANDA_ZSCORE_ROWCOL = 2 };
+
 /* Run parameters and the readings of the paper where it is ambiguous.
  * panda_default_options() fills the defaults given in brackets. */
 typedef struct {
@@ -85,6 +97,11 @@ typedef struct {
   int32_t update_last;  /* [0]    skip the P/C update on the converging iteration */
   int32_t poll_every;   /* [1]    panda_run reads h back every poll_every iterations */
   int32_t precision;    /* [PANDA_PREC_FP32]                                      */
+  int32_t sigma_ddof;   /* [0]    standard deviations (sigma of Eq. 6, and the
+                                  z-score of an identity default) divide by n;
+                                  1: by n - 1 (sample)                           */
+  int32_t zscore_mode;  /* [PANDA_ZSCORE_GLOBAL] scope of the z-score that the
+                                  library applies itself (identity defaults)     */
 } panda_options;
 
 typedef struct panda_ctx panda_ctx;
@@ -102,6 +119,21 @@ void panda_default_options(panda_options* opt);
 size_t panda_normalize_workspace_bytes(void);
 panda_status panda_normalize(float* M, int64_t rows, int64_t cols, void* workspace,
                              size_t ws_bytes, hipStream_t stream);
+
+/* The same z-score with a choice of scope (PANDA_ZSCORE_*) and normaliser
+ * (ddof 0: divide the sum of squared deviations by the count n; ddof 1: by
+ * n - 1).  M is rows x cols, row-major, contiguous, device memory, changed in
+ * place.  Moments in FP64, two passes.  Returns PANDA_ERR_NONFINITE (M
+ * untouched) for a NaN/Inf entry; PANDA_ERR_DEGENERATE (M untouched) if the
+ * network, or under the row / row + column scopes any row / column, has zero
+ * spread (or fewer than ddof + 1 entries).  Needs
+ * panda_normalize_ex_workspace_bytes(rows, cols, zscore_mode) bytes of
+ * workspace (0 for invalid arguments; about 16 (rows + cols) bytes).
+ * Synchronises the stream.  panda_normalize is zscore_mode GLOBAL, ddof 0. */
+size_t panda_normalize_ex_workspace_bytes(int64_t rows, int64_t cols, int32_t zscore_mode);
+panda_status panda_normalize_ex(float* M, int64_t rows, int64_t cols, int32_t zscore_mode,
+                                int32_t ddof, void* workspace, size_t ws_bytes,
+                                hipStream_t stream);
 
 /* Similarity matrix of Eq. 1 in the matrix form of Sec. II-C (the paper's
  * Tfunction): Out[i][j] = T(row i of X, column j of Y) for X (M x K) and
@@ -150,7 +182,12 @@ panda_status panda_ctx_load(panda_ctx* ctx, const float* W, const float* P, cons
  * further calls change nothing and return PANDA_OK with the same h and t. */
 panda_status panda_iterate(panda_ctx* ctx, double* h, int32_t* t);
 
-/* Copy the current state out (any pointer may be NULL to skip it). */
+/* Copy the current state out (any pointer may be NULL to skip it).  The
+ * diagonals of P and C (Eq. 6) grow like exp(2 alpha t); the library keeps
+ * them in FP64, rounded to FP32 after each step while they fit in FP32 (so a
+ * stored state loads and resumes exactly), unrounded beyond.  A diagonal
+ * past the FP32 range (about alpha t > 40) is stored as +inf; W and the
+ * off-diagonal entries are unaffected and the iteration itself goes on. */
 panda_status panda_ctx_store(panda_ctx* ctx, float* W, float* P, float* C, double* h, int32_t* t);
 
 void panda_ctx_destroy(panda_ctx* ctx);

@@ -286,13 +286,13 @@ __global__ __launch_bounds__(kUT) void k_batch_coop_finalize(const BInst* __rest
 __global__ __launch_bounds__(kUT) void k_batch_diagonals(const BInst* __restrict__ bi,
                                                          FlatList fl, double alpha,
                                                          int32_t diag_alpha, int32_t n_own,
-                                                         int32_t sigma_from_T) {
+                                                         int32_t sigma_from_T, int32_t ddof) {
   __shared__ double red[4];
   const int seg = find_segment(fl.seg_first, fl.nseg, blockIdx.x);
   const BInst& d = bi[seg];
   const DevState* st = d.st;
   if (st->run_pc == 0) return;
-  const upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
+  const upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, ddof, st->t);
   const int64_t q = (int64_t)blockIdx.x - fl.seg_first[seg];
   if (q < d.Ne) {
     upd::diag_p_row(q, d.P, d.Nep, d.dP, d.Ne, d.Na, sigma_from_T ? d.Tside : nullptr, d.nP, dr,
@@ -472,7 +472,7 @@ hipError_t launch_batch_coop_finalize(const BInst* bi, const FlatList& fl, Rule 
 
 hipError_t launch_batch_diagonals(const BInst* bi, const FlatList& fl, Rule rule, hipStream_t s) {
   k_batch_diagonals<<<dim3((unsigned)fl.total), dim3(kUT), 0, s>>>(
-      bi, fl, rule.alpha, rule.diag_alpha, rule.n_own, rule.sigma_from_T);
+      bi, fl, rule.alpha, rule.diag_alpha, rule.n_own, rule.sigma_from_T, rule.sigma_ddof);
   return hipGetLastError();
 }
 

@@ -43,6 +43,14 @@ struct Carver {
 };
 
 constexpr size_t kZsScratch = kZsBlocks + 8;  // doubles
+// Scratch (doubles) of a z-score of a rows x cols network with the given
+// scope: the global form's block partials, or 8 flags plus the per-row and
+// per-column moments.
+size_t zscore_scratch_doubles(int64_t rows, int64_t cols, int32_t mode);
+// Z-score in place (Sec. II-A) with the scope and normaliser of the
+// options; synchronises the stream to read the degeneracy flags.
+panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, int32_t mode, int32_t ddof,
+                    double* scratch, hipStream_t s);
 constexpr int kMaxPending = 16;               // timed iterations between read-backs
 
 Rule rule_of(const panda_options& o);

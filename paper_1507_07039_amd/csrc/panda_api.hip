@@ -38,6 +38,7 @@ Rule rule_of(const panda_options& o) {
   r.n_own = o.n_own;
   r.h_undamped = o.h_undamped;
   r.update_last = o.update_last;
+  r.sigma_ddof = o.sigma_ddof;
   return r;
 }
 
@@ -48,6 +49,9 @@ panda_status check_options(const panda_options& o) {
   if (o.poll_every < 1) return fail(PANDA_ERR_ARG, "poll_every must be >= 1%s");
   if (o.precision != PANDA_PREC_FP32 && o.precision != PANDA_PREC_BF16X3)
     return fail(PANDA_ERR_ARG, "unknown precision%s");
+  if (o.sigma_ddof != 0 && o.sigma_ddof != 1) return fail(PANDA_ERR_ARG, "sigma_ddof must be 0 or 1%s");
+  if (o.zscore_mode < PANDA_ZSCORE_GLOBAL || o.zscore_mode > PANDA_ZSCORE_ROWCOL)
+    return fail(PANDA_ERR_ARG, "unknown zscore_mode%s");
   return PANDA_OK;
 }
 
@@ -91,7 +95,9 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   double* hp = cv.take<double>((size_t)nh);
   double2* cs = cv.take<double2>((size_t)coreg_slots(Nap) * Nap);
   double* cq = cv.take<double>((size_t)coreg_slots(Nap) * Nap);
-  double* zs = cv.take<double>(kZsScratch);
+  // z-score scratch, large enough for an identity prior of either side in any scope
+  const int64_t nid = Nep > Nap ? Nep : Nap;
+  double* zs = cv.take<double>(zscore_scratch_doubles(nid, nid, PANDA_ZSCORE_ROWCOL));
   uint32_t* co = cv.take<uint32_t>((size_t)coreg_tiles(Nap));
   DevState* st = cv.take<DevState>(1);
   // split-BF16 operand planes
@@ -175,22 +181,43 @@ void ctx_free(panda_ctx* c) {
   c->ev[0][0] = nullptr;
 }
 
+size_t zscore_scratch_doubles(int64_t rows, int64_t cols, int32_t mode) {
+  if (mode == PANDA_ZSCORE_GLOBAL) return kZsScratch;
+  const size_t rc = 8 + 2 * (size_t)rows + (mode == PANDA_ZSCORE_ROWCOL ? 2 * (size_t)cols : 0);
+  return rc > kZsScratch ? rc : kZsScratch;
+}
+
+panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, int32_t mode, int32_t ddof,
+                    double* scratch, hipStream_t s) {
+  if (mode == PANDA_ZSCORE_GLOBAL) {
+    HIP_TRY(launch_zscore_stats(M, rows, cols, ld, scratch, s, ddof));
+    double tail[3];
+    HIP_TRY(hipMemcpyAsync(tail, scratch + kZsBlocks, sizeof tail, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (tail[2] != 0.0) return fail(PANDA_ERR_NONFINITE, "network contains NaN or Inf%s");
+    if (!(tail[1] > 0.0)) return fail(PANDA_ERR_DEGENERATE, "network is constant (std = 0)%s");
+    HIP_TRY(launch_zscore_apply(M, rows, cols, ld, scratch, s));
+    return PANDA_OK;
+  }
+  double* flags = scratch;
+  double2* rs = reinterpret_cast<double2*>(scratch + 8);
+  double2* cs = mode == PANDA_ZSCORE_ROWCOL ? rs + rows : nullptr;
+  HIP_TRY(launch_zscore_rc_stats(M, rows, cols, ld, ddof, flags, rs, cs, s));
+  double f[2];
+  HIP_TRY(hipMemcpyAsync(f, flags, sizeof f, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (f[0] != 0.0) return fail(PANDA_ERR_NONFINITE, "network contains NaN or Inf%s");
+  if (f[1] != 0.0)
+    return fail(PANDA_ERR_DEGENERATE, "a row or column of the network is constant (std = 0)%s");
+  HIP_TRY(launch_zscore_rc_apply(M, rows, cols, ld, rs, cs, s));
+  return PANDA_OK;
+}
+
 }  // namespace panda
 
 namespace {
 
 // z-score of a strided matrix using `scratch`; synchronises the stream.
-panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, double* scratch,
-                    hipStream_t s) {
-  HIP_TRY(launch_zscore_stats(M, rows, cols, ld, scratch, s));
-  double tail[3];
-  HIP_TRY(hipMemcpyAsync(tail, scratch + kZsBlocks, sizeof tail, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (tail[2] != 0.0) return fail(PANDA_ERR_NONFINITE, "network contains NaN or Inf%s");
-  if (!(tail[1] > 0.0)) return fail(PANDA_ERR_DEGENERATE, "network is constant (std = 0)%s");
-  HIP_TRY(launch_zscore_apply(M, rows, cols, ld, scratch, s));
-  return PANDA_OK;
-}
 
 // Phase boundary marker: records event `p` of the current pending
 // iteration when timing is on.
@@ -330,6 +357,8 @@ void panda_default_options(panda_options* o) {
   o->update_last = 0;
   o->poll_every = 1;
   o->precision = PANDA_PREC_FP32;
+  o->sigma_ddof = 0;
+  o->zscore_mode = PANDA_ZSCORE_GLOBAL;
 }
 
 panda_status panda_ctx_set_timing(panda_ctx* c, int32_t enable) {
@@ -388,7 +417,28 @@ panda_status panda_normalize(float* M, int64_t rows, int64_t cols, void* workspa
   if (!workspace || ws_bytes < panda_normalize_workspace_bytes() ||
       (reinterpret_cast<uintptr_t>(workspace) % kAlign))
     return fail(PANDA_ERR_WORKSPACE, "normalize: workspace too small or misaligned%s");
-  return zscore(M, rows, cols, cols, static_cast<double*>(workspace), stream);
+  return zscore(M, rows, cols, cols, PANDA_ZSCORE_GLOBAL, 0, static_cast<double*>(workspace),
+                stream);
+}
+
+size_t panda_normalize_ex_workspace_bytes(int64_t rows, int64_t cols, int32_t zscore_mode) {
+  if (rows < 1 || cols < 1 || zscore_mode < PANDA_ZSCORE_GLOBAL ||
+      zscore_mode > PANDA_ZSCORE_ROWCOL)
+    return 0;
+  return align_up(zscore_scratch_doubles(rows, cols, zscore_mode) * sizeof(double));
+}
+
+panda_status panda_normalize_ex(float* M, int64_t rows, int64_t cols, int32_t zscore_mode,
+                                int32_t ddof, void* workspace, size_t ws_bytes,
+                                hipStream_t stream) {
+  if (!M || rows < 1 || cols < 1) return fail(PANDA_ERR_ARG, "normalize_ex: bad matrix%s");
+  if (zscore_mode < PANDA_ZSCORE_GLOBAL || zscore_mode > PANDA_ZSCORE_ROWCOL || ddof < 0 ||
+      ddof > 1)
+    return fail(PANDA_ERR_ARG, "normalize_ex: unknown zscore_mode or ddof%s");
+  if (!workspace || ws_bytes < panda_normalize_ex_workspace_bytes(rows, cols, zscore_mode) ||
+      (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(PANDA_ERR_WORKSPACE, "normalize_ex: workspace too small or misaligned%s");
+  return zscore(M, rows, cols, cols, zscore_mode, ddof, static_cast<double*>(workspace), stream);
 }
 
 namespace {
@@ -532,14 +582,14 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
     st = copy_in(c->P, Nep, P, Ne, Ne, s);
   } else {
     HIP_TRY(launch_fill_identity(c->P, Ne, Nep, s));
-    st = zscore(c->P, Ne, Ne, Nep, c->zs, s);
+    st = zscore(c->P, Ne, Ne, Nep, c->opt.zscore_mode, c->opt.sigma_ddof, c->zs, s);
   }
   if (st != PANDA_OK) return st;
   if (C) {
     st = copy_in(c->C, Nap, C, Na, Na, s);
   } else {
     HIP_TRY(launch_fill_identity(c->C, Na, Nap, s));
-    st = zscore(c->C, Na, Na, Nap, c->zs, s);
+    st = zscore(c->C, Na, Na, Nap, c->opt.zscore_mode, c->opt.sigma_ddof, c->zs, s);
   }
   if (st != PANDA_OK) return st;
   // squared norms of the loaded state (later iterations produce their own)

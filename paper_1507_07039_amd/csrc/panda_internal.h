@@ -28,6 +28,7 @@ struct Rule {
   int32_t n_own;
   int32_t h_undamped;
   int32_t update_last;
+  int32_t sigma_ddof;
 };
 
 typedef unsigned short bf16_t;           // raw bits of a bfloat16
@@ -166,7 +167,15 @@ hipError_t launch_col_sqnorms(const float* M, int64_t rows, int64_t cols, int64_
 // Z-score (Sec. II-A) on a strided matrix; scratch holds kZsBlocks + 8 doubles.
 constexpr int kZsBlocks = 1024;
 hipError_t launch_zscore_stats(const float* M, int64_t rows, int64_t cols, int64_t ld,
-                               double* scratch, hipStream_t s);
+                               double* scratch, hipStream_t s, int ddof = 0);
+// Per-row moments (rs, one per row) and, when cs is given, per-column
+// moments (cs, one per column) as (mean, std); flags[0] / flags[1] are set
+// for a NaN/Inf entry / a row or column of zero spread.  apply: per-row
+// z-score, or (row z + column z) / sqrt 2 when cs is given.
+hipError_t launch_zscore_rc_stats(const float* M, int64_t rows, int64_t cols, int64_t ld, int ddof,
+                                  double* flags, double2* rs, double2* cs, hipStream_t s);
+hipError_t launch_zscore_rc_apply(float* M, int64_t rows, int64_t cols, int64_t ld,
+                                  const double2* rs, const double2* cs, hipStream_t s);
 hipError_t launch_zscore_apply(float* M, int64_t rows, int64_t cols, int64_t ld,
                                const double* scratch, hipStream_t s);
 hipError_t launch_fill_identity(float* M, int64_t n, int64_t ld, hipStream_t s);

@@ -95,14 +95,25 @@ __device__ __forceinline__ void coop_finalize_entry(
 struct DiagRule {
   double keep, g, f;
   int32_t n_own;
+  int32_t ddof;  // sigma: population (0) or sample (1) standard deviation
 };
 __device__ __forceinline__ DiagRule diag_rule(double alpha, int32_t diag_alpha, int32_t n_own,
-                                              int32_t t) {
-  return DiagRule{1.0 - alpha, exp(2.0 * alpha * (double)t), diag_alpha ? alpha : 1.0, n_own};
+                                              int32_t ddof, int32_t t) {
+  return DiagRule{1.0 - alpha, exp(2.0 * alpha * (double)t), diag_alpha ? alpha : 1.0, n_own,
+                  ddof};
 }
 
-// Eq. 6 for row i of P (one block): population std of the off-diagonal
-// entries by two passes over the row (of the fresh similarities when Tside is
+// A new diagonal is rounded to FP32 like every stored entry, so that a state
+// stored to FP32 matrices and loaded again resumes exactly; past the FP32
+// range (exp(2 alpha t) overflows it near alpha t ~ 40) it stays FP64, the
+// run goes on as in FP64, and only a stored copy of that diagonal reads inf.
+__device__ __forceinline__ double diag_round(double x) {
+  const float f = (float)x;
+  return __builtin_isinf(f) ? x : (double)f;
+}
+
+// Eq. 6 for row i of P (one block): standard deviation (population, or
+// sample under ddof = 1) of the off-diagonal entries by two passes over the row (of the fresh similarities when Tside is
 // set), the new diagonal dP[i] (an FP32 value held in FP64 beside P, which
 // holds zero there), and |P_i.|^2 for the next iteration.
 __device__ __forceinline__ void diag_p_row(int64_t i, const float* __restrict__ P, int64_t ldp,
@@ -124,11 +135,11 @@ __device__ __forceinline__ void diag_p_row(int64_t i, const float* __restrict__ 
   double q = 0.0;
   for (int64_t m = threadIdx.x; m < Ne; m += kUT)
     if (m != i) q += ((double)row[m] - mean) * ((double)row[m] - mean);
-  const double var = Ne > 1 ? block_sum(q, red) / n : 0.0;
+  const double qs = block_sum(q, red);
+  const double var = n - dr.ddof >= 1.0 ? qs / (n - dr.ddof) : 0.0;
   if (threadIdx.x == 0) {
     const double mult = dr.n_own ? (double)Ne : (double)Na;
-    // rounded to FP32 like every stored entry, so a stored state resumes exactly
-    const double dn = (double)(float)(dr.keep * dP[i] + dr.f * mult * sqrt(var) * dr.g);
+    const double dn = diag_round(dr.keep * dP[i] + dr.f * mult * sqrt(var) * dr.g);
     dP[i] = dn;
     nP[i] = off2 + dn * dn;
   }
@@ -142,14 +153,18 @@ __device__ __forceinline__ void diag_p_row(int64_t i, const float* __restrict__ 
 __device__ __forceinline__ void diag_c_finish(int64_t r, double s1, double s2, double c2,
                                               double* __restrict__ dC, int64_t Ne, int64_t Na,
                                               double* __restrict__ nC, const DiagRule& dr) {
+  // one-pass FP64 variance; the off-diagonal entries of C are O(1) with a
+  // mean well below their spread, so the cancellation costs a few FP64 ulps
   double var = 0.0;
-  if (Na > 1) {
-    const double n = (double)(Na - 1), mean = s1 / n;
+  const double n = (double)(Na - 1);
+  if (n - dr.ddof >= 1.0) {
+    const double mean = s1 / n;
     var = s2 / n - mean * mean;
     if (var < 0.0) var = 0.0;
+    if (dr.ddof) var *= n / (n - 1.0);
   }
   const double mult = dr.n_own ? (double)Na : (double)Ne;
-  const double dn = (double)(float)(dr.keep * dC[r] + dr.f * mult * sqrt(var) * dr.g);
+  const double dn = diag_round(dr.keep * dC[r] + dr.f * mult * sqrt(var) * dr.g);
   dC[r] = dn;
   nC[r] = c2 + dn * dn;
 }

@@ -35,10 +35,10 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     const float* __restrict__ Tside, double* __restrict__ nP, double* __restrict__ dC,
     int64_t ldc, int64_t Na, const double2* __restrict__ cstat, const double* __restrict__ csq,
     int64_t nslots, double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own,
-    const DevState* st, int32_t sched, double keep, double g) {
+    int32_t ddof, const DevState* st, int32_t sched, double keep, double g) {
   __shared__ double red[4];
   if (st->run_pc == 0) return;
-  upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, st->t);
+  upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, ddof, st->t);
   if (sched) {  // closed form of several steps (warm state)
     dr.keep = keep;
     dr.g = g;
@@ -307,7 +307,8 @@ __global__ __launch_bounds__(kRT) void k_zs_sum(const float* __restrict__ M, int
   }
 }
 
-__global__ __launch_bounds__(kRT) void k_zs_finish(double* scratch, int64_t n, int pass) {
+__global__ __launch_bounds__(kRT) void k_zs_finish(double* scratch, int64_t n, int pass,
+                                                   int ddof) {
   __shared__ double red[4];
   double s = 0.0;
   for (int i = threadIdx.x; i < kZsBlocks; i += kRT) s += scratch[i];
@@ -316,7 +317,8 @@ __global__ __launch_bounds__(kRT) void k_zs_finish(double* scratch, int64_t n, i
     if (!pass) {
       scratch[kZsBlocks] = tot / (double)n;
     } else {
-      scratch[kZsBlocks + 1] = sqrt(tot / (double)n);
+      // std = 0 (a constant network, or no degree of freedom) is reported
+      scratch[kZsBlocks + 1] = n - ddof >= 1 ? sqrt(tot / (double)(n - ddof)) : 0.0;
     }
   }
 }
@@ -334,6 +336,81 @@ __global__ __launch_bounds__(kRT) void k_zs_apply(float* __restrict__ M, int64_t
     float* p = M + (e / cols) * ld + e % cols;
     *p = (float)(((double)*p - mean) / sd);
   }
+}
+
+// Z-score per row, or row + column (scopes of the z-score of Sec. II-A).
+// flags[0] = 1 if an entry is NaN/Inf, flags[1] = 1 if a row or column has
+// zero spread (every writer stores the same 1.0).  Moments in FP64, two
+// passes; sd = 0 when fewer than ddof + 1 entries.
+__global__ __launch_bounds__(kRT) void k_zs_rows(const float* __restrict__ M, int64_t cols,
+                                                 int64_t ld, int ddof, double2* __restrict__ rs,
+                                                 double* flags) {
+  __shared__ double red[4];
+  const float* row = M + (int64_t)blockIdx.x * ld;
+  double s = 0.0, bad = 0.0;
+  for (int64_t j = threadIdx.x; j < cols; j += kRT) {
+    const double x = (double)row[j];
+    if (!isfinite(x)) bad += 1.0;
+    s += x;
+  }
+  const double mean = block_sum(s, red) / (double)cols;
+  const double nb = block_sum(bad, red);
+  double q = 0.0;
+  for (int64_t j = threadIdx.x; j < cols; j += kRT) {
+    const double d = (double)row[j] - mean;
+    q += d * d;
+  }
+  const double qs = block_sum(q, red);
+  if (threadIdx.x == 0) {
+    const double sd = cols - ddof >= 1 ? sqrt(qs / (double)(cols - ddof)) : 0.0;
+    rs[blockIdx.x] = make_double2(mean, sd);
+    if (nb > 0.0) flags[0] = 1.0;
+    if (!(sd > 0.0)) flags[1] = 1.0;
+  }
+}
+
+// Column moments, one thread per column walking down the rows (coalesced
+// across the wave).
+__global__ __launch_bounds__(kRT) void k_zs_cols(const float* __restrict__ M, int64_t rows,
+                                                 int64_t cols, int64_t ld, int ddof,
+                                                 double2* __restrict__ cs, double* flags) {
+  const int64_t j = (int64_t)blockIdx.x * kRT + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < rows; ++i) s += (double)M[i * ld + j];
+  const double mean = s / (double)rows;
+  double q = 0.0;
+  for (int64_t i = 0; i < rows; ++i) {
+    const double d = (double)M[i * ld + j] - mean;
+    q += d * d;
+  }
+  const double sd = rows - ddof >= 1 ? sqrt(q / (double)(rows - ddof)) : 0.0;
+  cs[j] = make_double2(mean, sd);
+  if (!(sd > 0.0)) flags[1] = 1.0;
+}
+
+__global__ __launch_bounds__(kRT) void k_zs_apply_rc(float* __restrict__ M, int64_t rows,
+                                                     int64_t cols, int64_t ld,
+                                                     const double2* __restrict__ rs,
+                                                     const double2* __restrict__ cs) {
+  const int64_t n = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * kRT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kRT) {
+    const int64_t i = e / cols, j = e % cols;
+    float* p = M + i * ld + j;
+    const double x = (double)*p;
+    const double2 r = rs[i];
+    const double zr = (x - r.x) / r.y;
+    if (cs) {
+      const double2 c = cs[j];
+      *p = (float)((zr + (x - c.x) / c.y) / sqrt(2.0));
+    } else {
+      *p = (float)zr;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_zs_flags_clear(double* flags) {
+  if (threadIdx.x < 8) flags[threadIdx.x] = 0.0;
 }
 
 __global__ __launch_bounds__(kRT) void k_fill_identity(float* __restrict__ M, int64_t n,
@@ -403,7 +480,7 @@ hipError_t launch_diagonals(const float* P, int64_t ldp, double* dP, int64_t Ne,
   const int64_t nb = Ne + (Na + 63) / 64;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
-                                                 rule.n_own, st, 0, 0.0, 0.0);
+                                                 rule.n_own, rule.sigma_ddof, st, 0, 0.0, 0.0);
   return hipGetLastError();
 }
 
@@ -415,7 +492,7 @@ hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, in
   const int64_t nb = Ne + (Na + 63) / 64;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
-                                                 rule.n_own, st, 1, keep, g);
+                                                 rule.n_own, rule.sigma_ddof, st, 1, keep, g);
   return hipGetLastError();
 }
 
@@ -495,13 +572,29 @@ hipError_t launch_col_sqnorms(const float* M, int64_t rows, int64_t cols, int64_
 }
 
 hipError_t launch_zscore_stats(const float* M, int64_t rows, int64_t cols, int64_t ld,
-                               double* scratch, hipStream_t s) {
+                               double* scratch, hipStream_t s, int ddof) {
   const int64_t n = rows * cols;
   k_zs_clear<<<1, kRT, 0, s>>>(scratch);
   k_zs_sum<<<kZsBlocks, kRT, 0, s>>>(M, rows, cols, ld, scratch, 0);
-  k_zs_finish<<<1, kRT, 0, s>>>(scratch, n, 0);
+  k_zs_finish<<<1, kRT, 0, s>>>(scratch, n, 0, ddof);
   k_zs_sum<<<kZsBlocks, kRT, 0, s>>>(M, rows, cols, ld, scratch, 1);
-  k_zs_finish<<<1, kRT, 0, s>>>(scratch, n, 1);
+  k_zs_finish<<<1, kRT, 0, s>>>(scratch, n, 1, ddof);
+  return hipGetLastError();
+}
+
+hipError_t launch_zscore_rc_stats(const float* M, int64_t rows, int64_t cols, int64_t ld, int ddof,
+                                  double* flags, double2* rs, double2* cs, hipStream_t s) {
+  k_zs_flags_clear<<<1, kRT, 0, s>>>(flags);
+  k_zs_rows<<<dim3((unsigned)rows), kRT, 0, s>>>(M, cols, ld, ddof, rs, flags);
+  if (cs)
+    k_zs_cols<<<dim3((unsigned)((cols + kRT - 1) / kRT)), kRT, 0, s>>>(M, rows, cols, ld, ddof, cs,
+                                                                         flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_zscore_rc_apply(float* M, int64_t rows, int64_t cols, int64_t ld,
+                                  const double2* rs, const double2* cs, hipStream_t s) {
+  k_zs_apply_rc<<<grid_for(rows * cols, 4096), kRT, 0, s>>>(M, rows, cols, ld, rs, cs);
   return hipGetLastError();
 }
 

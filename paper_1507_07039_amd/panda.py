@@ -21,6 +21,7 @@ ERR_ARG, ERR_DEGENERATE, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4,
 # Every extern "C" entry point declared in include/panda.h.
 EXPORTS = (
     "panda_default_options", "panda_normalize_workspace_bytes", "panda_normalize",
+    "panda_normalize_ex_workspace_bytes", "panda_normalize_ex",
     "panda_tanimoto_workspace_bytes", "panda_tanimoto",
     "panda_pearson_workspace_bytes", "panda_pearson", "panda_workspace_bytes",
     "panda_ctx_create", "panda_ctx_load", "panda_iterate", "panda_ctx_store",
@@ -43,6 +44,9 @@ BATCH_TILES = ("R", "A+W", "P-partial", "C")
 PHASES = ("R", "A+W", "h", "P-partial", "P-final", "C", "diag")
 
 
+ZSCORE_GLOBAL, ZSCORE_ROW, ZSCORE_ROWCOL = 0, 1, 2
+
+
 class PandaError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"panda status {code}: {msg}")
@@ -55,7 +59,8 @@ class Options(ct.Structure):
                 ("diag_alpha", ct.c_int32), ("sigma_from_T", ct.c_int32),
                 ("n_own", ct.c_int32), ("h_undamped", ct.c_int32),
                 ("update_last", ct.c_int32), ("poll_every", ct.c_int32),
-                ("precision", ct.c_int32)]
+                ("precision", ct.c_int32), ("sigma_ddof", ct.c_int32),
+                ("zscore_mode", ct.c_int32)]
 
 
 _lib = None
@@ -75,6 +80,8 @@ def load_library(path: str = LIB_PATH):
         "panda_default_options": (None, [op]),
         "panda_normalize_workspace_bytes": (sz, []),
         "panda_normalize": (ct.c_int, [vp, i64, i64, vp, sz, vp]),
+        "panda_normalize_ex_workspace_bytes": (sz, [i64, i64, i32]),
+        "panda_normalize_ex": (ct.c_int, [vp, i64, i64, i32, i32, vp, sz, vp]),
         "panda_tanimoto_workspace_bytes": (sz, [i64, i64, i64]),
         "panda_tanimoto": (ct.c_int, [vp, vp, i64, i64, i64, vp, vp, sz, vp]),
         "panda_pearson_workspace_bytes": (sz, [i64, i64]),
@@ -176,12 +183,20 @@ def workspace(nbytes: int):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
 
 
-def normalize(M) -> None:
-    """Z-score the network M in place (panda_normalize)."""
+def normalize(M, mode: int = 0, ddof: int = 0) -> None:
+    """Z-score the network M in place: panda_normalize (all entries,
+    population std) by default, else panda_normalize_ex with the scope
+    mode (ZSCORE_GLOBAL / ZSCORE_ROW / ZSCORE_ROWCOL) and normaliser ddof."""
     lib = load_library()
     rows, cols = M.shape
-    ws = workspace(lib.panda_normalize_workspace_bytes())
-    _check(lib.panda_normalize(_dev(M, "M"), rows, cols, ws.data_ptr(), ws.numel(), _stream()))
+    if mode == ZSCORE_GLOBAL and ddof == 0:
+        ws = workspace(lib.panda_normalize_workspace_bytes())
+        _check(lib.panda_normalize(_dev(M, "M"), rows, cols, ws.data_ptr(), ws.numel(),
+                                   _stream()))
+        return
+    ws = workspace(lib.panda_normalize_ex_workspace_bytes(rows, cols, mode))
+    _check(lib.panda_normalize_ex(_dev(M, "M"), rows, cols, mode, ddof, ws.data_ptr(),
+                                  ws.numel(), _stream()))
 
 
 def tanimoto(X, Y):

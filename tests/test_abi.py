@@ -35,10 +35,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_options_struct_layout(lib):
     o = panda.default_options()
-    assert ct.sizeof(panda.Options) == 8 + 8 + 8 * 4
+    assert ct.sizeof(panda.Options) == 8 + 8 + 10 * 4
     assert o.alpha == 0.1 and o.tol == 1e-3 and o.max_iter == 200
     assert (o.diag_alpha, o.sigma_from_T, o.n_own, o.h_undamped, o.update_last) == (1, 0, 0, 0, 0)
     assert o.poll_every == 1 and o.precision == 0
+    assert o.sigma_ddof == 0 and o.zscore_mode == panda.ZSCORE_GLOBAL
 
 
 def test_status_strings(lib):
@@ -57,6 +58,15 @@ def test_workspace_sizes(lib):
     assert big >= 18176 * 18176 * 4 and big < 1.25 * 18176 * 18176 * 4
     assert 0 < small < big
     assert lib.panda_tanimoto_workspace_bytes(0, 1, 1) == 0
+    # z-score scratch: the global form needs a fixed few KB, the row and
+    # row + column forms grow with the row and column counts
+    g = lib.panda_normalize_ex_workspace_bytes(18000, 18000, panda.ZSCORE_GLOBAL)
+    assert g == lib.panda_normalize_workspace_bytes()
+    r = lib.panda_normalize_ex_workspace_bytes(18000, 18000, panda.ZSCORE_ROW)
+    rc = lib.panda_normalize_ex_workspace_bytes(18000, 18000, panda.ZSCORE_ROWCOL)
+    assert 16 * 18000 <= r < rc and rc >= 32 * 18000
+    assert lib.panda_normalize_ex_workspace_bytes(5, 5, 3) == 0
+    assert lib.panda_normalize_ex_workspace_bytes(0, 5, 0) == 0
     assert lib.panda_tanimoto_workspace_bytes(3, 5, 7) > 0
     assert lib.panda_normalize_workspace_bytes() >= 8 * 1024
     assert lib.panda_pearson_workspace_bytes(0, 5) == 0

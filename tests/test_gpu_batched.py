@@ -83,7 +83,8 @@ def test_batch_matches_oracle_per_network(torch, pd, oracle):
 
 
 @pytest.mark.parametrize("kw", [{"sigma_from_T": True}, {"n_own": True, "diag_alpha": False},
-                                {"h_undamped": True, "update_last": True}])
+                                {"h_undamped": True, "update_last": True},
+                                {"sigma_ddof": 1, "sigma_from_T": True}])
 def test_batch_reading_flags(torch, pd, oracle, kw):
     nets = [prep(oracle, *I.workload_priors(I.SMALL)), ragged(65, 300)]
     check_steps(torch, pd, oracle, nets, 4, what=f"flags {kw}", **kw)

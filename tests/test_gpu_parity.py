@@ -123,6 +123,65 @@ def test_normalize_errors(torch, pd):
     assert e.value.code == pd.ERR_NONFINITE
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("ddof", [0, 1])
+def test_normalize_ex_matches_oracle(torch, pd, oracle, mode, ddof):
+    """Every scope and normaliser of the z-score against the oracle's, on
+    the small workload's priors, a ragged dense matrix, one-row and one-column
+    shapes (where the scope allows them) and the identity."""
+    W0, P0, C0 = I.workload_priors(I.SMALL)
+    cases = [W0, P0, C0, I.random_dense(3, (17, 33), 5.0, 9.0), np.eye(130)]
+    if mode == 0:
+        cases += [I.random_dense(4, (1, 9), 1.0, 2.0), I.random_dense(5, (7, 1), 1.0, 2.0)]
+    if mode == 1:
+        cases += [I.random_dense(4, (1, 9), 1.0, 2.0), I.random_dense(6, (300, 2), 1.0, 2.0)]
+    for M in cases:
+        M32 = f32r(M)
+        t = cuda(torch, M32)
+        try:
+            want = oracle.normalize_ex(M32, mode, ddof)
+        except oracle.OracleError as e:  # e.g. W0 has empty columns: both sides refuse
+            with pytest.raises(pd.PandaError) as g:
+                pd.normalize(t, mode=mode, ddof=ddof)
+            assert g.value.code == e.code == pd.ERR_DEGENERATE
+            continue
+        pd.normalize(t, mode=mode, ddof=ddof)
+        # one FP32 rounding of an FP64 value (the moments agree to FP64 rounding)
+        err = np.abs(host(t) - want).max()
+        assert err <= 2e-7 * max(1.0, np.abs(want).max()), (M.shape, err)
+
+
+def test_normalize_ex_errors(torch, pd):
+    rng = np.random.default_rng(11)
+    M = rng.normal(size=(6, 9)).astype(np.float32)
+    M[2] = 1.5  # constant row
+    t = cuda(torch, M)
+    pd.normalize(t, mode=pd.ZSCORE_GLOBAL, ddof=1)  # fine for the global scope
+    for mode in (pd.ZSCORE_ROW, pd.ZSCORE_ROWCOL):
+        t = cuda(torch, M)
+        with pytest.raises(pd.PandaError) as e:
+            pd.normalize(t, mode=mode)
+        assert e.value.code == pd.ERR_DEGENERATE
+        assert np.array_equal(host(t), M.astype(np.float64))  # untouched
+    M = rng.normal(size=(6, 9)).astype(np.float32)
+    M[:, 4] = -2.0  # constant column: only the row + column scope fails
+    pd.normalize(cuda(torch, M), mode=pd.ZSCORE_ROW)
+    with pytest.raises(pd.PandaError) as e:
+        pd.normalize(cuda(torch, M), mode=pd.ZSCORE_ROWCOL)
+    assert e.value.code == pd.ERR_DEGENERATE
+    with pytest.raises(pd.PandaError) as e:  # one entry per row, sample std
+        pd.normalize(cuda(torch, M[:, :1].copy()), mode=pd.ZSCORE_ROW, ddof=1)
+    assert e.value.code == pd.ERR_DEGENERATE
+    M[3, 3] = np.nan
+    for mode in (0, 1, 2):
+        with pytest.raises(pd.PandaError) as e:
+            pd.normalize(cuda(torch, M), mode=mode, ddof=1)
+        assert e.value.code == pd.ERR_NONFINITE
+    with pytest.raises(pd.PandaError) as e:
+        pd.normalize(cuda(torch, M), mode=3)
+    assert e.value.code == pd.ERR_ARG
+
+
 # ------------------------------------------------------------ iterations ---
 
 def compare_state(W, P, C, Wo, Po, Co, what=""):
@@ -179,7 +238,8 @@ def test_small_workload_matched_iterations(torch, pd, oracle):
 
 
 @pytest.mark.parametrize("kw", [{"diag_alpha": False}, {"sigma_from_T": True}, {"n_own": True},
-                                {"h_undamped": True}, {"update_last": True},
+                                {"h_undamped": True}, {"update_last": True}, {"sigma_ddof": 1},
+                                {"sigma_ddof": 1, "sigma_from_T": True},
                                 {"alpha": 0.3, "tol": 1e-4}])
 def test_readings_flags(torch, pd, oracle, kw):
     W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
@@ -211,6 +271,23 @@ def test_identity_defaults(torch, pd, oracle):
     assert np.abs(host(Pg) - P).max() <= 2e-7 * np.abs(P).max()
     assert np.abs(host(Cg) - C).max() <= 2e-7 * np.abs(C).max()
     run_matched(torch, pd, oracle, W, P, C, steps=5, pass_identity=True)
+
+
+@pytest.mark.parametrize("mode,ddof", [(1, 0), (2, 1), (0, 1)])
+def test_identity_defaults_other_scopes(torch, pd, oracle, mode, ddof):
+    """The identity default is z-scored with the context's scope and
+    normaliser; the run from it follows the oracle with the same sigma rule."""
+    W0, _, _ = I.workload_priors(I.SMALL)
+    W = f32r(oracle.normalize(W0))
+    Ne, Na = W.shape
+    P = f32r(oracle.normalize_ex(np.eye(Ne), mode, ddof))
+    C = f32r(oracle.normalize_ex(np.eye(Na), mode, ddof))
+    ctx = pd.Context(Ne, Na, pd.default_options(zscore_mode=mode, sigma_ddof=ddof))
+    ctx.load(cuda(torch, W))
+    _, Pg, Cg, _, _ = ctx.state()
+    assert np.abs(host(Pg) - P).max() <= 2e-7 * np.abs(P).max()
+    assert np.abs(host(Cg) - C).max() <= 2e-7 * np.abs(C).max()
+    run_matched(torch, pd, oracle, W, P, C, opts_kw={"sigma_ddof": ddof}, steps=5)
 
 
 def test_run_entry_point(torch, pd, oracle):
@@ -258,3 +335,25 @@ def test_resume_equals_straight_run(torch, pd, oracle):
     Wr, Pr, Cr, hr, tr = ctx2.state()
     assert tr == straight.iters
     assert torch.equal(Wr, straight.W) and torch.equal(Cr, straight.C) and torch.equal(Pr, straight.P)
+
+
+def test_diagonals_past_fp32_range(torch, pd, oracle):
+    """At alpha = 1 the Eq. 6 diagonals pass FLT_MAX near t = 40 (they reach
+    ~1e55 by t = 60).  They stay FP64 on the GPU, so W and the off-diagonal
+    entries keep following the FP64 oracle; a stored diagonal past the FP32
+    range reads +inf, every other one matches."""
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    kw = dict(alpha=1.0, tol=0.0, max_iter=60)
+    ref = oracle.run(W, P, C, oracle.Options(**kw))
+    assert ref.status == oracle.NOT_CONVERGED and np.diag(ref.P).max() > 1e50
+    res = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C), **kw)
+    assert res.status == pd.NOT_CONVERGED and res.iters == 60
+    Wg, Pg, Cg = host(res.W), host(res.P), host(res.C)
+    assert np.abs(Wg - ref.W).max() <= 1e-4
+    for G, R in ((Pg, ref.P), (Cg, ref.C)):
+        off = ~np.eye(G.shape[0], dtype=bool)
+        assert np.abs(G - R)[off].max() <= 1e-4
+        dg, dr = np.diag(G), np.diag(R)
+        big = np.abs(dr) > np.finfo(np.float32).max
+        assert big.any() and np.all(dg[big] == np.inf)
+        assert np.all(np.abs(dg[~big] - dr[~big]) <= 1e-5 * np.abs(dr[~big]))

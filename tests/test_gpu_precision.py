@@ -89,7 +89,7 @@ def test_small_workload_matched_iterations(torch, pd, oracle):
 
 
 @pytest.mark.parametrize("kw", [{"sigma_from_T": True}, {"n_own": True, "diag_alpha": False},
-                                {"h_undamped": True}])
+                                {"h_undamped": True}, {"sigma_ddof": 1}])
 def test_reading_flags(torch, pd, oracle, kw):
     """The readings of the paper (option flags) in the split-BF16 form, per
     step against the FP64 oracle with the same flags."""
