@@ -12,13 +12,18 @@ Printed (one JSON line):
   roofline     the dominant kernel (A = T(W, C) fused with the W update):
                algorithmic FLOPs 2 T G^2 per launch over its event-timed
                average duration, against the FP32 matrix-core peak
-  cpu_baseline the FP64 oracle on a bounded sample of the same iteration,
-               scaled to seconds per iteration
+  cpu_baseline the FP64 oracle: one whole iteration of this workload,
+               measured on every host thread, and on one thread a column
+               slice of the same iteration scaled up; with the CPU model
+  accuracy     W of both forms against the stored FP64 oracle run of this
+               workload (tests/golden/, written by the oracle alone) at its
+               checkpoints, max-abs and relative to max|W|
   chosen_form  the split-BF16 products (and the learned warm start, judged
                against the plain run: accepted only within 1e-3 max|W|)
-HBM traffic of the dominant kernels comes from rocprofv3 FETCH_SIZE /
-WRITE_SIZE counters recorded in profiles/ and is reported only while the
-kernel sources still hash to the digest recorded with them.
+HBM traffic of the dominant kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE) and
+their kernel-trace durations come from summaries recorded in profiles/ and
+are reported only while the kernel sources still hash to the digest recorded
+with them.
 """
 from __future__ import annotations
 
@@ -44,6 +49,8 @@ PEAK_HBM_GBS = 8000.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "iteration_T700_G18000_hbm_traffic.md")
+TRACE_FILE = os.path.join(ROOT, "profiles", "iteration_T700_G18000_kernel_trace.md")
+GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "oracle_panda-T700-G18000.json")
 
 
 def log(*a):
@@ -61,20 +68,75 @@ def csrc_digest() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """{key: bytes per launch} from the counter summary, or {} when the
-    summary is missing or the kernels changed since it was recorded."""
-    if not os.path.exists(TRAFFIC_FILE):
+def recorded_values(path, suffix):
+    """{key: value} of the machine-readable lines (- `key`: value) of a
+    profile summary whose key ends in suffix, or {} when the summary is
+    missing or the kernels changed since it was recorded."""
+    if not os.path.exists(path):
         return {}
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         line = line.strip()
         if line.startswith("- `") and "`: " in line:
             k, v = line[3:].split("`: ", 1)
             vals[k] = v.strip()
     if vals.get("csrc_sha256") != csrc_digest():
         return {}
-    return {k: float(v) for k, v in vals.items() if k.endswith("_bytes")}
+    return {k: float(v) for k, v in vals.items() if k.endswith(suffix)}
+
+
+def recorded_traffic():
+    """{key: bytes per launch} from the counter summary."""
+    return recorded_values(TRAFFIC_FILE, "_bytes")
+
+
+def recorded_trace_us():
+    """{key: average kernel duration in us} from the kernel-trace summary."""
+    return recorded_values(TRACE_FILE, "_us")
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def accuracy_vs_golden(torch, panda, W, P, C, precision: int):
+    """W of the form against the stored FP64 oracle run at its checkpoints:
+    {t: [max-abs, max-abs / max(1, max|W|)]} over the stored sampled entries.
+    The stored run started from the oracle's z-scores rounded to FP32; these
+    inputs are the library's z-scores (FP64 moments in another summation
+    order, the same FP32 values up to rare last-bit flips), so the figures
+    include that input difference."""
+    if not os.path.exists(GOLDEN_FILE):
+        return None
+    g = json.load(open(GOLDEN_FILE))
+    Ne, Na = W.shape
+    if (g["workload"]["T"], g["workload"]["G"]) != (Ne, Na):
+        return None
+    ctx = panda.Context(Ne, Na, panda.default_options(tol=0.0, precision=precision))
+    ctx.load(W, P, C)
+    iw = g["idx"]["W"]
+    rows = torch.as_tensor(iw[0], device="cuda")
+    cols = torch.as_tensor(iw[1], device="cuda")
+    out = {}
+    for t in range(1, len(g["h_trace"]) + 1):
+        ctx.iterate()
+        snap = g["snapshots"].get(str(t))
+        if snap is None:
+            continue
+        Wg = ctx.state()[0]
+        got = Wg[rows, cols].double().cpu().numpy()
+        want = np.asarray(snap["W"], dtype=np.float64)
+        err = float(np.abs(got - want).max())
+        out[str(t)] = [err, err / max(1.0, float(np.abs(want).max()))]
+        del Wg
+    ctx.close()
+    return out
 
 
 def gpu_inputs(w: I.Workload, torch, panda):
@@ -150,36 +212,69 @@ def warm_start_eval(torch, panda, W, P, C, plain):
             "note": "judged by the plain run; when not accepted the plain result stands"}
 
 
-def cpu_baseline(w: I.Workload, budget_s: float = 4.0):
-    """FP64 oracle on sampled entries of each phase of one iteration."""
+def oracle_iteration(O, W, P, C, frac: float = 1.0, report=None):
+    """Time one FP64 oracle iteration as oracle_step runs it: the similarity
+    matrices R = T(P, W), A = T(W, C) (with the W update), T(W', W'^T) and
+    T(W'^T, W') by the oracle's Tfunction, which gathers each column once and
+    runs every row against it.  frac < 1 computes only the leading frac of
+    each matrix's columns (all rows) and scales each part by its column
+    fraction, which keeps that access pattern; frac = 1 is the whole
+    iteration, measured.  The C side runs in column blocks so that progress
+    can be reported.  Returns (seconds, {part: seconds})."""
+    a = 0.1
+    Ne, Na = W.shape
+    nA = max(1, int(round(Na * frac)))
+    nE = max(1, int(round(Ne * frac)))
+    parts = {}
+
+    def timed(name, fn, scale):
+        t0 = time.perf_counter()
+        out = fn()
+        parts[name] = parts.get(name, 0.0) + (time.perf_counter() - t0) * scale
+        if report:
+            report(f"{name}: {parts[name]:.1f} s")
+        return out
+
+    R = timed("R", lambda: O.tanimoto(P, np.ascontiguousarray(W[:, :nA])), Na / nA)
+    Wn = timed("A+W", lambda: (1 - a) * W[:, :nA] + a * 0.5 * (
+        O.tanimoto(W, np.ascontiguousarray(C[:, :nA])) + R), Na / nA)
+    del R
+    if nA < Na:  # the columns not computed keep their W (the matrices below need a full W)
+        Wn = np.concatenate([Wn, W[:, nA:]], axis=1)
+    Wt = np.ascontiguousarray(Wn.T)
+    timed("P", lambda: O.tanimoto(Wn, np.ascontiguousarray(Wt[:, :nE])), Ne / nE)
+    for lo in range(0, nA, 4096):
+        hi = min(nA, lo + 4096)
+        timed("C", lambda: (1 - a) * C[:, lo:hi] + a * O.tanimoto(
+            Wt, np.ascontiguousarray(Wn[:, lo:hi])), Na / nA)
+    return sum(parts.values()), parts
+
+
+def cpu_baseline(w: I.Workload):
+    """The FP64 oracle on this workload: one whole iteration, measured, on
+    every host thread the process may use; and on one thread, the same
+    iteration on a 1/64 column slice of every similarity matrix, scaled."""
     from oracle import oracle as O
     W0, P0, C0 = I.workload_priors(w)
     W, P, C = O.normalize(W0), O.normalize(P0), O.normalize(C0)
     del W0, P0, C0
     Ne, Na = W.shape
-    Wt = np.ascontiguousarray(W.T)
-    rng = np.random.default_rng(0)
-
-    def timed(fn, total, n0):
-        n = n0
-        while True:
-            r = rng.integers(0, 1 << 62, size=n)
-            t0 = time.perf_counter()
-            fn(r, n)
-            dt = time.perf_counter() - t0
-            if dt >= budget_s or n >= total:
-                return dt / n, n
-            n = min(total, n * 4)
-
-    per_w, nw = timed(lambda r, n: O.step_w_entries(W, P, C, 0.1, r % Ne, (r >> 20) % Na), Ne * Na, 2000)
-    per_p, npp = timed(lambda r, n: O.tanimoto_entries(W, Wt, r % Ne, (r >> 20) % Ne), Ne * Ne, 2000)
-    per_c, nc = timed(lambda r, n: O.tanimoto_entries(Wt, W, r % Na, (r >> 20) % Na), Na * Na, 20000)
-    s_iter = per_w * Ne * Na + per_p * Ne * Ne + per_c * Na * Na
-    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    return {"value": s_iter, "unit": "s/iteration", "cores": cores, "kind": "oracle",
-            "sample": (f"FP64 element-wise oracle, {nw} W entries (R+A+update), {npp} P entries, "
-                       f"{nc} C entries of one iteration at T={Ne} G={Na}, time per entry scaled "
-                       f"to the full {Ne}x{Na}, {Ne}x{Ne} and {Na}x{Na} matrices")}
+    cores = O.set_threads(0)  # the OpenMP default: every host thread this process may use
+    full, parts = oracle_iteration(O, W, P, C, 1.0, lambda m: log("cpu baseline, " + m))
+    O.set_threads(1)
+    frac = 1.0 / 64
+    one, parts1 = oracle_iteration(O, W, P, C, frac, lambda m: log("cpu baseline, 1 thread, " + m))
+    O.set_threads(cores)
+    return {"value": full, "unit": "s/iteration", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": (f"one whole FP64 oracle iteration at T={Ne} G={Na}, measured: every entry "
+                       f"of R, A, W, T(W, W^T) and T(W^T, W) by the element-wise Tfunction"),
+            "phases_s": parts,
+            "single_thread": {"value": one, "unit": "s/iteration", "cores": 1,
+                              "sample": (f"the same iteration on one thread over the first 1/64 "
+                                         f"of the columns of each similarity matrix (all rows), "
+                                         f"each part scaled by its column fraction"),
+                              "phases_s": parts1}}
 
 
 def main():
@@ -188,13 +283,16 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="human", choices=["human", "small", "large"])
-    ap.add_argument("--converge-runs", type=int, default=3)
+    ap.add_argument("--converge-runs", type=int, default=5)
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true", help="skip the split-BF16 form")
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (counter calibration)")
+                    help="also run a device copy, a read-only sum and a fill of this many MiB "
+                         "(counter calibration)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the comparison with the stored oracle run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
@@ -222,6 +320,17 @@ def main():
         return per, ms, rates
 
     traffic = recorded_traffic()
+    trace = recorded_trace_us()
+    algo = {"A+W": flops["A+W"]}
+
+    def trace_frac(prefix, peak, mult=1.0):
+        us = trace.get(prefix + "_aw_product_us"), trace.get(prefix + "_aw_fixup_us")
+        if us[0] is None or us[1] is None:
+            return None
+        tot = us[0] + us[1]
+        return {"kernel_us": tot, "achieved": mult * algo["A+W"] / (tot * 1e-6) / 1e12,
+                "frac": mult * algo["A+W"] / (tot * 1e-6) / 1e12 / peak}
+
     log("timing iterations (plain FP32)")
     per, ms, rates = measure(0)
     s_iter = statistics.median(per)
@@ -239,7 +348,8 @@ def main():
                                "k_rect_fixup",
                      "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": traffic.get("fp32_aw_traffic_bytes")},
+                     "traffic": traffic.get("fp32_aw_traffic_bytes"),
+                     "from_kernel_trace": trace_frac("fp32", PEAK_FP32_MFMA_TFLOPS)},
     }
     if not args.plain_only:
         log("timing iterations (split-BF16 form)")
@@ -255,7 +365,8 @@ def main():
                                    "EpiWUpdate> + k_rect_fixup",
                          "achieved": bf_rate, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                          "frac": bf_rate / PEAK_BF16_MFMA_TFLOPS,
-                         "traffic": traffic.get("b3_aw_traffic_bytes")},
+                         "traffic": traffic.get("b3_aw_traffic_bytes"),
+                         "from_kernel_trace": trace_frac("b3", PEAK_BF16_MFMA_TFLOPS, 3.0)},
         }
     if not args.no_converge:
         log("time to converge (plain FP32)")
@@ -277,12 +388,25 @@ def main():
             cf["max_abs_W_plain"] = Wp.abs().max().item()
             if not args.no_warm_start and w is I.HUMAN:
                 cf["warm_start"] = warm_start_eval(torch, panda, W, P, C, res)
+    if not args.no_accuracy and w is I.HUMAN:
+        log("accuracy against the stored oracle run")
+        acc = {"plain-fp32": accuracy_vs_golden(torch, panda, W, P, C, 0)}
+        if not args.plain_only:
+            acc["bf16x3"] = accuracy_vs_golden(torch, panda, W, P, C, 1)
+        result["accuracy_vs_oracle"] = {
+            "what": "W at the stored oracle checkpoints t: [max-abs error, max-abs / max(1, max|W|)]",
+            **acc}
     if args.copy_calibration:
+        # known traffic for the counters: a copy (n reads + n writes), a
+        # read-only sum (n reads) and a fill (n writes)
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
+        torch.cuda.synchronize()
+        _ = a.sum().item()
+        b.fill_(2.0)
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = n * 4
     if not args.no_cpu_baseline:

@@ -87,6 +87,8 @@ def _load():
         lib.oracle_T.argtypes = [dp, i64, dp, i64, i64]
         lib.oracle_tanimoto.argtypes = [dp, dp, i64, i64, i64, dp]
         lib.oracle_tanimoto_entries.argtypes = [dp, dp, i64, i64, i64, lp, lp, i64, dp]
+        lib.oracle_set_threads.argtypes = [ct.c_int]
+        lib.oracle_set_threads.restype = ct.c_int
         lib.oracle_normalize.argtypes = [dp, i64]
         lib.oracle_normalize_ex.argtypes = [dp, i64, i64, i32, i32]
         lib.oracle_step.argtypes = [dp, dp, dp, i64, i64, i32, ct.POINTER(_Opts),
@@ -128,6 +130,11 @@ def _check(code: int, what: str, allow=(OK,)) -> int:
     if code not in allow:
         raise OracleError(code, what)
     return code
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of later oracle calls; returns the previous maximum."""
+    return _load().oracle_set_threads(int(n))
 
 
 def T(x, y) -> float:

@@ -37,6 +37,7 @@
  *   - T(0,0) := 0 (zero denominator only when both vectors are zero).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -59,6 +60,15 @@ typedef struct {
   int32_t update_last;
   int32_t sigma_ddof; /* 0: population std in Eq. 6; 1: sample std */
 } oracle_opts;
+
+/* Number of OpenMP threads for the calls that follow (n >= 1); returns the
+ * previous maximum.  Results do not depend on it (each output entry is owned
+ * by one thread); only timing does. */
+int oracle_set_threads(int n) {
+  int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+}
 
 /* Eq. 1: T(x, y) = x.y / sqrt(|x|^2 + |y|^2 - |x.y|), x and y given with
  * element strides incx and incy.  One pass, three accumulators. */

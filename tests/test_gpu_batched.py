@@ -259,6 +259,8 @@ def test_48_networks_full_size(torch, pd, oracle):
         assert rel <= 1e-3, (i, rel)
         relp = (Wg - Wref).abs().max().item() / max(1.0, Wref.abs().max().item())
         worst_plain = max(worst_plain, (relp, i))
+        print(f"    net {i:2d} {shapes[i][:2]}: plain t={itref}, split t={tg}, "
+              f"max|W| {Wref.abs().max().item():.1f}, split vs plain {relp:.2e}")
     print(f"  split-BF16 batched run {t_b3:.3f} s ({steps3} steps); worst max|dW|/max|W| "
           f"against the split-BF16 single runs = {worst3:.2e}, against the plain runs = "
           f"{worst_plain[0]:.2e} (network {worst_plain[1]}, {shapes[worst_plain[1]][:2]})")

@@ -93,8 +93,14 @@ def test_trajectory_matches_stored_oracle_run(torch, pd, human):
     off-diagonal products, 2^-24, grown by the iteration's sensitivity; the
     diagonal terms of P and C, which grow like exp(2 alpha t), are added in
     FP64).  h is a mean of changes that shrink to ~1e-3 while |W| stays ~1e2:
-    relative 2e-3.  P and C off-diagonals relative to their largest entry
-    1e-4, their diagonals relative 1e-3.  The oracle skips the P/C update on
+    relative 2e-3 (measured 1.5e-3 at t = 74, where h ~ tol: the mean of
+    changes ~1e-3 of entries ~2e3 carries their FP32 drift).  P and C
+    off-diagonals relative to their largest entry 1e-4.  Their diagonals
+    (Eq. 6) follow sigma of their row, whose relative error is that of the
+    row's off-diagonal entries over the row's spread: relative 1.5e-4
+    (measured at most 8.1e-5, diagonal of P at t = 20; the run is
+    deterministic, so the margin covers only the input rounding of
+    regenerated priors).  The oracle skips the P/C update on
     its converging iteration, so P and C are not compared there.  The stopping
     iteration may differ by one only where the oracle's h lies within the h
     tolerance of tol."""
@@ -131,7 +137,7 @@ def test_trajectory_matches_stored_oracle_run(torch, pd, human):
             dC = (np.abs(Cg[idx["Cdiag"], idx["Cdiag"]] - cd_) / np.maximum(1, np.abs(cd_))).max()
             line += f"  P rel {eP:.2e}  C rel {eC:.2e}  diag P {dP:.2e}  diag C {dC:.2e}"
             assert eP <= 1e-4 and eC <= 1e-4, (t, eP, eC)
-            assert dP <= 1e-3 and dC <= 1e-3, (t, dP, dC)
+            assert dP <= 1.5e-4 and dC <= 1.5e-4, (t, dP, dC)
         print(line)
     ctx.close()
     assert g["converged"]
