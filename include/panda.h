@@ -161,6 +161,24 @@ size_t panda_pearson_workspace_bytes(int64_t G, int64_t S);
 panda_status panda_pearson(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
                            int64_t ldc, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* The same prior without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit for bit) as
+ * panda_pearson; its scratch is an array of PANDA_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that the library holds in the memory of every GPU it runs on
+ * until the process ends, found once per device on the first call there.
+ * The call itself allocates nothing and does not synchronise.  Sizes whose
+ * panda_pearson_workspace_bytes(G, S) exceeds PANDA_NOALLOC_SCRATCH_BYTES
+ * (for example G = 30000 genes with S up to about 550 samples fit) return
+ * PANDA_ERR_ARG with the sizes in panda_last_error() and enqueue nothing.
+ * The stream must belong to the current device.  All calls on one GPU share
+ * its array: calls that overlap in time on one GPU (different streams, or
+ * threads without ordering) race and must not be made; calls ordered on one
+ * stream are safe, since every byte of scratch a call reads it writes first. */
+#define PANDA_NOALLOC_SCRATCH_BYTES (64u << 20)
+panda_status panda_pearson_noalloc(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
+                                   int64_t ldc, hipStream_t stream);
+
 /* Workspace for a context or panda_run on an N_e x N_a problem. */
 size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt);
 

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -512,19 +513,74 @@ size_t panda_pearson_workspace_bytes(int64_t G, int64_t S) {
   return pearson_layout(G, S, nullptr, nullptr);
 }
 
-panda_status panda_pearson(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
-                           int64_t ldc, void* workspace, size_t ws_bytes, hipStream_t s) {
-  if (!E || !C || G < 1 || S < 2 || G > (1 << 18) || S > (1 << 20) || lde < S || ldc < G)
-    return fail(PANDA_ERR_ARG, "pearson: bad arguments%s");
-  const size_t need = panda_pearson_workspace_bytes(G, S);
-  if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
-    return fail(PANDA_ERR_WORKSPACE, "pearson: workspace too small or misaligned%s");
+namespace {
+bool pearson_args_ok(const float* E, int64_t G, int64_t S, int64_t lde, const float* C,
+                     int64_t ldc) {
+  return E && C && G >= 1 && S >= 2 && G <= (1 << 18) && S <= (1 << 20) && lde >= S && ldc >= G;
+}
+
+// The two kernels of the prior on a scratch region laid out by
+// pearson_layout; every byte of it that they read they have written first.
+panda_status pearson_enqueue(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
+                             int64_t ldc, char* base, hipStream_t s) {
   const int64_t Gp = round_up(G, kPadA), Sp = round_up(S, kPadK);
   PearsonLayout L;
-  pearson_layout(G, S, static_cast<char*>(workspace), &L);
+  pearson_layout(G, S, base, &L);
   HIP_TRY(launch_pearson_z(E, G, S, lde, L.stat, L.Zt, Gp, Sp, s));
   HIP_TRY(launch_corr(L.Zt, Gp, Sp, G, C, ldc, s));
   return PANDA_OK;
+}
+
+// Scratch of panda_pearson_noalloc, one copy on every GPU the library runs
+// on, held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device array: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[PANDA_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];
+
+panda_status scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PANDA_ERR_ARG, "pearson_noalloc: device id out of range%s");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(PANDA_ERR_HIP, "pearson_noalloc: no device address for the scratch array%s");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PANDA_OK;
+}
+}  // namespace
+
+panda_status panda_pearson(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
+                           int64_t ldc, void* workspace, size_t ws_bytes, hipStream_t s) {
+  if (!pearson_args_ok(E, G, S, lde, C, ldc)) return fail(PANDA_ERR_ARG, "pearson: bad arguments%s");
+  const size_t need = panda_pearson_workspace_bytes(G, S);
+  if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(PANDA_ERR_WORKSPACE, "pearson: workspace too small or misaligned%s");
+  return pearson_enqueue(E, G, S, lde, C, ldc, static_cast<char*>(workspace), s);
+}
+
+panda_status panda_pearson_noalloc(const float* E, int64_t G, int64_t S, int64_t lde, float* C,
+                                   int64_t ldc, hipStream_t s) {
+  if (!pearson_args_ok(E, G, S, lde, C, ldc))
+    return fail(PANDA_ERR_ARG, "pearson_noalloc: bad arguments%s");
+  const size_t need = panda_pearson_workspace_bytes(G, S);
+  if (need > (size_t)PANDA_NOALLOC_SCRATCH_BYTES) {
+    snprintf(g_err, sizeof g_err,
+             "pearson_noalloc: G = %lld genes x S = %lld samples need %zu bytes of scratch, more "
+             "than the %zu the library holds; use panda_pearson with a workspace",
+             (long long)G, (long long)S, need, (size_t)PANDA_NOALLOC_SCRATCH_BYTES);
+    return PANDA_ERR_ARG;
+  }
+  void* base = nullptr;
+  PANDA_TRY(scratch_address(&base));
+  return pearson_enqueue(E, G, S, lde, C, ldc, static_cast<char*>(base), s);
 }
 
 size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt) {

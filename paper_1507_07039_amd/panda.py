@@ -23,7 +23,8 @@ EXPORTS = (
     "panda_default_options", "panda_normalize_workspace_bytes", "panda_normalize",
     "panda_normalize_ex_workspace_bytes", "panda_normalize_ex",
     "panda_tanimoto_workspace_bytes", "panda_tanimoto",
-    "panda_pearson_workspace_bytes", "panda_pearson", "panda_workspace_bytes",
+    "panda_pearson_workspace_bytes", "panda_pearson", "panda_pearson_noalloc",
+    "panda_workspace_bytes",
     "panda_ctx_create", "panda_ctx_load", "panda_iterate", "panda_ctx_store",
     "panda_ctx_destroy", "panda_run", "panda_ctx_set_timing", "panda_ctx_phase_times",
     "panda_batch_workspace_bytes", "panda_batch_create", "panda_batch_destroy",
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "panda_tanimoto": (ct.c_int, [vp, vp, i64, i64, i64, vp, vp, sz, vp]),
         "panda_pearson_workspace_bytes": (sz, [i64, i64]),
         "panda_pearson": (ct.c_int, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
+        "panda_pearson_noalloc": (ct.c_int, [vp, i64, i64, i64, vp, i64, vp]),
         "panda_workspace_bytes": (sz, [i64, i64, op]),
         "panda_ctx_create": (ct.c_int, [i64, i64, op, vp, sz, vp, ct.POINTER(vp)]),
         "panda_ctx_load": (ct.c_int, [vp, vp, vp, vp, i32]),
@@ -226,6 +228,26 @@ def pearson(E):
     _check(lib.panda_pearson(_dev(E, "E"), G, S, S, out.data_ptr(), G,
                              ws.data_ptr(), ws.numel(), _stream()))
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def pearson_noalloc(E, C=None, ldc: int | None = None):
+    """The same prior through panda_pearson_noalloc (no workspace: the
+    library's per-GPU scratch array).  C (optional, device FP32, G rows of
+    leading dimension ldc) receives the result; columns past G are left
+    alone."""
+    torch = _torch()
+    lib = load_library()
+    G, S = E.shape
+    if C is None:
+        C = torch.empty((G, G), dtype=torch.float32, device="cuda")
+    ldc = C.shape[1] if ldc is None else ldc
+    if C.shape[0] != G or C.shape[1] != ldc or ldc < G:
+        raise ValueError("C must be G x ldc with ldc >= G")
+    _check(lib.panda_pearson_noalloc(_dev(E, "E"), G, S, S, _dev(C, "C"), ldc, _stream()))
+    return C
 
 
 def workspace_bytes(Ne: int, Na: int, opts: Options | None = None) -> int:
