@@ -48,6 +48,9 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
+# options of the library set from the command line (e.g. packed_c), for every form
+LIB_OPTS = {}
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "iteration_T700_G18000_hbm_traffic.md")
 TRACE_FILE = os.path.join(ROOT, "profiles", "iteration_T700_G18000_kernel_trace.md")
 GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "oracle_panda-T700-G18000.json")
@@ -118,7 +121,7 @@ def accuracy_vs_golden(torch, panda, W, P, C, precision: int):
     Ne, Na = W.shape
     if (g["workload"]["T"], g["workload"]["G"]) != (Ne, Na):
         return None
-    ctx = panda.Context(Ne, Na, panda.default_options(tol=0.0, precision=precision))
+    ctx = panda.Context(Ne, Na, panda.default_options(tol=0.0, precision=precision, **LIB_OPTS))
     ctx.load(W, P, C)
     iw = g["idx"]["W"]
     rows = torch.as_tensor(iw[0], device="cuda")
@@ -152,7 +155,7 @@ def gpu_inputs(w: I.Workload, torch, panda):
 def time_iterations(torch, panda, W, P, C, steps: int, warmup: int, precision: int = 0):
     Ne, Na = W.shape
     # tol = 0: no iteration inside the timing is skipped by convergence
-    opts = panda.default_options(tol=0.0, max_iter=1 << 30, precision=precision)
+    opts = panda.default_options(tol=0.0, max_iter=1 << 30, precision=precision, **LIB_OPTS)
     ctx = panda.Context(Ne, Na, opts)
     ctx.load(W, P, C)
     for _ in range(warmup):
@@ -174,7 +177,7 @@ def time_iterations(torch, panda, W, P, C, steps: int, warmup: int, precision: i
 
 def time_to_converge(torch, panda, W, P, C, runs: int, precision: int = 0):
     Ne, Na = W.shape
-    opts = panda.default_options(precision=precision)
+    opts = panda.default_options(precision=precision, **LIB_OPTS)
     ws = panda.workspace(panda.workspace_bytes(Ne, Na, opts))
     out = (torch.empty_like(W), torch.empty_like(P), torch.empty_like(C))
     times, res = [], None
@@ -291,9 +294,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy, a read-only sum and a fill of this many MiB "
                          "(counter calibration)")
+    ap.add_argument("--packed-c", type=int, default=None, choices=[0, 1],
+                    help="store C as its upper tiles (both forms); default: the library's")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the comparison with the stored oracle run")
     args = ap.parse_args()
+    if args.packed_c is not None:
+        LIB_OPTS["packed_c"] = args.packed_c
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
               "described in the design notes but not built", file=sys.stderr)

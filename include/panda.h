@@ -102,6 +102,13 @@ typedef struct {
                                   1: by n - 1 (sample)                           */
   int32_t zscore_mode;  /* [PANDA_ZSCORE_GLOBAL] scope of the z-score that the
                                   library applies itself (identity defaults)     */
+  int32_t packed_c;     /* [0]    1: a context stores C as its upper 128 x 128 tiles
+                                  only (C is symmetric, and Eq. 5 keeps it so):
+                                  about half the workspace of C, no mirror writes
+                                  in the C update; the A product reads each
+                                  stored tile for both triangles.  Results are the
+                                  same as with 0.  Contexts and panda_run only (a
+                                  batch stores C whole); panda_ws_features needs 0 */
 } panda_options;
 
 typedef struct panda_ctx panda_ctx;

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpanda.so")
-SOURCES = ["panda_api.hip", "batch_api.hip", "warm_api.hip", "tanimoto_gemm.hip",
+SOURCES = ["panda_api.hip", "batch_api.hip", "warm_api.hip", "tanimoto_gemm.hip", "packed.hip",
            "update_kernels.hip", "batched.hip", "warmstart.hip", "null.hip"]
 
 # Packed FP32 instructions are switched off for all device code; hipcc's host

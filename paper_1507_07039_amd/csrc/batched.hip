@@ -154,7 +154,7 @@ struct PhCoreg {
       g.run(OpsB3{d.Wth, d.Wtl, d.Nep, d.Wth, d.Wtl, d.Nep}, I * kCB, J * kCB, 0, d.Nep, smem);
     else
       g.run(OpsF32{W, d.Nap, W, d.Nap}, I * kCB, J * kCB, 0, d.Nep, smem);
-    coreg_epilogue<SIGT>(g, smem, I, J, d.C, d.Nap, d.Na, nval, alpha, d.cstat, d.csq, d.Nap);
+    coreg_epilogue<SIGT, false>(g, smem, I, J, d.C, d.Nap, d.Na, nval, alpha, d.cstat, d.csq, d.Nap);
   }
 };
 

@@ -91,6 +91,7 @@ struct EpiWUpdate {
 // Tile configurations.  Rectangular products: 64 x 128 tiles (N_e = 700 pads
 // to 704 = 11 x 64), 4 waves side by side.  Symmetric C product: 128 x 128.
 using RectF32 = BlockGemm<64, 128, 1, 4, true, false, 16>;
+using RectF32P = BlockGemm<64, 128, 1, 4, true, false, 16, true>;  // A product, packed C
 using RectB3 = BlockGemmB3<64, 128, 1, 4>;  // R: K = N_e is short, register staging wins
 static_assert(RectF32::BM == RectB3::BM && RectF32::BN == RectB3::BN, "one tile grid");
 // The split-BF16 A product moves its operands by direct loads into LDS, and
@@ -100,6 +101,7 @@ static_assert(RectF32::BM == RectB3::BM && RectF32::BN == RectB3::BN, "one tile 
 // spanning all of N_e with a 64-gene strip of C reads C once but re-reads
 // W's planes per block: 2.6 ms against 1.46 ms.)
 using RectB3D = BlockGemmB3P<256, 128, 4, 1>;
+using RectB3DP = BlockGemmB3P<256, 128, 4, 1, true, 3, 32, true>;  // the same on packed C
 using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
 using SymB3 = BlockGemmB3P<128, 128, 2, 2, false, 2>;  // direct-to-LDS, two stages (two blocks per CU)
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;
@@ -118,7 +120,11 @@ static_assert(CoopF32::BK == CoopB3::BK, "one K split");
 // squares of the updated entries (for |C_.j|^2) go to csq.  With shadows
 // (split-BF16 form) the hi/lo planes of the new entries are written too; the
 // diagonal of the planes stays zero.
+// With PK, C is packed (packed_tile): the tile is read and written in its own
+// slot, row length kPT, and an off-diagonal tile has no mirror image to
+// write; a diagonal tile gets its lower triangle as well.
 constexpr int kCB = 128;
+static_assert(kCB == kPT, "C-update tiles are the packed tiles");
 constexpr int kSymLD = kCB + 1;
 
 // Fresh similarity of one C-tile entry from its product and the squared
@@ -148,13 +154,17 @@ __device__ __forceinline__ double coreg_norm_load(const double* __restrict__ nco
 constexpr int kC4 = kCB / 4;                     // float4 per tile row
 constexpr int kChunks = kCB * kC4 / kThreads;    // float4 per thread
 
-template <bool SIGT, class FV>
+template <bool SIGT, bool PK, class FV>
 __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I, int64_t J,
                                                   float* __restrict__ C, int64_t ldc, int64_t Na,
                                                   double alpha, double2* __restrict__ cstat,
                                                   double* __restrict__ csq, int64_t ldstat) {
   static_assert(kChunks * kThreads == kCB * kC4, "whole chunks");
   const int64_t m0 = I * kCB, n0 = J * kCB;
+  // address of entry (rr, c) of the tile: in C, or in the tile's packed slot
+  float* const Ct = PK ? C + packed_tile(I, J) * (kCB * kCB) : C;
+  const int64_t ldt = PK ? kCB : ldc;
+  const int64_t r0 = PK ? 0 : m0, c0 = PK ? 0 : n0;
   float* ts = reinterpret_cast<float*>(smem);  // fresh T, then the updated values
   float* tt = ts + kCB * kSymLD;               // fresh T (SIGT only)
   const int t = threadIdx.x;
@@ -171,7 +181,7 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
   for (int k = 0; k < kChunks; ++k) {  // all old values in flight together
     const int id = t + k * kThreads, rr = id / kC4, c = (id % kC4) * 4;
     old[k] = __builtin_nontemporal_load(
-        reinterpret_cast<const f4*>(C + (m0 + rr) * ldc + n0 + c));
+        reinterpret_cast<const f4*>(Ct + (r0 + rr) * ldt + c0 + c));
   }
 #pragma unroll
   for (int k = 0; k < kChunks; ++k) {
@@ -186,7 +196,7 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
       nv[e] = upper[e] ? v : old[k][e];
       ts[rr * kSymLD + c + e] = v;
     }
-    float* dst = C + gr * ldc + gc;
+    float* dst = Ct + (r0 + rr) * ldt + c0 + c;
     if (I != J) {
       // every entry of an upper off-diagonal tile is strictly upper; padding
       // columns keep their zeros
@@ -198,16 +208,18 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
     }
   }
   __syncthreads();
-  // mirror: C[n0 + q][m0 + p] = ts[p][q] for the strictly-upper entries
+  // mirror: C[n0 + q][m0 + p] = ts[p][q] for the strictly-upper entries (a
+  // packed off-diagonal tile has no mirror image to write)
 #pragma unroll 4
   for (int k = 0; k < kChunks; ++k) {
+    if (PK && I != J) break;
     const int id = t + k * kThreads, q = id / kC4, p = (id % kC4) * 4;
     const int64_t gj = n0 + q, gi = m0 + p;
     if (gj >= Na) continue;
     f4 v;
 #pragma unroll
     for (int e = 0; e < 4; ++e) v[e] = ts[(p + e) * kSymLD + q];
-    float* dst = C + gj * ldc + gi;
+    float* dst = PK ? Ct + q * ldt + p : C + gj * ldc + gi;
     if (gi + 3 < gj) {
       __builtin_nontemporal_store(v, reinterpret_cast<f4*>(dst));
     } else {
@@ -267,7 +279,7 @@ template <bool SIGT>
 constexpr int coreg_tile_bytes() {
   return kCB * kSymLD * 4 * (SIGT ? 2 : 1);
 }
-template <bool SIGT, class G>
+template <bool SIGT, bool PK, class G>
 __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I, int64_t J,
                                                float* __restrict__ C, int64_t ldc, int64_t Na,
                                                double nval, double alpha,
@@ -278,7 +290,7 @@ __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I
   double* nsh = reinterpret_cast<double*>(smem + coreg_tile_bytes<SIGT>());
   nsh[threadIdx.x] = nval;
   __syncthreads();
-  coreg_tile_update<SIGT>(
+  coreg_tile_update<SIGT, PK>(
       [&](auto&& f) {
 #pragma unroll
         for (int i = 0; i < G::TM; ++i)

@@ -151,13 +151,82 @@ struct OpsF32 {
   const float* Y;
   int64_t ldy;
 };
+// The same with Y a packed symmetric matrix (packed_tile).
+struct OpsF32P {
+  const float* X;
+  int64_t ldx;
+  const float* Yp;
+};
+
+// Y tile (MN = kPT columns, BK rows) of a product whose Y is a packed
+// symmetric matrix: element (k, n) = Y[k][n], n in column block J = n0 / kPT.
+// For k in block Kb <= J, tile (Kb, J) holds it at row k, column n (n
+// contiguous, TileLoad<MN, false>'s pattern); for Kb > J, tile (J, Kb) holds
+// it at row n, column k (k contiguous, TileLoad<MN, true>'s pattern).  A
+// K-tile lies inside one block (BK divides kPT), so the orientation is chosen
+// per K-tile, the same for the whole block; both fill the same [k][mn] LDS
+// layout.
+template <int MN, int BK>
+struct TileLoadPY {
+  using LN = TileLoad<MN, false, BK>;
+  using LT = TileLoad<MN, true, BK>;
+  static_assert(MN == kPT && kPT % BK == 0, "one packed column block per tile");
+  static_assert(LN::LD == LT::LD && LN::NV == LT::NV, "one LDS layout for both orientations");
+  static constexpr int LD = LN::LD;
+  static constexpr int NV = LN::NV;
+  f4 v[NV];
+  bool tr;
+
+  __device__ __forceinline__ void load(const float* __restrict__ Yp, int64_t n0, int64_t k0, int t) {
+    const int64_t J = n0 / kPT, Kb = k0 / kPT, kk = k0 % kPT;
+    tr = Kb > J;
+    if (!tr) {
+      const float* base = Yp + packed_tile(Kb, J) * (kPT * kPT) + kk * kPT;
+      const int mnq = (t % LN::TPR) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int k = t / LN::TPR + i * LN::RPP;
+        v[i] = *reinterpret_cast<const f4*>(base + k * kPT + mnq);
+      }
+    } else {
+      const float* base = Yp + packed_tile(J, Kb) * (kPT * kPT) + kk;
+      const int kq = (t % LT::KQ) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int mn = t / LT::KQ + i * LT::RP;
+        v[i] = *reinterpret_cast<const f4*>(base + mn * kPT + kq);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(float* lds, int t) const {
+    if (!tr) {
+      const int mnq = (t % LN::TPR) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int k = t / LN::TPR + i * LN::RPP;
+        *reinterpret_cast<f4*>(lds + k * LD + mnq) = v[i];
+      }
+    } else {
+      const int kq = (t % LT::KQ) * 4;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int mn = t / LT::KQ + i * LT::RP;
+        lds[(kq + 0) * LD + mn] = v[i].x;
+        lds[(kq + 1) * LD + mn] = v[i].y;
+        lds[(kq + 2) * LD + mn] = v[i].z;
+        lds[(kq + 3) * LD + mn] = v[i].w;
+      }
+    }
+  }
+};
 
 // Block-level FP32 GEMM over k in [kbeg, kend) for a BM x BN tile with WM x WN
 // waves; each wave owns a (BM/WM) x (BN/WN) sub-tile of 32 x 32 MFMA blocks
-// (v_mfma_f32_32x32x2f32).
-template <int BM_, int BN_, int WM, int WN, bool XK, bool YK, int BK_>
+// (v_mfma_f32_32x32x2f32).  YP: Y is a packed symmetric matrix (OpsF32P).
+template <int BM_, int BN_, int WM, int WN, bool XK, bool YK, int BK_, bool YP = false>
 struct BlockGemm {
-  using Ops = OpsF32;
+  using Ops = typename std::conditional<YP, OpsF32P, OpsF32>::type;
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = kThreads;
   static constexpr int WAVES_PER_EU = 1;  // occupancy asked of the compiler (1: no request)
   static_assert(WM * WN == 4, "four waves per block");
@@ -165,7 +234,14 @@ struct BlockGemm {
   static constexpr int TN = BN / WN / 32;
   static_assert(TM >= 1 && TN >= 1, "wave tile below one MFMA block");
   using LX = TileLoad<BM, XK, BK>;
-  using LY = TileLoad<BN, YK, BK>;
+  using LY = typename std::conditional<YP, TileLoadPY<BN, BK>, TileLoad<BN, YK, BK>>::type;
+  __device__ __forceinline__ static void load_y(LY& ly, const Ops& o, int64_t n0, int64_t k0,
+                                                int t) {
+    if constexpr (YP)
+      ly.load(o.Yp, n0, k0, t);
+    else
+      ly.load(o.Y, o.ldy, n0, k0, t);
+  }
   static constexpr int XS = BK * LX::LD;
   static constexpr int YS = BK * LY::LD;
   static constexpr int MAIN_BYTES = 2 * (XS + YS) * 4;
@@ -194,7 +270,7 @@ struct BlockGemm {
     const int64_t nk = (kend - kbeg) / BK;
     if (nk > 0) {
       lx.load(o.X, o.ldx, m0, kbeg, t);
-      ly.load(o.Y, o.ldy, n0, kbeg, t);
+      load_y(ly, o, n0, kbeg, t);
       lx.store(xs, t);
       ly.store(ys, t);
     }
@@ -207,7 +283,7 @@ struct BlockGemm {
       const bool more = kt + 1 < nk;
       if (more) {
         lx.load(o.X, o.ldx, m0, kbeg + (kt + 1) * BK, t);
-        ly.load(o.Y, o.ldy, n0, kbeg + (kt + 1) * BK, t);
+        load_y(ly, o, n0, kbeg + (kt + 1) * BK, t);
       }
       const float* xc = xs + cur * XS;
       const float* yc = ys + cur * YS;
@@ -280,6 +356,14 @@ struct OpsB3F {
   const float* Y;
   int64_t ldy;
   int64_t mrows = INT64_MAX;  // rows of X that exist (loaders may clamp to them)
+};
+// ... with Y stored packed (packed_tile).
+struct OpsB3FP {
+  const bf16_t* Xh;
+  const bf16_t* Xl;
+  int64_t ldx;
+  const float* Yp;
+  int64_t mrows = INT64_MAX;
 };
 
 // MN x BK tile of one K-contiguous operand, both planes, loaded by NT
@@ -508,9 +592,21 @@ __device__ __forceinline__ void split_pair(float a, float b, unsigned& h, unsign
 // YF32: Y is the FP32 symmetric matrix split as its fragments are read;
 // otherwise Y is given as bf16 hi/lo planes like X (no split arithmetic).
 // The STAGES stage buffers are carved from the caller's shared memory.
-template <int BM_, int BN_, int WM, int WN, bool YF32 = true, int STAGES = 3, int BK_ = 32>
+// YP: Y (FP32) is stored packed (packed_tile).  The product needs row n of Y
+// over the K-tile's k (Y symmetric: row n is column n).  Where the tile of
+// (n, k) lies above the diagonal it holds that row directly; below it, the
+// tile of (k, n) holds it as a column, so such a K-tile is loaded as it is
+// stored, [k][n] rows of kPT floats, and its fragments are read with one
+// 4-byte read per k.  Both rows of a fragment read's two half-waves differ
+// by 8 in k, and their 16-byte chunks are XOR-swizzled by that bit, so the
+// two half-waves use different banks.
+template <int BM_, int BN_, int WM, int WN, bool YF32 = true, int STAGES = 3, int BK_ = 32,
+          bool YP = false>
 struct BlockGemmB3P {
-  using Ops = typename std::conditional<YF32, OpsB3F, OpsB3>::type;
+  using Ops = typename std::conditional<
+      YP, OpsB3FP, typename std::conditional<YF32, OpsB3F, OpsB3>::type>::type;
+  static_assert(!YP || (YF32 && BN_ == (int)kPT && kPT % BK_ == 0 && BK_ == 32),
+                "packed Y: FP32 rows of one packed column block, K-tiles inside a block");
   // one block per CU and the accumulators in AGPRs: the epilogue has the
   // VGPRs to fetch its per-entry operands 16 at a time (see epi_tile)
   static constexpr bool kPrefetchEpi = true;
@@ -563,7 +659,17 @@ struct BlockGemmB3P {
     const char* yl;
     unsigned voff[IPW];  // per lane
     unsigned wofs;       // this wave's LDS offset within a stage
+    // packed Y: its base, the column block, the range start, and the per-lane
+    // offsets of the K-tiles loaded as stored ([k][n])
+    const char* yp;
+    int64_t jb, kbeg;
+    unsigned voffT[IPW];
   };
+  // packed Y: whether K-tile kt of a range starting at kbeg is read as stored
+  __device__ __forceinline__ static bool tr_at(const Dma& d, int kt) {
+    if constexpr (!YP) return false;
+    return d.jb > (d.kbeg + (int64_t)kt * BK) / kPT;
+  }
   static constexpr int YSTEP = YF32 ? BK * 4 : BK * 2;  // bytes per K-tile along a Y row
 
   __device__ __forceinline__ static unsigned lds_addr(const void* p) {
@@ -574,7 +680,9 @@ struct BlockGemmB3P {
                                         Dma& d) const {
     d.xh = reinterpret_cast<const char*>(o.Xh + m0 * o.ldx + kbeg);
     d.xl = reinterpret_cast<const char*>(o.Xl + m0 * o.ldx + kbeg);
-    if constexpr (YF32) {
+    if constexpr (YP) {
+      d.yh = d.yl = nullptr;  // per K-tile, from the packed tile (dma_at)
+    } else if constexpr (YF32) {
       d.yh = reinterpret_cast<const char*>(o.Y + n0 * o.ldy + kbeg);
       d.yl = d.yh;
     } else {
@@ -582,6 +690,11 @@ struct BlockGemmB3P {
       d.yl = reinterpret_cast<const char*>(o.Yl + n0 * o.ldy + kbeg);
     }
     d.wofs = (unsigned)w * 1024u;
+    if constexpr (YP) {
+      d.yp = reinterpret_cast<const char*>(o.Yp);
+      d.jb = n0 / kPT;
+      d.kbeg = kbeg;
+    }
 #pragma unroll
     for (int q = 0; q < IPW; ++q) {
       if (q < XPW) {
@@ -592,6 +705,15 @@ struct BlockGemmB3P {
         // row; their outputs are never stored
         const int64_t rr = (m0 + r < o.mrows ? m0 + r : o.mrows - 1) - m0;
         d.voff[q] = (unsigned)((rr * o.ldx + chunk * 8) * 2);
+      } else if constexpr (YP) {
+        const int p = ((q - XPW) * WAVES + w) * 64 + lane;
+        const int r = p / (BK / 4), slot = p % (BK / 4);
+        const int chunk = slot ^ yswz(r);
+        d.voff[q] = (unsigned)(((int64_t)r * kPT + chunk * 4) * 4);  // rows of a packed tile
+        // as stored: row kr of kPT floats (32 chunks), chunk c in slot c ^ 8 (kr / 8 % 2)
+        const int kr = p / (int)(kPT / 4), s2 = p % (int)(kPT / 4);
+        const int c2 = s2 ^ (((kr >> 3) & 1) << 3);
+        d.voffT[q] = (unsigned)((kr * kPT + c2 * 4) * 4);
       } else if constexpr (YF32) {
         const int p = ((q - XPW) * WAVES + w) * 64 + lane;
         const int r = p / (BK / 4), slot = p % (BK / 4);
@@ -610,19 +732,60 @@ struct BlockGemmB3P {
   // part of it).
   __device__ __forceinline__ static void dma_at(const Dma& d, int q, int kt, unsigned sb) {
     const char* b;
-    if (q < XPP)
+    unsigned vo = d.voff[q];
+    if (q < XPP) {
       b = d.xh + (size_t)kt * (BK * 2);
-    else if (q < XPW)
+    } else if (q < XPW) {
       b = d.xl + (size_t)kt * (BK * 2);
-    else if (YF32 || q < XPW + YPP)
+    } else if constexpr (YP) {
+      const int64_t k = d.kbeg + (int64_t)kt * BK, kb = k / kPT, kk = k % kPT;
+      if (d.jb > kb) {  // tile (kb, jb): rows k, read as stored
+        b = d.yp + (size_t)(packed_tile(kb, d.jb) * (kPT * kPT) + kk * kPT) * 4;
+        vo = d.voffT[q];
+      } else {          // tile (jb, kb): rows n, columns kk ..
+        b = d.yp + (size_t)(packed_tile(d.jb, kb) * (kPT * kPT) + kk) * 4;
+      }
+    } else if (YF32 || q < XPW + YPP) {
       b = d.yh + (size_t)kt * YSTEP;
-    else
+    } else {
       b = d.yl + (size_t)kt * YSTEP;
-    lds_dma16(d.voff[q], b, sb + d.wofs + (unsigned)(q * WAVES) * 1024u);
+    }
+    lds_dma16(vo, b, sb + d.wofs + (unsigned)(q * WAVES) * 1024u);
   }
   __device__ __forceinline__ static void issue(const Dma& d, int kt, const char* st) {
 #pragma unroll
     for (int q = 0; q < IPW; ++q) dma_at(d, q, kt, lds_addr(st));
+  }
+
+  // Packed Y read as stored: byte offset (within a stage) of this lane's
+  // column n of fragment j, at the first of its 8 k (the rest at + kPT * 4 per k).
+  __device__ __forceinline__ void read_offsets_t(unsigned (&adT)[TN]) const {
+    const int khalf = lane >> 5;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = wn * (BN / WN) + j * 32 + (lane & 31);
+      adT[j] = 2u * XQ * 16 + (unsigned)(8 * khalf) * (unsigned)(kPT * 4) +
+               (((unsigned)(n >> 2) ^ (unsigned)(8 * khalf)) << 4) + 4u * (n & 3);
+    }
+  }
+  // Read r of a K-tile's fragment reads: X and row-stored Y reads are 16
+  // bytes at ad[r]; a packed Y K-tile read as stored takes four 4-byte reads
+  // of consecutive k.
+  template <bool TR>
+  __device__ __forceinline__ static u4 read_r(const char* st, const unsigned (&ad)[NR],
+                                              const unsigned (&adT)[TN], int r) {
+    if constexpr (TR) {
+      const int ks = r / PER, q = r % PER;
+      if (q >= 2 * TM) {
+        const int j = (q - 2 * TM) / 2, h = (q - 2 * TM) % 2;
+        const char* b = st + adT[j] + (unsigned)((16 * ks + 4 * h) * kPT * 4);
+        return (u4){*reinterpret_cast<const unsigned*>(b),
+                    *reinterpret_cast<const unsigned*>(b + kPT * 4),
+                    *reinterpret_cast<const unsigned*>(b + 2 * kPT * 4),
+                    *reinterpret_cast<const unsigned*>(b + 3 * kPT * 4)};
+      }
+    }
+    return *reinterpret_cast<const u4*>(st + ad[r]);
   }
 
   // Byte offsets (within a stage) of this lane's fragment reads.
@@ -656,9 +819,11 @@ struct BlockGemmB3P {
     }
   }
 
-  __device__ __forceinline__ static void read(const char* st, const unsigned (&ad)[NR], Raw& rw) {
+  template <bool TR>
+  __device__ __forceinline__ static void read(const char* st, const unsigned (&ad)[NR],
+                                              const unsigned (&adT)[TN], Raw& rw) {
 #pragma unroll
-    for (int i = 0; i < NR; ++i) rw.r[i] = *reinterpret_cast<const u4*>(st + ad[i]);
+    for (int i = 0; i < NR; ++i) rw.r[i] = read_r<TR>(st, ad, adT, i);
   }
 
   // Split pair sp of the next tile's FP32 Y fragments (4 pairs per fragment).
@@ -738,8 +903,10 @@ struct BlockGemmB3P {
   // loads of tile kt + STAGES and the LDS reads of tile kt + 1, then the
   // split of tile kt + 1's C fragments.  Scheduling barriers keep this order
   // (the matrix core runs each MFMA while the wave issues what follows it).
-  __device__ __forceinline__ void full_step(const Dma& d, const unsigned (&ad)[NR], int kt,
-                                            const char* rd, const char* fr, Frag& cur) {
+  template <bool TR>
+  __device__ __forceinline__ void full_step(const Dma& d, const unsigned (&ad)[NR],
+                                            const unsigned (&adT)[TN], int kt, const char* rd,
+                                            const char* fr, Frag& cur) {
     constexpr int NM = KS * TM * TN * 3;  // MFMAs per K-tile
     constexpr int NRM = (NR + 1) / 2;     // MFMAs followed by reads
     static_assert(IPW <= NM, "one direct load per MFMA slot at most");
@@ -755,8 +922,7 @@ struct BlockGemmB3P {
       if (m < IPW) dma_at(d, m, kt + STAGES, sb);
       if (m < NRM) {
 #pragma unroll
-        for (int r = 2 * m; r < 2 * m + 2 && r < NR; ++r)
-          rw.r[r] = *reinterpret_cast<const u4*>(rd + ad[r]);
+        for (int r = 2 * m; r < 2 * m + 2 && r < NR; ++r) rw.r[r] = read_r<TR>(rd, ad, adT, r);
       } else if (m - NRM < NSP) {
         split_at(rw, h, l, m - NRM);
       }
@@ -767,15 +933,25 @@ struct BlockGemmB3P {
     assemble(rw, h, l, cur);
   }
 
+  // Packed Y: K-tiles [0, ksplit) of the range lie below the diagonal.
+  __device__ __forceinline__ static int ksplit_of(const Dma& d, int nk) {
+    const int64_t ks = (d.jb * kPT - d.kbeg + BK - 1) / BK;
+    return ks <= 0 ? 0 : ks >= nk ? nk : (int)ks;
+  }
+
   // Any K-tile (near the end of the range): the same with bounds.
-  __device__ __forceinline__ void tail_step(const Dma& d, const unsigned (&ad)[NR], int kt, int nk,
+  __device__ __forceinline__ void tail_step(const Dma& d, const unsigned (&ad)[NR],
+                                            const unsigned (&adT)[TN], int kt, int nk,
                                             const char* rd, const char* fr, Frag& cur) {
     if (kt + 1 < nk) {
       if (STAGES == 3 && kt + 2 < nk) wait_vmem<IPW>(); else wait_vmem<0>();
       wave_barrier_mem();
       if (kt + STAGES < nk) issue(d, kt + STAGES, fr);
       Raw rw;
-      read(rd, ad, rw);
+      if (tr_at(d, kt + 1))
+        read<true>(rd, ad, adT, rw);
+      else
+        read<false>(rd, ad, adT, rw);
       mfma(cur);
       split(rw, cur);
     } else {
@@ -808,6 +984,8 @@ struct BlockGemmB3P {
     setup(o, m0, n0, kbeg, w, d);
     unsigned ad[NR];
     read_offsets(ad);
+    unsigned adT[TN];
+    if constexpr (YP) read_offsets_t(adT);
     issue(d, 0, s0);
     if (nk > 1) {
       issue(d, 1, s1);
@@ -832,30 +1010,44 @@ struct BlockGemmB3P {
     Frag cur;
     {
       Raw rw;
-      read(s0, ad, rw);
+      if (tr_at(d, 0))
+        read<true>(s0, ad, adT, rw);
+      else
+        read<false>(s0, ad, adT, rw);
       split(rw, cur);
     }
     int kt = 0;
     if constexpr (STAGES == 3) {
+      // Packed Y: the K-tiles below the diagonal (k < jb kPT, read as stored)
+      // come first, then the others; each run of one orientation gets its own
+      // loop (a choice between the two inside one loop costs the register
+      // allocator hundreds of spilled registers).  Reads of tile kt + 1.
+      const int ksplit = YP ? ksplit_of(d, nk) : 0;
+      auto stg = [&](int k) { const int m = k % 3; return m == 0 ? s0 : m == 1 ? s1 : s2; };
+      for (; kt + 5 < nk && kt + 3 < ksplit; kt += 3) {
+        full_step<true>(d, ad, adT, kt, s1, s0, cur);
+        full_step<true>(d, ad, adT, kt + 1, s2, s1, cur);
+        full_step<true>(d, ad, adT, kt + 2, s0, s2, cur);
+      }
+      for (; kt + 5 < nk && kt + 1 < ksplit; ++kt)
+        full_step<true>(d, ad, adT, kt, stg(kt + 1), stg(kt), cur);
+      for (; kt + 5 < nk && kt % 3 != 0; ++kt)
+        full_step<false>(d, ad, adT, kt, stg(kt + 1), stg(kt), cur);
       for (; kt + 5 < nk; kt += 3) {
-        full_step(d, ad, kt, s1, s0, cur);
-        full_step(d, ad, kt + 1, s2, s1, cur);
-        full_step(d, ad, kt + 2, s0, s2, cur);
+        full_step<false>(d, ad, adT, kt, s1, s0, cur);
+        full_step<false>(d, ad, adT, kt + 1, s2, s1, cur);
+        full_step<false>(d, ad, adT, kt + 2, s0, s2, cur);
       }
-      for (; kt < nk; ++kt) {
-        const int ph = kt % 3;
-        const char* rd = ph == 0 ? s1 : ph == 1 ? s2 : s0;
-        const char* fr = ph == 0 ? s0 : ph == 1 ? s1 : s2;
-        tail_step(d, ad, kt, nk, rd, fr, cur);
-      }
+      for (; kt < nk; ++kt) tail_step(d, ad, adT, kt, nk, stg(kt + 1), stg(kt), cur);
     } else {
+      static_assert(!YP, "packed Y takes three stages");
       for (; kt + 3 < nk; kt += 2) {
-        full_step(d, ad, kt, s1, s0, cur);
-        full_step(d, ad, kt + 1, s0, s1, cur);
+        full_step<false>(d, ad, adT, kt, s1, s0, cur);
+        full_step<false>(d, ad, adT, kt + 1, s0, s1, cur);
       }
       for (; kt < nk; ++kt) {
         const bool ph = kt % 2;
-        tail_step(d, ad, kt, nk, ph ? s0 : s1, ph ? s1 : s0, cur);
+        tail_step(d, ad, adT, kt, nk, ph ? s0 : s1, ph ? s1 : s0, cur);
       }
     }
     // the caller may reuse the shared memory once every wave has read its last stage

@@ -47,6 +47,9 @@ constexpr size_t kZsScratch = kZsBlocks + 8;  // doubles
 // scope: the global form's block partials, or 8 flags plus the per-row and
 // per-column moments.
 size_t zscore_scratch_doubles(int64_t rows, int64_t cols, int32_t mode);
+// Diagonal and off-diagonal value of the z-scored identity of order n; false
+// if its standard deviation is 0.
+bool identity_zscore(int64_t n, int32_t mode, int32_t ddof, double* dv, double* ov);
 // Z-score in place (Sec. II-A) with the scope and normaliser of the
 // options; synchronises the stream to read the degeneracy flags.
 panda_status zscore(float* M, int64_t rows, int64_t cols, int64_t ld, int32_t mode, int32_t ddof,
@@ -66,8 +69,9 @@ struct LayoutSpec {
   bool batched;
   int64_t hpart_tiles;  // per-tile h partials of the A + W product
   int64_t ppart_splits; // K splits of the W W^T partial products
+  bool packed_c = false; // C as its upper tiles (packed_tile)
 };
-LayoutSpec single_spec(int64_t Ne, int64_t Na);
+LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c = false);
 
 }  // namespace panda
 
@@ -97,6 +101,7 @@ struct panda_ctx {
   uint32_t* corder;  // launch order of the upper C tiles
   panda::DevState* st;
   bool b3;  // split-BF16 products
+  bool packed;  // C stored as its upper tiles (packed_tile)
   panda::bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl;  // split planes (C stays FP32)
   panda::DevState* host;  // pinned
   int splits;

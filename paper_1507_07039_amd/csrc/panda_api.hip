@@ -51,6 +51,7 @@ panda_status check_options(const panda_options& o) {
   if (o.precision != PANDA_PREC_FP32 && o.precision != PANDA_PREC_BF16X3)
     return fail(PANDA_ERR_ARG, "unknown precision%s");
   if (o.sigma_ddof != 0 && o.sigma_ddof != 1) return fail(PANDA_ERR_ARG, "sigma_ddof must be 0 or 1%s");
+  if (o.packed_c != 0 && o.packed_c != 1) return fail(PANDA_ERR_ARG, "packed_c must be 0 or 1%s");
   if (o.zscore_mode < PANDA_ZSCORE_GLOBAL || o.zscore_mode > PANDA_ZSCORE_ROWCOL)
     return fail(PANDA_ERR_ARG, "unknown zscore_mode%s");
   return PANDA_OK;
@@ -65,9 +66,9 @@ bool dims_ok(int64_t Ne, int64_t Na) {
 
 namespace panda {
 
-LayoutSpec single_spec(int64_t Ne, int64_t Na) {
+LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c) {
   const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
-  return LayoutSpec{false, rect_tiles(Nep, Nap), coop_splits(Nep, Nap)};
+  return LayoutSpec{false, rect_tiles(Nep, Nap), coop_splits(Nep, Nap), packed_c};
 }
 
 // Workspace layout shared by the size queries and the contexts.
@@ -80,7 +81,7 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   float* w1 = cv.take<float>(nw);
   float* r = cv.take<float>(nw);
   float* p = cv.take<float>((size_t)Nep * Nep);
-  float* cc = cv.take<float>((size_t)Nap * Nap);
+  float* cc = cv.take<float>(spec.packed_c ? (size_t)packed_floats(Nap) : (size_t)Nap * Nap);
   float* ts = cv.take<float>((size_t)Nep * Nep);
   const int splits = (int)spec.ppart_splits;
   float* pp = cv.take<float>((size_t)splits * Nep * Nep);
@@ -139,6 +140,7 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
     c->corder = co;
     c->st = st;
     c->b3 = b3;
+    c->packed = spec.packed_c;
     c->Wh = sh[0];
     c->Wl = sh[1];
     c->Wth = sh[2];
@@ -180,6 +182,27 @@ void ctx_free(panda_ctx* c) {
     for (int i = 0; i < kMaxPending; ++i)
       for (int p = 0; p <= PANDA_NPHASE; ++p) (void)hipEventDestroy(c->ev[i][p]);
   c->ev[0][0] = nullptr;
+}
+
+// The z-scored identity of order n (Sec. II-A: an absent prior is the
+// identity, z-scored like any network) in closed form: every row, every
+// column and the whole matrix hold one 1 among zeros, so the result has one
+// value on the diagonal (dv) and one off it (ov).  Mean m = 1/n; sum of
+// squared deviations over n^2 entries n (1 - m)^2 + (n^2 - n) m^2 = n - 1,
+// over a row (1 - m)^2 + (n - 1) m^2; the row + column scope gives
+// (Zr + Zc) / sqrt 2 = sqrt 2 Zr.  False when the std is 0 (n = 1).
+bool identity_zscore(int64_t n, int32_t mode, int32_t ddof, double* dv, double* ov) {
+  const double m = 1.0 / (double)n, nn = (double)n;
+  const double cnt = mode == PANDA_ZSCORE_GLOBAL ? nn * nn : nn;
+  const double ss = mode == PANDA_ZSCORE_GLOBAL ? nn * (1.0 - m) * (1.0 - m) + (nn * nn - nn) * m * m
+                                                : (1.0 - m) * (1.0 - m) + (nn - 1.0) * m * m;
+  if (cnt - ddof < 1.0) return false;
+  const double sd = sqrt(ss / (cnt - ddof));
+  if (!(sd > 0.0)) return false;
+  const double f = mode == PANDA_ZSCORE_ROWCOL ? sqrt(2.0) : 1.0;
+  *dv = f * (1.0 - m) / sd;
+  *ov = f * (-m) / sd;
+  return true;
 }
 
 size_t zscore_scratch_doubles(int64_t rows, int64_t cols, int32_t mode) {
@@ -274,10 +297,11 @@ panda_status enqueue_iteration(panda_ctx* c) {
   if (c->b3)
     HIP_TRY(launch_avail_wupdate_b3(c->Wh, c->Wl, Wold, c->C, c->dC, c->R, Wnew, c->Nap, c->Nep,
                                     c->Nap, c->Ne, c->Na, c->nWr, c->nC, c->rule, c->hpart,
-                                    c->skpart, active, s));
+                                    c->skpart, active, s, c->packed));
   else
     HIP_TRY(launch_avail_wupdate(Wold, c->C, c->dC, c->R, Wnew, c->Nap, c->Nep, c->Nap, c->Ne,
-                                 c->Na, c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s));
+                                 c->Na, c->nWr, c->nC, c->rule, c->hpart, c->skpart, active, s,
+                                 c->packed));
   PANDA_TRY(mark(c, PANDA_PHASE_H));
   HIP_TRY(launch_finish_h(c->hpart, c->nh, c->Ne * c->Na, c->st, c->rule, s));
   // squared norms (and split planes) of the new W
@@ -299,10 +323,10 @@ panda_status enqueue_iteration(panda_ctx* c) {
   if (c->b3)
     HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Nap,
                                    c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder,
-                                   run_pc, s));
+                                   run_pc, s, c->packed));
   else
     HIP_TRY(launch_coreg_update(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc,
-                                c->rule, c->cstat, c->csq, c->corder, run_pc, s));
+                                c->rule, c->cstat, c->csq, c->corder, run_pc, s, c->packed));
   PANDA_TRY(mark(c, PANDA_PHASE_DIAG));
   // Eq. 6, and |P_i.|^2, |C_.j|^2 for the next iteration
   HIP_TRY(launch_diagonals(c->P, c->Nep, c->dP, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr,
@@ -360,6 +384,7 @@ void panda_default_options(panda_options* o) {
   o->precision = PANDA_PREC_FP32;
   o->sigma_ddof = 0;
   o->zscore_mode = PANDA_ZSCORE_GLOBAL;
+  o->packed_c = 0;
 }
 
 panda_status panda_ctx_set_timing(panda_ctx* c, int32_t enable) {
@@ -586,7 +611,8 @@ panda_status panda_pearson_noalloc(const float* E, int64_t G, int64_t S, int64_t
 size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt) {
   (void)opt;
   if (!dims_ok(Ne, Na)) return 0;
-  return ctx_layout(Ne, Na, opt ? opt->precision : PANDA_PREC_FP32, single_spec(Ne, Na), nullptr,
+  return ctx_layout(Ne, Na, opt ? opt->precision : PANDA_PREC_FP32,
+                    single_spec(Ne, Na, opt && opt->packed_c), nullptr,
                     nullptr);
 }
 
@@ -607,7 +633,8 @@ panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, 
     return fail(PANDA_ERR_WORKSPACE, "ctx_create: workspace too small or misaligned%s");
   panda_ctx* c = new (std::nothrow) panda_ctx();
   if (!c) return fail(PANDA_ERR_ARG, "ctx_create: out of host memory%s");
-  st = ctx_setup(c, Ne, Na, o, single_spec(Ne, Na), static_cast<char*>(workspace), stream);
+  st = ctx_setup(c, Ne, Na, o, single_spec(Ne, Na, o.packed_c != 0), static_cast<char*>(workspace),
+                 stream);
   if (st != PANDA_OK) {
     delete c;
     return st;
@@ -630,7 +657,7 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
   HIP_TRY(hipMemsetAsync(c->W[0], 0, (size_t)Nep * Nap * 4, s));
   HIP_TRY(hipMemsetAsync(c->W[1], 0, (size_t)Nep * Nap * 4, s));
   HIP_TRY(hipMemsetAsync(c->P, 0, (size_t)Nep * Nep * 4, s));
-  HIP_TRY(hipMemsetAsync(c->C, 0, (size_t)Nap * Nap * 4, s));
+  if (!c->packed) HIP_TRY(hipMemsetAsync(c->C, 0, (size_t)Nap * Nap * 4, s));
   HIP_TRY(hipMemsetAsync(c->Tside, 0, (size_t)Nep * Nep * 4, s));
   panda_status st = copy_in(c->W[0], Nap, W, Ne, Na, s);
   if (st != PANDA_OK) return st;
@@ -641,7 +668,17 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
     st = zscore(c->P, Ne, Ne, Nep, c->opt.zscore_mode, c->opt.sigma_ddof, c->zs, s);
   }
   if (st != PANDA_OK) return st;
-  if (C) {
+  if (c->packed) {
+    // the upper tiles of C (every stored entry is written: no clearing)
+    if (C) {
+      HIP_TRY(launch_pack_sym(C, Na, Na, c->C, Nap, s));
+    } else {
+      double dv, ov;
+      if (!identity_zscore(Na, c->opt.zscore_mode, c->opt.sigma_ddof, &dv, &ov))
+        return fail(PANDA_ERR_DEGENERATE, "identity C of order 1 has std 0%s");
+      HIP_TRY(launch_identity_packed(c->C, Na, Nap, dv, ov, s));
+    }
+  } else if (C) {
     st = copy_in(c->C, Nap, C, Na, Na, s);
   } else {
     HIP_TRY(launch_fill_identity(c->C, Na, Nap, s));
@@ -654,10 +691,16 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
   HIP_TRY(hipMemsetAsync(c->nC, 0, (size_t)Nap * 8, s));
   HIP_TRY(hipMemsetAsync(c->nWc, 0, (size_t)Nap * 8, s));
   HIP_TRY(launch_row_sqnorms(c->P, Ne, Ne, Nep, c->nP, nullptr, s));
-  HIP_TRY(launch_col_sqnorms(c->C, Na, Na, Nap, c->nC, c->colscr, nullptr, s));
+  if (c->packed)
+    HIP_TRY(launch_col_sqnorms_packed(c->C, Nap, c->csq, c->nC, s));
+  else
+    HIP_TRY(launch_col_sqnorms(c->C, Na, Na, Nap, c->nC, c->colscr, nullptr, s));
   // the diagonals of P and C move to their FP64 vectors (zero in the matrices)
   HIP_TRY(launch_take_diag(c->P, Ne, Nep, c->dP, s));
-  HIP_TRY(launch_take_diag(c->C, Na, Nap, c->dC, s));
+  if (c->packed)
+    HIP_TRY(launch_take_diag_packed(c->C, Na, c->dC, s));
+  else
+    HIP_TRY(launch_take_diag(c->C, Na, Nap, c->dC, s));
   if (c->b3) {
     // planes of the loaded state; padding and the P/C diagonals stay zero
     const size_t nw = (size_t)Nep * Nap;
@@ -715,8 +758,11 @@ panda_status panda_ctx_store(panda_ctx* c, float* W, float* P, float* C, double*
     HIP_TRY(launch_put_diag(P, c->Ne, c->Ne, c->dP, s));
   }
   if (C) {
-    HIP_TRY(hipMemcpy2DAsync(C, (size_t)c->Na * 4, c->C, (size_t)c->Nap * 4, (size_t)c->Na * 4,
-                             (size_t)c->Na, hipMemcpyDeviceToDevice, s));
+    if (c->packed)
+      HIP_TRY(launch_unpack_sym(c->C, c->Na, c->Nap, C, c->Na, s));
+    else
+      HIP_TRY(hipMemcpy2DAsync(C, (size_t)c->Na * 4, c->C, (size_t)c->Nap * 4, (size_t)c->Na * 4,
+                               (size_t)c->Na, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_put_diag(C, c->Na, c->Na, c->dC, s));
   }
   if (h) *h = c->host->h;

@@ -44,6 +44,20 @@ constexpr int64_t kPadK = 32;            // K of a stand-alone similarity produc
 constexpr int64_t kCoopTile = 64;        // tile side of the W W^T partial products
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Packed-symmetric storage of C (an option of the single-network context):
+// only the upper kPT x kPT tiles (a <= b) of the padded N_a x N_a matrix,
+// tile (a, b) at index b (b + 1) / 2 + a, each tile row-major with its own
+// row length kPT.  An upper tile serves both triangles: C[i][j] for i in
+// block a, j in block b is tile (a, b) entry (i mod kPT, j mod kPT), and
+// C[j][i] is the same entry.  Diagonal tiles hold both of their triangles
+// (they are symmetric), so any row of them can be read directly.
+constexpr int64_t kPT = 128;
+__host__ __device__ inline int64_t packed_tile(int64_t a, int64_t b) { return b * (b + 1) / 2 + a; }
+inline int64_t packed_floats(int64_t Nap) {
+  const int64_t nT = Nap / kPT;
+  return nT * (nT + 1) / 2 * kPT * kPT;
+}
+
 // ------------------------------------------------------------ launchers --
 // Rectangular similarity products (stream-K).  X is Mp x Kp (k contiguous),
 // Y is Kp x Np (n contiguous); Mp % 64 == 0, Np % 128 == 0, Kp % 32 == 0.
@@ -74,7 +88,7 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const double*
                                 const float* R, float* Wnew, int64_t ld, int64_t Nep, int64_t Nap,
                                 int64_t Ne, int64_t Na, const double* nWrow, const double* nC,
                                 Rule rule, double* hpart, float* part, const int32_t* gate,
-                                hipStream_t s);
+                                hipStream_t s, bool packed = false);
 
 // C update (Eq. 5) on the upper tiles of T(W^T, W) with mirror writes and
 // per-row partial sums for the sigma of Eq. 6 (and |C_.j|^2).  order holds
@@ -82,7 +96,7 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const double*
 hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* C, int64_t ldc,
                                int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
                                double2* cstat, double* csq, const uint32_t* order,
-                               const int32_t* gate, hipStream_t s);
+                               const int32_t* gate, hipStream_t s, bool packed = false);
 int64_t coreg_slots(int64_t Nap);
 // Upper tiles of the C product (Nap / 128 per side) and their launch order:
 // group x group super-tiles, so the tiles running together on one XCD share
@@ -113,11 +127,12 @@ hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const flo
                                    int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
                                    const double* nWrow, const double* nC, Rule rule,
                                    double* hpart, float* part, const int32_t* gate,
-                                   hipStream_t s);
+                                   hipStream_t s, bool packed = false);
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
                                   float* C, int64_t ldc, int64_t Nap, int64_t Na,
                                   const double* nWcol, Rule rule, double2* cstat, double* csq,
-                                  const uint32_t* order, const int32_t* gate, hipStream_t s);
+                                  const uint32_t* order, const int32_t* gate, hipStream_t s,
+                                  bool packed = false);
 hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ldw, int64_t Nep,
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s);
@@ -125,6 +140,23 @@ hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ld
 // hi/lo planes of an n x n matrix with its diagonal left zero.
 hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* Mh, bf16_t* Ml,
                                 hipStream_t s);
+
+// Packed C (see packed_tile).  pack: the upper tiles of the n x n symmetric
+// matrix src (leading dimension lds; the upper triangle is read, and
+// mirrored inside diagonal tiles), zero past n.  unpack: the full n x n
+// matrix into dst (leading dimension ldd).  identity: dval on the diagonal,
+// oval off it (within n), zero past n.  take_diag: the diagonal moves to d
+// and reads zero.  col_sqnorms: out[j] = sum_i C[i][j]^2 (j < Nap, FP64),
+// through slots (nT x Nap doubles, nT = Nap / kPT).
+hipError_t launch_pack_sym(const float* src, int64_t n, int64_t lds, float* dst, int64_t Nap,
+                           hipStream_t s);
+hipError_t launch_unpack_sym(const float* src, int64_t n, int64_t Nap, float* dst, int64_t ldd,
+                             hipStream_t s);
+hipError_t launch_identity_packed(float* dst, int64_t n, int64_t Nap, double dval, double oval,
+                                  hipStream_t s);
+hipError_t launch_take_diag_packed(float* C, int64_t n, double* d, hipStream_t s);
+hipError_t launch_col_sqnorms_packed(const float* C, int64_t Nap, double* slots, double* out,
+                                     hipStream_t s);
 
 // Rest of the iteration: h, P finalisation, both diagonals, norm vectors.
 hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevState* st,

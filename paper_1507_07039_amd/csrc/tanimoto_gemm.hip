@@ -20,7 +20,7 @@ using namespace gemm;
 
 // The product of the tile, then the update in its epilogue (two blocks per
 // CU, so one block's epilogue overlaps the other's products).
-template <class G, bool SIGT>
+template <class G, bool SIGT, bool PK>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_coreg_update(
     typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
     const double* __restrict__ ncol, double alpha, double2* __restrict__ cstat,
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const double nval = coreg_norm_load(ncol, I, J, Na);
   G g;
   g.run(ops, m0, n0, 0, Kp, smem);
-  coreg_epilogue<SIGT>(g, smem, I, J, C, ldc, Na, nval, alpha, cstat, csq, ldstat);
+  coreg_epilogue<SIGT, PK>(g, smem, I, J, C, ldc, Na, nval, alpha, cstat, csq, ldstat);
 }
 
 // Pearson correlations: one upper 128 x 128 tile of Z Z^T per block, both
@@ -134,8 +134,10 @@ hipError_t launch_avail_wupdate(const float* Wold, const float* C, const double*
                                 const float* R, float* Wnew, int64_t ld, int64_t Nep, int64_t Nap,
                                 int64_t Ne, int64_t Na, const double* nWrow, const double* nC,
                                 Rule rule, double* hpart, float* part, const int32_t* gate,
-                                hipStream_t s) {
+                                hipStream_t s, bool packed) {
   EpiWUpdate epi{Wold, R, Wnew, ld, Ne, Na, nWrow, nC, dC, rule.alpha, rule.h_undamped, hpart, 0.0};
+  if (packed)
+    return launch_rect<RectF32P>(OpsF32P{Wold, ld, C}, Nep, Nap, Nap, epi, part, gate, s);
   return launch_rect<RectF32>(OpsF32{Wold, ld, C, ld}, Nep, Nap, Nap, epi, part, gate, s);
 }
 
@@ -144,10 +146,12 @@ hipError_t launch_avail_wupdate_b3(const bf16_t* Wh, const bf16_t* Wl, const flo
                                    int64_t ld, int64_t Nep, int64_t Nap, int64_t Ne, int64_t Na,
                                    const double* nWrow, const double* nC, Rule rule,
                                    double* hpart, float* part, const int32_t* gate,
-                                   hipStream_t s) {
+                                   hipStream_t s, bool packed) {
   EpiWUpdate epi{Wold, R, Wnew, ld, Ne, Na, nWrow, nC, dC, rule.alpha, rule.h_undamped, hpart, 0.0};
   // C is symmetric: its row n is the column n the product needs
   const int64_t Mp = (Nep + RectB3D::BM - 1) / RectB3D::BM * RectB3D::BM;
+  if (packed)
+    return launch_rect<RectB3DP>(OpsB3FP{Wh, Wl, ld, C, Nep}, Mp, Nap, Nap, epi, part, gate, s);
   return launch_rect<RectB3D>(OpsB3F{Wh, Wl, ld, C, ld, Nep}, Mp, Nap, Nap, epi, part, gate, s);
 }
 
@@ -164,40 +168,50 @@ void coreg_order_fill(int64_t Nap, int group, uint32_t* out) {
           out[k++] = (uint32_t)(I | (J << 16));
 }
 
+template <class G, bool PK>
+static hipError_t coreg_launch_pk(const typename G::Ops& ops, int64_t Nep, float* C, int64_t ldc,
+                                  int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
+                                  double2* cstat, double* csq, const uint32_t* order,
+                                  const int32_t* gate, hipStream_t s) {
+  const unsigned nb = (unsigned)coreg_tiles(Nap);
+  if (rule.sigma_from_T)
+    k_coreg_update<G, true, PK><<<dim3(nb), dim3(kThreads), 0, s>>>(
+        ops, Nep, C, ldc, Na, nWcol, rule.alpha, cstat, csq, Nap, order, gate);
+  else
+    k_coreg_update<G, false, PK><<<dim3(nb), dim3(kThreads), 0, s>>>(
+        ops, Nep, C, ldc, Na, nWcol, rule.alpha, cstat, csq, Nap, order, gate);
+  return hipGetLastError();
+}
+
 template <class G>
 static hipError_t coreg_launch(const typename G::Ops& ops, int64_t Nep, float* C, int64_t ldc,
                                int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
                                double2* cstat, double* csq, const uint32_t* order,
-                               const int32_t* gate, hipStream_t s) {
-  const unsigned nb = (unsigned)coreg_tiles(Nap);
-  if (rule.sigma_from_T)
-    k_coreg_update<G, true><<<dim3(nb), dim3(kThreads), 0, s>>>(ops, Nep, C, ldc, Na, nWcol,
-                                                                rule.alpha, cstat, csq, Nap, order,
-                                                                gate);
-  else
-    k_coreg_update<G, false><<<dim3(nb), dim3(kThreads), 0, s>>>(ops, Nep, C, ldc, Na, nWcol,
-                                                                 rule.alpha, cstat, csq, Nap, order,
-                                                                 gate);
-  return hipGetLastError();
+                               const int32_t* gate, hipStream_t s, bool packed) {
+  return packed ? coreg_launch_pk<G, true>(ops, Nep, C, ldc, Nap, Na, nWcol, rule, cstat, csq,
+                                           order, gate, s)
+                : coreg_launch_pk<G, false>(ops, Nep, C, ldc, Nap, Na, nWcol, rule, cstat, csq,
+                                            order, gate, s);
 }
 
 hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* C, int64_t ldc,
                                int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
                                double2* cstat, double* csq, const uint32_t* order,
-                               const int32_t* gate, hipStream_t s) {
+                               const int32_t* gate, hipStream_t s, bool packed) {
   // X = W^T (gene m, tf k) = W[k][m]; Y = W (tf k, gene n) = W[k][n].
   return coreg_launch<SymF32>(OpsF32{W, ldw, W, ldw}, Nep, C, ldc, Nap, Na, nWcol, rule, cstat,
-                              csq, order, gate, s);
+                              csq, order, gate, s, packed);
 }
 
 hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nep,
                                   float* C, int64_t ldc, int64_t Nap, int64_t Na,
                                   const double* nWcol, Rule rule, double2* cstat, double* csq,
-                                  const uint32_t* order, const int32_t* gate, hipStream_t s) {
+                                  const uint32_t* order, const int32_t* gate, hipStream_t s,
+                                  bool packed) {
   // X = Yt = W^T stored gene-major: row m of W^T is column m of W.  Only the
   // FP32 C is written; the next A product splits it while staging.
   return coreg_launch<SymB3>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol,
-                             rule, cstat, csq, order, gate, s);
+                             rule, cstat, csq, order, gate, s, packed);
 }
 
 int coop_splits(int64_t Nep, int64_t Nap) {

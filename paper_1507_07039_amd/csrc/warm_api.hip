@@ -64,6 +64,7 @@ panda_status panda_ws_features(panda_ctx* c, const float* omegaP, const float* o
   if (!aligned(workspace) || ws_bytes < feat_layout(Ne, Na, nullptr, nullptr))
     return fail(PANDA_ERR_WORKSPACE, "ws_features: workspace too small or misaligned%s");
   if (!c->skpart) return fail(PANDA_ERR_ARG, "ws_features: context of a batch%s");
+  if (c->packed) return fail(PANDA_ERR_ARG, "ws_features: needs a context with C stored whole (packed_c = 0)%s");
   FeatLayout L;
   feat_layout(Ne, Na, static_cast<char*>(workspace), &L);
   hipStream_t s = c->stream;
@@ -205,10 +206,11 @@ panda_status panda_ws_init(panda_ctx* c, const float* Wpred, int32_t t0) {
                                c->rule.sigma_from_T ? c->Tside : nullptr, c->Ph, c->Pl, run_pc, s));
   if (c->b3)
     HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, Nep, Nep, c->C, Nap, Nap, Na,
-                                   c->nWc, r1, c->cstat, c->csq, c->corder, run_pc, s));
+                                   c->nWc, r1, c->cstat, c->csq, c->corder, run_pc, s,
+                                   c->packed));
   else
     HIP_TRY(launch_coreg_update(W, Nap, Nep, c->C, Nap, Nap, Na, c->nWc, r1, c->cstat, c->csq,
-                                c->corder, run_pc, s));
+                                c->corder, run_pc, s, c->packed));
   // diagonals: t0 steps of Eq. 6 in closed form with sigma of the rebuilt rows
   const double a = c->rule.alpha;
   double g = 0.0;

@@ -61,7 +61,7 @@ class Options(ct.Structure):
                 ("n_own", ct.c_int32), ("h_undamped", ct.c_int32),
                 ("update_last", ct.c_int32), ("poll_every", ct.c_int32),
                 ("precision", ct.c_int32), ("sigma_ddof", ct.c_int32),
-                ("zscore_mode", ct.c_int32)]
+                ("zscore_mode", ct.c_int32), ("packed_c", ct.c_int32)]
 
 
 _lib = None

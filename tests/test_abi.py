@@ -35,11 +35,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_options_struct_layout(lib):
     o = panda.default_options()
-    assert ct.sizeof(panda.Options) == 8 + 8 + 10 * 4
+    assert ct.sizeof(panda.Options) == 8 + 8 + 11 * 4 + 4  # padded to 8 bytes
     assert o.alpha == 0.1 and o.tol == 1e-3 and o.max_iter == 200
     assert (o.diag_alpha, o.sigma_from_T, o.n_own, o.h_undamped, o.update_last) == (1, 0, 0, 0, 0)
     assert o.poll_every == 1 and o.precision == 0
-    assert o.sigma_ddof == 0 and o.zscore_mode == panda.ZSCORE_GLOBAL
+    assert o.sigma_ddof == 0 and o.zscore_mode == panda.ZSCORE_GLOBAL and o.packed_c == 0
 
 
 def test_status_strings(lib):

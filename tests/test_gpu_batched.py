@@ -259,8 +259,16 @@ def test_48_networks_full_size(torch, pd, oracle):
         assert rel <= 1e-3, (i, rel)
         relp = (Wg - Wref).abs().max().item() / max(1.0, Wref.abs().max().item())
         worst_plain = max(worst_plain, (relp, i))
+        # the network's own sensitivity: the plain run from W0 perturbed by
+        # 2^-17 relative (the split's operand truncation), against the plain run
+        g = torch.Generator(device="cuda").manual_seed(1000 + i)
+        xi = torch.rand(dev[i][0].shape, generator=g, device="cuda") * 2 - 1
+        Wpert = (dev[i][0].double() * (1 + 2.0 ** -17 * xi.double())).float()
+        pert = pd.run(Wpert, dev[i][1], dev[i][2])
+        sens = (pert.W - Wref).abs().max().item() / max(1.0, Wref.abs().max().item())
         print(f"    net {i:2d} {shapes[i][:2]}: plain t={itref}, split t={tg}, "
-              f"max|W| {Wref.abs().max().item():.1f}, split vs plain {relp:.2e}")
+              f"max|W| {Wref.abs().max().item():.1f}, split vs plain {relp:.2e}, "
+              f"sensitivity {sens:.2e}, ratio {relp / max(sens, 1e-12):.1f}")
     print(f"  split-BF16 batched run {t_b3:.3f} s ({steps3} steps); worst max|dW|/max|W| "
           f"against the split-BF16 single runs = {worst3:.2e}, against the plain runs = "
           f"{worst_plain[0]:.2e} (network {worst_plain[1]}, {shapes[worst_plain[1]][:2]})")

@@ -151,6 +151,21 @@ def test_trajectory_matches_stored_oracle_run(torch, pd, human):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_packed_c_equals_full_storage_full_size(torch, pd, human, precision):
+    """Converged runs at T=700, G=18000 with C stored packed (its upper tiles)
+    and whole give the same W, P, C and iteration count bit for bit: the
+    products read the same values in the same order."""
+    (W, P, C), _ = human
+    dev = [torch.from_numpy(a).cuda() for a in (W, P, C)]
+    full = pd.run(*dev, opts=pd.default_options(precision=precision))
+    pk = pd.run(*dev, opts=pd.default_options(precision=precision, packed_c=1))
+    assert full.status == pd.OK and pk.status == pd.OK
+    assert full.iters == pk.iters and full.h == pk.h
+    assert torch.equal(full.W, pk.W) and torch.equal(full.P, pk.P) and torch.equal(full.C, pk.C)
+    print(f"precision {precision}: packed and full C equal bit for bit over {pk.iters} iterations")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_runs_repeat_bit_for_bit(torch, pd, human, precision):
     """Two converged runs of the same inputs, in the benchmark's launch
     configuration, give the same W, P, C and iteration count bit for bit (no

@@ -357,3 +357,56 @@ def test_diagonals_past_fp32_range(torch, pd, oracle):
         big = np.abs(dr) > np.finfo(np.float32).max
         assert big.any() and np.all(dg[big] == np.inf)
         assert np.all(np.abs(dg[~big] - dr[~big]) <= 1e-5 * np.abs(dr[~big]))
+
+
+# ------------------------------------------------------- packed C storage --
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_packed_c_runs_like_full_storage(torch, pd, oracle, precision):
+    """C stored as its upper 128 x 128 tiles: the products read the same values
+    in the same order, so every iteration equals the full-storage one bit for
+    bit (W, P, C, h), on the small workload and on ragged shapes that leave
+    partial tiles, and both follow the oracle."""
+    cases = [prep(oracle, *I.workload_priors(I.SMALL))]
+    for Ne, Na in ((1, 7), (3, 1), (65, 300), (70, 257), (9, 129)):
+        rng = np.random.default_rng(Ne * 1000 + Na)
+        cases.append((f32r(rng.normal(size=(Ne, Na))), f32r(I.random_symmetric(Ne + 1, Ne)),
+                      f32r(I.random_symmetric(Na + 2, Na))))
+    for W, P, C in cases:
+        Ne, Na = W.shape
+        ctx = {k: pd.Context(Ne, Na, pd.default_options(precision=precision, packed_c=k, tol=0.0))
+               for k in (0, 1)}
+        for k in (0, 1):
+            ctx[k].load(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+        Wo, Po, Co = W, P, C
+        for t in range(1, 7):
+            h0, _ = ctx[0].iterate()
+            h1, _ = ctx[1].iterate()
+            assert h0 == h1, (W.shape, t)
+            s0, s1 = ctx[0].state(), ctx[1].state()
+            for a, b in zip(s0[:3], s1[:3]):
+                assert torch.equal(a, b), (W.shape, t)
+            if precision == 0:  # the split-BF16 form has its own bounds (test_gpu_precision)
+                Wo, Po, Co, _, _ = oracle.step(Wo, Po, Co, t, oracle.Options(tol=0.0))
+                compare_state(host(s1[0]), host(s1[1]), host(s1[2]), Wo, Po, Co, f"packed t={t}")
+
+
+def test_packed_c_identity_default_and_run(torch, pd, oracle):
+    """The identity default of a packed context (its z-score in closed form)
+    against the oracle's z-scored identity, then panda_run from it."""
+    W0, _, _ = I.workload_priors(I.SMALL)
+    W = f32r(oracle.normalize(W0))
+    Ne, Na = W.shape
+    for mode, ddof in ((0, 0), (2, 1)):
+        opts = pd.default_options(packed_c=1, zscore_mode=mode, sigma_ddof=ddof)
+        ctx = pd.Context(Ne, Na, opts)
+        ctx.load(cuda(torch, W))
+        _, Pg, Cg, _, _ = ctx.state()
+        C = oracle.normalize_ex(np.eye(Na), mode, ddof)
+        assert np.abs(host(Cg) - C).max() <= 2e-7 * np.abs(C).max()
+        P = oracle.normalize_ex(np.eye(Ne), mode, ddof)
+        assert np.abs(host(Pg) - P).max() <= 2e-7 * np.abs(P).max()
+    res = pd.run(cuda(torch, W), None, None, opts=pd.default_options(packed_c=1))
+    ref = oracle.run(W, f32r(oracle.normalize(np.eye(Ne))), f32r(oracle.normalize(np.eye(Na))))
+    assert res.iters == ref.iters
+    compare_state(host(res.W), host(res.P), host(res.C), ref.W, ref.P, ref.C, "packed identity")
