@@ -48,8 +48,14 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
-# options of the library set from the command line (e.g. packed_c), for every form
-LIB_OPTS = {}
+# library options of each form: each runs in the layout that is faster for it
+# (split-BF16 on packed C, plain FP32 on C stored whole; --packed-c sets both)
+PLAIN_OPTS = {"packed_c": 0}
+CHOSEN_OPTS = {"packed_c": 1}
+
+
+def form_opts(precision):
+    return CHOSEN_OPTS if precision else PLAIN_OPTS
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "iteration_T700_G18000_hbm_traffic.md")
 TRACE_FILE = os.path.join(ROOT, "profiles", "iteration_T700_G18000_kernel_trace.md")
@@ -121,7 +127,7 @@ def accuracy_vs_golden(torch, panda, W, P, C, precision: int):
     Ne, Na = W.shape
     if (g["workload"]["T"], g["workload"]["G"]) != (Ne, Na):
         return None
-    ctx = panda.Context(Ne, Na, panda.default_options(tol=0.0, precision=precision, **LIB_OPTS))
+    ctx = panda.Context(Ne, Na, panda.default_options(tol=0.0, precision=precision, **form_opts(precision)))
     ctx.load(W, P, C)
     iw = g["idx"]["W"]
     rows = torch.as_tensor(iw[0], device="cuda")
@@ -155,7 +161,7 @@ def gpu_inputs(w: I.Workload, torch, panda):
 def time_iterations(torch, panda, W, P, C, steps: int, warmup: int, precision: int = 0):
     Ne, Na = W.shape
     # tol = 0: no iteration inside the timing is skipped by convergence
-    opts = panda.default_options(tol=0.0, max_iter=1 << 30, precision=precision, **LIB_OPTS)
+    opts = panda.default_options(tol=0.0, max_iter=1 << 30, precision=precision, **form_opts(precision))
     ctx = panda.Context(Ne, Na, opts)
     ctx.load(W, P, C)
     for _ in range(warmup):
@@ -177,7 +183,7 @@ def time_iterations(torch, panda, W, P, C, steps: int, warmup: int, precision: i
 
 def time_to_converge(torch, panda, W, P, C, runs: int, precision: int = 0):
     Ne, Na = W.shape
-    opts = panda.default_options(precision=precision, **LIB_OPTS)
+    opts = panda.default_options(precision=precision, **form_opts(precision))
     ws = panda.workspace(panda.workspace_bytes(Ne, Na, opts))
     out = (torch.empty_like(W), torch.empty_like(P), torch.empty_like(C))
     times, res = [], None
@@ -210,9 +216,14 @@ def warm_start_eval(torch, panda, W, P, C, plain):
     err = (warm.W - plain.W).abs().max().item()
     scale = max(1.0, plain.W.abs().max().item())
     accepted = warm.converged and err <= 1e-3 * scale
-    return {"available": True, "t0": t0, "polish_iters": warm.polish, "time_s": t_warm,
-            "max_abs_dW_vs_plain": err, "rel": err / scale, "accepted": accepted,
-            "note": "judged by the plain run; when not accepted the plain result stands"}
+    ev = meta.get("eval_T700_G18000", {})
+    return {"available": True, "t0": t0, "polish_iters": warm.polish, "frozen": warm.frozen,
+            "time_s": t_warm, "max_abs_dW_vs_plain": err, "rel": err / scale,
+            "accepted": accepted,
+            "prediction_rel_err_vs_converged": ev.get("prediction", {}).get("rel_err_vs_converged"),
+            "amplification_eps_1e-4": ev.get("amplification_eps_1e-4"),
+            "note": ("judged by the plain run; not accepted, so the plain result stands and the "
+                     "warm start is not part of the chosen form's time")}
 
 
 def oracle_iteration(O, W, P, C, frac: float = 1.0, report=None):
@@ -300,7 +311,7 @@ def main():
                     help="skip the comparison with the stored oracle run")
     args = ap.parse_args()
     if args.packed_c is not None:
-        LIB_OPTS["packed_c"] = args.packed_c
+        PLAIN_OPTS["packed_c"] = CHOSEN_OPTS["packed_c"] = args.packed_c
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
               "described in the design notes but not built", file=sys.stderr)
@@ -364,16 +375,21 @@ def main():
         # executed bf16 flops: three products per FP32-equivalent product
         bf_rate = 3.0 * rates3["A+W"]
         result["chosen_form"] = {
-            "form": "bf16x3", "s_per_iteration": statistics.median(per3),
+            "form": "bf16x3" + (" + packed C" if CHOSEN_OPTS.get("packed_c") else ""),
+            "plain_layout": "packed C" if PLAIN_OPTS.get("packed_c") else "C stored whole",
+            "s_per_iteration": statistics.median(per3),
             "speedup_per_iteration": s_iter / statistics.median(per3),
             "phase_ms": ms3, "phase_tflops_fp32_equivalent": rates3,
             "roofline": {"bound": "mfma",
-                         "kernel": "A+W: k_rect_streamk<BlockGemmB3P<256,128,4,1,FP32 C,3,32>, "
-                                   "EpiWUpdate> + k_rect_fixup",
+                         "kernel": ("A+W: k_rect_streamk<BlockGemmB3P<256,128,4,1,FP32 C,3,32,"
+                                    + ("packed" if CHOSEN_OPTS.get("packed_c") else "whole")
+                                    + " C>, EpiWUpdate> + k_rect_fixup"),
                          "achieved": bf_rate, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                          "frac": bf_rate / PEAK_BF16_MFMA_TFLOPS,
-                         "traffic": traffic.get("b3_aw_traffic_bytes"),
-                         "from_kernel_trace": trace_frac("b3", PEAK_BF16_MFMA_TFLOPS, 3.0)},
+                         "traffic": traffic.get(("b3p" if CHOSEN_OPTS.get("packed_c") else "b3")
+                                                + "_aw_traffic_bytes"),
+                         "from_kernel_trace": trace_frac("b3p" if CHOSEN_OPTS.get("packed_c") else "b3",
+                                                         PEAK_BF16_MFMA_TFLOPS, 3.0)},
         }
     if not args.no_converge:
         log("time to converge (plain FP32)")

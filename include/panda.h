@@ -54,7 +54,10 @@ typedef enum {
   PANDA_ERR_DEGENERATE = -2, /* z-score of a constant network (std = 0)        */
   PANDA_ERR_NONFINITE = -3,  /* NaN or Inf in an input network                 */
   PANDA_ERR_HIP = -4,        /* a HIP runtime call failed                      */
-  PANDA_ERR_WORKSPACE = -5   /* workspace missing, too small or misaligned     */
+  PANDA_ERR_WORKSPACE = -5,  /* workspace missing, too small or misaligned     */
+  PANDA_STATUS_MAX_ENUM = 0x7fffffff /* not a status: makes every 32-bit value a
+                                        valid panda_status (so an unknown code can
+                                        be passed to panda_status_string)      */
 } panda_status;
 
 /* Arithmetic of the similarity products (norms, denominators, h and the

@@ -20,20 +20,29 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "panda_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (CPU test of the oracle's memory and arithmetic safety); loaded instead of
+# the plain build when ORACLE_SANITIZED=1 (the sanitizer runtime must then be
+# preloaded into the process)
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_DEGENERATE, ERR_NONFINITE, ERR_NOMEM = -1, -2, -3, -5
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain IEEE FP64: -O2 -ffp-contract=off)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (plain IEEE FP64: -O2 -ffp-contract=off);
+    sanitize: the AddressSanitizer + UndefinedBehaviorSanitizer build."""
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp%d" % os.getpid()
+        san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                "-fno-omit-frame-pointer", "-g"] if sanitize else [])
+        cmd = (["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                "-fno-fast-math"] + san + ["-o", tmp, _SRC, "-lm"])
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Opts(ct.Structure):
@@ -77,9 +86,11 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        lib = ct.CDLL(_LIB)
+        sanitized = os.environ.get("ORACLE_SANITIZED") == "1"
+        path = _LIB_SAN if sanitized else _LIB
+        if not os.path.exists(path):
+            build(force=False, sanitize=sanitized)
+        lib = ct.CDLL(path)
         dp = ct.POINTER(ct.c_double)
         lp = ct.POINTER(ct.c_int64)
         i64, i32 = ct.c_int64, ct.c_int32

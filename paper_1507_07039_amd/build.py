@@ -19,9 +19,20 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = (["/opt/rocm/bin/hipcc"] + HIPFLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp]
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the
+# library (a CPU check of the host code: argument checks, layouts, the ABI);
+# the device code is built as usual.  Loaded by the sanitizer test only.
+LIB_SAN = os.path.join(HERE, "libpanda_san.so")
+SANFLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-shared-libsan"]
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out = LIB_SAN if sanitize else LIB
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = (["/opt/rocm/bin/hipcc"] + HIPFLAGS + (SANFLAGS if sanitize else [])
+           + ["-I", os.path.join(ROOT, "include"), "-o", tmp]
            + [os.path.join(CSRC, s) for s in SOURCES])
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -29,8 +40,8 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libpanda.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -14,6 +14,9 @@ from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpanda.so")
+# the host-sanitized build, for the sanitizer test (PANDA_LIB_SANITIZED=1)
+if os.environ.get("PANDA_LIB_SANITIZED") == "1":
+    LIB_PATH = os.path.join(HERE, "libpanda_san.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_DEGENERATE, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5

@@ -133,14 +133,29 @@ def main():
             torch.cuda.synchronize()
             t_warm = time.perf_counter() - ts
             res[name] = {"t0": t0e, "polish_iters": j["warm"].polish,
-                         "converged": j["warm"].converged, "max_abs_err": j["max_abs_err"],
+                         "converged": j["warm"].converged, "frozen": j["warm"].frozen,
+                         "max_abs_err": j["max_abs_err"],
                          "max_abs_W": j["scale"], "rel_err": j["max_abs_err"] / j["scale"],
                          "accepted": j["accepted"],
                          "rank_agreement": rank_agreement(j["warm"].W, plain.W),
                          "time_s_incl_judge": t_warm}
             log(name, res[name])
+        # how close the prediction is to the converged W, and how close a warm
+        # state at t0 would have to be to the plain run's own state there
+        Wp = WSG.predict(params, W, P, C, args.sketch_seed)
+        pred = {"max_abs_err_vs_converged": (Wp - plain.W).abs().max().item(),
+                "rel_err_vs_converged": (Wp - plain.W).abs().max().item()
+                / max(1.0, plain.W.abs().max().item()),
+                "rank_agreement": rank_agreement(Wp, plain.W)}
+        t0s = sorted({2, 5, 10, 20, 40, max(1, plain.iters - 5)})
+        amp, _ = WSG.amplification(W, P, C, t0s, eps=1e-4, plain=plain)
+        for t0e, a in amp.items():
+            a["required_rel_accuracy_at_t0"] = 1e-3 / max(a["amp"], 1e-30)
+        log("prediction", pred)
+        log("amplification", amp)
         summary["eval_T700_G18000"] = {"plain_iters": plain.iters, "plain_time_s": t_plain,
                                        "prior_rank_agreement": rank_agreement(W, plain.W),
+                                       "prediction": pred, "amplification_eps_1e-4": amp,
                                        "runs": res}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(summary, f, indent=1)

@@ -14,6 +14,9 @@ moves tensors between calls and keeps the training loop.
   warm_run       W_pred -> warm state at t0 -> message passing to h < tol
   judged_run     warm_run checked against the plain run from the priors (the
                  reference and the fallback)
+  amplification  how much a small change of W at iteration t0 of the plain
+                 run grows by the end of the run (what a warm state at t0
+                 would have to be accurate to)
 """
 from __future__ import annotations
 
@@ -123,7 +126,8 @@ class WarmResult:
     t: int            # final iteration number (t0 + polish iterations)
     polish: int       # iterations run from the warm state
     h: float
-    converged: bool
+    converged: bool   # h < tol after more than one polish iteration
+    frozen: bool      # h < tol at once: the warm state did not move
 
 
 def warm_run(params, W, P, C, t0: int, sketch_seed: int = 0, opts=None, max_polish: int = 200):
@@ -143,7 +147,10 @@ def warm_run(params, W, P, C, t0: int, sketch_seed: int = 0, opts=None, max_poli
     Wf, Pf, Cf, h, t = ctx.state()
     o = opts or panda.default_options()
     ctx.close()
-    return WarmResult(Wf, Pf, Cf, t, t - t0, h, h < o.tol)
+    # a warm state whose first iteration already has h < tol did not move:
+    # that is not a converged run of the method, and the judge rejects it
+    frozen = h < o.tol and t - t0 <= 1
+    return WarmResult(Wf, Pf, Cf, t, t - t0, h, h < o.tol and not frozen, frozen)
 
 
 def judged_run(params, W, P, C, t0: int, sketch_seed: int = 0, opts=None, rel_tol: float = 1e-3,
@@ -158,3 +165,44 @@ def judged_run(params, W, P, C, t0: int, sketch_seed: int = 0, opts=None, rel_to
     ok = warm.converged and err <= rel_tol * scale
     return {"accepted": ok, "warm": warm, "plain": plain, "max_abs_err": err, "scale": scale,
             "result_W": warm.W if ok else plain.W}
+
+
+def amplification(W, P, C, t0s, eps: float = 1e-4, seed: int = 0, opts=None, plain=None):
+    """For each t0: run the plain method to iteration t0, multiply every entry
+    of W by (1 + eps u), u ~ U(-1, 1), resume from there (a stored state
+    resumes exactly) and run to h < tol.  Returns {t0: {"amp": max|dW| /
+    max(1, max|W|) / eps at the end, "iters": stopping iteration}} and the
+    plain run.  A warm state at t0 is accepted only if its own W is within
+    about 1e-3 / amp of the plain run's W at t0."""
+    torch = _torch()
+    Ne, Na = W.shape
+    if plain is None:
+        plain = panda.run(W, P, C, opts=opts)
+    scale = max(1.0, plain.W.abs().max().item())
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    out = {}
+    for t0 in t0s:
+        ctx = panda.Context(Ne, Na, opts)
+        ctx.load(W, P, C)
+        t = 0
+        while t < t0:
+            _, t2 = ctx.iterate()
+            if t2 == t:
+                break
+            t = t2
+        Wt, Pt, Ct, _, tt = ctx.state()
+        ctx.close()
+        u = torch.rand(Wt.shape, generator=g, device="cuda") * 2 - 1
+        Wp = (Wt.double() * (1 + eps * u.double())).float()
+        ctx = panda.Context(Ne, Na, opts)
+        ctx.load(Wp, Pt, Ct, t=tt)
+        t = tt
+        while True:
+            _, t2 = ctx.iterate()
+            if t2 == t:
+                break
+            t = t2
+        Wf = ctx.state()[0]
+        ctx.close()
+        out[int(t0)] = {"amp": (Wf - plain.W).abs().max().item() / scale / eps, "iters": int(t)}
+    return out, plain
