@@ -130,11 +130,13 @@ constexpr int kSymLD = kCB + 1;
 // Fresh similarity of one C-tile entry from its product and the squared
 // norms nr = |W_.gr|^2, nc = |W_.gc|^2 (FP32 math, see above); 0 outside the
 // strictly-upper real part.
+// Computed without branches (the entries outside, or with den <= 0, select
+// 0 after the fact), so a wave's entries need no divergent paths.
 __device__ __forceinline__ float coreg_sim(float acc, int64_t gr, int64_t gc, int64_t Na,
                                            double nr, double nc) {
-  if (!(gr < gc && gc < Na)) return 0.0f;
   const float den = (float)(nr + nc - fabs((double)acc));
-  return den > 0.0f ? acc * __frsqrt_rn(den) : 0.0f;
+  const float v = acc * __frsqrt_rn(den);
+  return (gr < gc && gc < Na && den > 0.0f) ? v : 0.0f;
 }
 
 // The squared norm this thread stages for tile (I, J): threads 0-127 the
@@ -183,6 +185,15 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
     old[k] = __builtin_nontemporal_load(
         reinterpret_cast<const f4*>(Ct + (r0 + rr) * ldt + c0 + c));
   }
+  // this thread's fresh similarities, all read before the first write-back
+  // below (a read after a write to the staged tile would wait for it)
+  float fresh[kChunks][4];
+#pragma unroll
+  for (int k = 0; k < kChunks; ++k) {
+    const int id = t + k * kThreads, rr = id / kC4, c = (id % kC4) * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) fresh[k][e] = ts[rr * kSymLD + c + e];
+  }
 #pragma unroll
   for (int k = 0; k < kChunks; ++k) {
     const int id = t + k * kThreads, rr = id / kC4, c = (id % kC4) * 4;
@@ -192,7 +203,7 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       upper[e] = gr < gc + e && gc + e < Na;  // strictly upper and real
-      const float v = upper[e] ? keep * old[k][e] + alf * ts[rr * kSymLD + c + e] : 0.0f;
+      const float v = upper[e] ? keep * old[k][e] + alf * fresh[k][e] : 0.0f;
       nv[e] = upper[e] ? v : old[k][e];
       ts[rr * kSymLD + c + e] = v;
     }
@@ -228,47 +239,42 @@ __device__ __forceinline__ void coreg_tile_update(FV&& fv, char* smem, int64_t I
         if (gi + e < gj) dst[e] = v[e];
     }
   }
-  // per-row partial sums of the off-diagonal entries
+  // per-row partial sums of the off-diagonal entries, each over four
+  // interleaved partial sums (four independent FP64 chains instead of one)
   const float* sv = SIGT ? tt : ts;
+  double a1[4] = {0.0, 0.0, 0.0, 0.0}, a2[4] = {0.0, 0.0, 0.0, 0.0}, a3[4] = {0.0, 0.0, 0.0, 0.0};
+  // entries base + e * step, e = 0 .. kCB - 1
+  auto walk = [&](int base, int step) {
+#pragma unroll 8
+    for (int e = 0; e < kCB; e += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int at = base + (e + u) * step;
+        const double x = sv[at];
+        a1[u] += x;
+        a2[u] += x * x;
+        if constexpr (SIGT) a3[u] += (double)ts[at] * (double)ts[at];
+      }
+    }
+  };
+  auto fold = [](const double (&a)[4]) { return (a[0] + a[1]) + (a[2] + a[3]); };
   if (I == J) {
     if (t < kCB) {
-      double s1 = 0.0, s2 = 0.0, c2 = 0.0;
-      for (int q = 0; q < kCB; ++q) {  // row part (entries right of the diagonal)
-        const double x = sv[t * kSymLD + q];
-        s1 += x;
-        s2 += x * x;
-        if constexpr (SIGT) c2 += (double)ts[t * kSymLD + q] * (double)ts[t * kSymLD + q];
-      }
-      for (int p = 0; p < kCB; ++p) {  // column part (entries above the diagonal)
-        const double x = sv[p * kSymLD + t];
-        s1 += x;
-        s2 += x * x;
-        if constexpr (SIGT) c2 += (double)ts[p * kSymLD + t] * (double)ts[p * kSymLD + t];
-      }
-      cstat[I * ldstat + m0 + t] = make_double2(s1, s2);
-      if constexpr (SIGT) csq[I * ldstat + m0 + t] = c2;
+      walk(t * kSymLD, 1);  // row part (entries right of the diagonal)
+      walk(t, kSymLD);      // column part (entries above the diagonal)
+      cstat[I * ldstat + m0 + t] = make_double2(fold(a1), fold(a2));
+      if constexpr (SIGT) csq[I * ldstat + m0 + t] = fold(a3);
     }
   } else {
     const int q = t & (kCB - 1);
-    double s1 = 0.0, s2 = 0.0, c2 = 0.0;
     if (t < kCB) {
-      for (int p = 0; p < kCB; ++p) {
-        const double x = sv[q * kSymLD + p];
-        s1 += x;
-        s2 += x * x;
-        if constexpr (SIGT) c2 += (double)ts[q * kSymLD + p] * (double)ts[q * kSymLD + p];
-      }
-      cstat[J * ldstat + m0 + q] = make_double2(s1, s2);
-      if constexpr (SIGT) csq[J * ldstat + m0 + q] = c2;
+      walk(q * kSymLD, 1);
+      cstat[J * ldstat + m0 + q] = make_double2(fold(a1), fold(a2));
+      if constexpr (SIGT) csq[J * ldstat + m0 + q] = fold(a3);
     } else {
-      for (int p = 0; p < kCB; ++p) {
-        const double x = sv[p * kSymLD + q];
-        s1 += x;
-        s2 += x * x;
-        if constexpr (SIGT) c2 += (double)ts[p * kSymLD + q] * (double)ts[p * kSymLD + q];
-      }
-      cstat[I * ldstat + n0 + q] = make_double2(s1, s2);
-      if constexpr (SIGT) csq[I * ldstat + n0 + q] = c2;
+      walk(q, kSymLD);
+      cstat[I * ldstat + n0 + q] = make_double2(fold(a1), fold(a2));
+      if constexpr (SIGT) csq[I * ldstat + n0 + q] = fold(a3);
     }
   }
 }
@@ -290,6 +296,16 @@ __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I
   double* nsh = reinterpret_cast<double*>(smem + coreg_tile_bytes<SIGT>());
   nsh[threadIdx.x] = nval;
   __syncthreads();
+  // the norms of this lane's rows and columns, all read before the first
+  // store of the staged tile (reads after a store to the same shared array
+  // would each wait for the one before)
+  double nr[G::TM][16], nc[G::TN];
+#pragma unroll
+  for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) nr[i][r] = nsh[g.row_of(i, r)];
+#pragma unroll
+  for (int j = 0; j < G::TN; ++j) nc[j] = nsh[kCB + g.col_of(j)];
   coreg_tile_update<SIGT, PK>(
       [&](auto&& f) {
 #pragma unroll
@@ -299,7 +315,7 @@ __device__ __forceinline__ void coreg_epilogue(const G& g, char* smem, int64_t I
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int rr = g.row_of(i, r), c = g.col_of(j);
-              f(rr, c, coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, nsh[rr], nsh[kCB + c]));
+              f(rr, c, coreg_sim(g.acc[i][j][r], m0 + rr, n0 + c, Na, nr[i][r], nc[j]));
             }
       },
       smem, I, J, C, ldc, Na, alpha, cstat, csq, ldstat);

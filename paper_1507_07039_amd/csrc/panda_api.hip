@@ -429,6 +429,7 @@ const char* panda_status_string(panda_status s) {
     case PANDA_ERR_NONFINITE: return "non-finite input";
     case PANDA_ERR_HIP: return "HIP runtime error";
     case PANDA_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case PANDA_STATUS_MAX_ENUM: break;  // sizes the enum, no status
   }
   return "unknown status";
 }

@@ -178,9 +178,18 @@ __global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, in
   const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   double cs = 0.0;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr, c = c0 + tx;
-    const float v = (r < Ne && c < Na) ? W[r * ldw + c] : 0.0f;
+  // this thread's 16 entries, all loads in flight before the first is used
+  float vals[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t r = r0 + ty + 4 * k, c = c0 + tx;
+    vals[k] = (r < Ne && c < Na) ? W[r * ldw + c] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int rr = ty + 4 * k;
+    const int64_t r = r0 + rr;
+    const float v = vals[k];
     if constexpr (SHADOW) tile[rr][tx] = v;
     const double q = (double)v * (double)v;
     cs += q;
