@@ -73,7 +73,7 @@ struct PhResp {
     else
       g.run(OpsF32{d.P, d.Nep, W, d.Nap}, m0, n0, 0, d.Nep, smem);
     EpiStoreT epi{d.R, d.Nap, d.Ne, d.Na, d.nP, d.nWc, d.dP, W, d.Nap};
-    g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
+    epi_tile(g, epi, m0, n0);
   }
 };
 
@@ -101,7 +101,7 @@ struct PhAvail {
       g.run(OpsF32{Wold, d.Nap, d.C, d.Nap}, m0, n0, 0, d.Nap, smem);
     EpiWUpdate epi{Wold, d.R,   d.W[ws ^ 1], d.Nap, d.Ne,       d.Na,    d.nWr,
                    d.nC, d.dC,  alpha,       h_undamped, d.hpart, 0.0};
-    g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
+    epi_tile(g, epi, m0, n0);
     epi.end_tile(local, red);
   }
 };

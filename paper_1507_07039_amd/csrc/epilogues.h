@@ -38,6 +38,39 @@ struct EpiStoreT {
       out[r * ldo + c] = (float)tanimoto(dot, nx[r], ny[c]);
     }
   }
+  // NE entries at once, the same arithmetic as element(); entries past
+  // M x N read a clamped in-range entry and store nothing.
+  template <int NE>
+  __device__ __forceinline__ void block(const int64_t (&r)[NE], const int64_t (&c)[NE],
+                                        const float (&acc)[NE]) {
+    float v[NE];
+    if (xd) {
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int64_t rr = r[k] < M ? r[k] : M - 1, cc = c[k] < N ? c[k] : N - 1;
+        double dot = (double)acc[k];
+        dot += xd[rr] * (double)yv[rr * ldyv + cc];
+        v[k] = (float)tanimoto(dot, nx[rr], ny[cc]);
+      }
+    } else if (yd) {
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int64_t rr = r[k] < M ? r[k] : M - 1, cc = c[k] < N ? c[k] : N - 1;
+        double dot = (double)acc[k];
+        dot += (double)xv[rr * ldxv + cc] * yd[cc];
+        v[k] = (float)tanimoto(dot, nx[rr], ny[cc]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int64_t rr = r[k] < M ? r[k] : M - 1, cc = c[k] < N ? c[k] : N - 1;
+        v[k] = (float)tanimoto((double)acc[k], nx[rr], ny[cc]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (r[k] < M && c[k] < N) out[r[k] * ldo + c[k]] = v[k];
+  }
   __device__ __forceinline__ void end_tile(int64_t, double*) {}
 };
 
@@ -80,6 +113,33 @@ struct EpiWUpdate {
   }
   __device__ __forceinline__ void element(int64_t r, int64_t c, float acc) {
     element_pre(r, c, acc, fetch(r, c));
+  }
+  // NE entries at once, the same arithmetic as element_pre and the same
+  // order of the h sum; entries past Ne x Na read a clamped in-range entry
+  // and neither store nor count.
+  template <int NE>
+  __device__ __forceinline__ void block(const int64_t (&r)[NE], const int64_t (&c)[NE],
+                                        const float (&acc)[NE]) {
+    float wn[NE];
+    double dh[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int64_t rr = r[k] < Ne ? r[k] : Ne - 1, cc = c[k] < Na ? c[k] : Na - 1;
+      const int64_t o = rr * ld + cc;
+      const double w = Wold[o];
+      double dot = (double)acc[k];
+      dot += w * cd[cc];
+      const double a = tanimoto(dot, nx[rr], ny[cc]);
+      const double pred = 0.5 * (a + (double)R[o]);
+      wn[k] = (float)((1.0 - alpha) * w + alpha * pred);
+      dh[k] = h_undamped ? fabs(pred - w) : fabs((double)wn[k] - w);
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (r[k] < Ne && c[k] < Na) {
+        Wnew[r[k] * ld + c[k]] = wn[k];
+        hsum += dh[k];
+      }
   }
   __device__ __forceinline__ void end_tile(int64_t tile, double* red) {
     const double s = block_sum(hsum, red);

@@ -48,12 +48,13 @@ __device__ __forceinline__ void tri_tile(int64_t u, int64_t& I, int64_t& J) {
 // (about 2^-23 relative) refined by one Newton step, which squares its error
 // (about 1e-14 relative, far under the FP32 rounding of every result), for a
 // few FMAs instead of a double divide and square root per entry.
+// Computed without a branch (den <= 0 selects 0 after the fact), so that
+// runs of entries compile to straight-line code.
 __device__ __forceinline__ double tanimoto(double dot, double xx, double yy) {
   const double den = xx + yy - fabs(dot);
-  if (!(den > 0.0)) return 0.0;
   const double y0 = __builtin_amdgcn_rsq(den);
   const double y1 = y0 * (1.5 - 0.5 * den * y0 * y0);
-  return dot * y1;
+  return den > 0.0 ? dot * y1 : 0.0;
 }
 
 // Deterministic sum of one double per thread over the block; red holds one
@@ -415,6 +416,7 @@ struct TileLoadB3 {
 template <int BM_, int BN_, int WM, int WN, int BK_ = 32, int WPE = 1>
 struct BlockGemmB3 {
   using Ops = OpsB3;
+  static constexpr bool kBlockEpi = true;  // epilogue entries in runs of 8
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
   static constexpr int WAVES_PER_EU = WPE;  // occupancy asked of the compiler (1: no request)
   static constexpr int TM = BM / WM / 32;
@@ -1106,6 +1108,23 @@ template <class G>
 struct prefetch_epi<G, std::void_t<decltype(G::kPrefetchEpi)>>
     : std::integral_constant<bool, G::kPrefetchEpi> {};
 
+// Epilogues with a block<N>(rows, cols, acc) member take N entries at once:
+// every operand of the N entries is loaded before the first result is
+// stored (a store may alias an operand buffer, so entry by entry each
+// entry's loads would wait for the store before them).
+template <class E, class = void>
+struct has_block : std::false_type {};
+template <class E>
+struct has_block<E, std::void_t<decltype(&E::template block<16>)>> : std::true_type {};
+// Block GEMMs whose epilogue takes entries in runs (kBlockEpi); the others
+// keep their registers for occupancy (measured: the FP32 products run
+// slower with the extra live operands).
+template <class G, class = void>
+struct block_epi : std::false_type {};
+template <class G>
+struct block_epi<G, std::void_t<decltype(G::kBlockEpi)>>
+    : std::integral_constant<bool, G::kBlockEpi> {};
+
 template <class G, class Epi>
 __device__ __forceinline__ void epi_tile(const G& g, Epi& epi, int64_t m0, int64_t n0) {
   if constexpr (has_fetch<Epi>::value && prefetch_epi<G>::value) {
@@ -1120,6 +1139,24 @@ __device__ __forceinline__ void epi_tile(const G& g, Epi& epi, int64_t m0, int64
 #pragma unroll
         for (int r = 0; r < 16; ++r) epi.element_pre(m0 + g.row_of(i, r), c, g.acc[i][j][r], pre[r]);
       }
+  } else if constexpr (has_block<Epi>::value && block_epi<G>::value) {
+    constexpr int NB = 8;
+#pragma unroll
+    for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::TN; ++j)
+#pragma unroll
+        for (int r0 = 0; r0 < 16; r0 += NB) {
+          int64_t rs[NB], cs[NB];
+          float a[NB];
+#pragma unroll
+          for (int r = 0; r < NB; ++r) {
+            rs[r] = m0 + g.row_of(i, r0 + r);
+            cs[r] = n0 + g.col_of(j);
+            a[r] = g.acc[i][j][r0 + r];
+          }
+          epi.template block<NB>(rs, cs, a);
+        }
   } else {
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
   }
@@ -1186,7 +1223,16 @@ __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t
     for (int64_t c = 1; c < S; ++c)
 #pragma unroll
       for (int q = 0; q < GRP; ++q) s[q] += part[(c * T + t) * E + threadIdx.x + (q0 + q) * kFixThreads];
-    if constexpr (has_fetch<Epi>::value) {
+    if constexpr (has_block<Epi>::value && !has_fetch<Epi>::value) {
+      int64_t rs[GRP], cs[GRP];
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = threadIdx.x + (q0 + q) * kFixThreads;
+        rs[q] = m0 + e / G::BN;
+        cs[q] = n0 + e % G::BN;
+      }
+      epi.template block<GRP>(rs, cs, s);
+    } else if constexpr (has_fetch<Epi>::value) {
       typename Epi::Pre pre[GRP];
 #pragma unroll
       for (int q = 0; q < GRP; ++q) {
