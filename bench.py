@@ -381,7 +381,7 @@ def main():
             "speedup_per_iteration": s_iter / statistics.median(per3),
             "phase_ms": ms3, "phase_tflops_fp32_equivalent": rates3,
             "roofline": {"bound": "mfma",
-                         "kernel": ("A+W: k_rect_streamk<BlockGemmB3P<256,128,4,1,FP32 C,3,32,"
+                         "kernel": ("A+W: k_rect_streamk<BlockGemmB3P<256,128,4,2,FP32 C,3,32,"
                                     + ("packed" if CHOSEN_OPTS.get("packed_c") else "whole")
                                     + " C>, EpiWUpdate> + k_rect_fixup"),
                          "achieved": bf_rate, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",

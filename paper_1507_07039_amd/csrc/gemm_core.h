@@ -609,12 +609,15 @@ struct BlockGemmB3P {
       YP, OpsB3FP, typename std::conditional<YF32, OpsB3F, OpsB3>::type>::type;
   static_assert(!YP || (YF32 && BN_ == (int)kPT && kPT % BK_ == 0 && BK_ == 32),
                 "packed Y: FP32 rows of one packed column block, K-tiles inside a block");
-  // one block per CU and the accumulators in AGPRs: the epilogue has the
-  // VGPRs to fetch its per-entry operands 16 at a time (see epi_tile)
+  // one block per CU (its stages fill most of the LDS): the epilogue has
+  // the registers to fetch its per-entry operands 16 at a time (see epi_tile)
   static constexpr bool kPrefetchEpi = true;
   static constexpr int BM = BM_, BN = BN_, BK = BK_, NT = 64 * WM * WN;
   static constexpr int WAVES = WM * WN;
-  static constexpr int WAVES_PER_EU = 1;
+  // the block's waves spread over the CU's four SIMDs: eight waves give each
+  // SIMD two, so one wave's waits are covered by the other's matrix work
+  static_assert(WAVES % 4 == 0, "whole waves per SIMD");
+  static constexpr int WAVES_PER_EU = WAVES / 4;
   static constexpr int TM = BM / WM / 32;
   static constexpr int TN = BN / WN / 32;
   static constexpr int KS = BK / 16;
