@@ -104,6 +104,8 @@ struct panda_ctx {
   bool packed;  // C stored as its upper tiles (packed_tile)
   panda::bf16_t *Wh, *Wl, *Wth, *Wtl, *Ph, *Pl;  // split planes (C stays FP32)
   panda::DevState* host;  // pinned
+  panda::DevState* snap;  // pinned, two slots: states copied ahead (run_loaded)
+  hipEvent_t snap_ev[2];
   int splits;
   int64_t nh;
   int32_t t0;

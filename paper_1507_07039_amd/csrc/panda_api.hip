@@ -178,6 +178,11 @@ panda_status ctx_fill_order(panda_ctx* c) {
 void ctx_free(panda_ctx* c) {
   if (c->host) (void)hipHostFree(c->host);
   c->host = nullptr;
+  if (c->snap) {
+    (void)hipHostFree(c->snap);
+    for (hipEvent_t& e : c->snap_ev) (void)hipEventDestroy(e);
+  }
+  c->snap = nullptr;
   if (c->ev[0][0])
     for (int i = 0; i < kMaxPending; ++i)
       for (int p = 0; p <= PANDA_NPHASE; ++p) (void)hipEventDestroy(c->ev[i][p]);
@@ -352,18 +357,39 @@ namespace panda {
 
 // Enqueue ahead and read h back every poll_every iterations; iterations
 // enqueued past convergence are no-ops on the device.
+// Iterate to convergence or max_iter.  The host never makes the device wait
+// for it: the state after a polled iteration is copied to a pinned slot (with
+// an event) as soon as that iteration is enqueued, and the host looks at it
+// only after enqueueing the next iteration, so the device always has work
+// queued while the host waits.  The one iteration enqueued after convergence
+// runs gated (its kernels return at once: the executed iterations are always
+// a prefix of the enqueued ones), so the result is that of polling at once.
 panda_status run_loaded(panda_ctx* c) {
-  panda_status st = PANDA_OK;
   const int64_t max_iter = c->opt.max_iter, poll = c->opt.poll_every;
-  while (st == PANDA_OK && c->enqueued < max_iter) {
-    st = enqueue_iteration(c);
-    if (st != PANDA_OK) break;
-    if (c->enqueued % poll == 0 || c->enqueued == max_iter) {
-      st = read_state(c);
-      if (st != PANDA_OK || !c->host->active) break;
+  if (!c->snap) {
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->snap), 2 * sizeof(DevState),
+                          hipHostMallocDefault));
+    for (hipEvent_t& e : c->snap_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  int64_t pending = -1;  // polled iteration whose state copy is awaited
+  while (c->enqueued < max_iter) {
+    PANDA_TRY(enqueue_iteration(c));
+    const int64_t k = c->enqueued;
+    if (pending >= 0) {
+      HIP_TRY(hipEventSynchronize(c->snap_ev[pending & 1]));
+      if (!c->snap[pending & 1].active) break;
+      pending = -1;
+    }
+    if (k % poll == 0 && k < max_iter) {
+      HIP_TRY(hipMemcpyAsync(&c->snap[k & 1], c->st, sizeof(DevState), hipMemcpyDeviceToHost,
+                             c->stream));
+      HIP_TRY(hipEventRecord(c->snap_ev[k & 1], c->stream));
+      pending = k;
     }
   }
-  return st;
+  PANDA_TRY(read_state(c));
+  c->enqueued = c->executed;
+  return PANDA_OK;
 }
 
 }  // namespace panda

@@ -160,9 +160,12 @@ __global__ __launch_bounds__(kRT) void k_split_offdiag(const float* __restrict__
 // row-major and gene-major.  Block (bx, by) takes the 64 x 64 tile at rows
 // 64 by, columns 64 bx and writes FP64 partial sums: rowpart[bx][r] over its
 // 64 columns, colpart[by][c] over its 64 rows; k_w_norms_sum adds them up in
-// block order (deterministic).  The planes are written whole tiles at a time
-// from the tile staged in LDS, 8 entries (16 bytes) per store; entries past
-// Ne x Na are zero in the tile, so the padding of the planes stays zero.
+// block order (deterministic).  The tile is staged in LDS: a column's sum is
+// the thread's own (its 16 rows, then the four waves in order), a row's the
+// sum of four threads' quarters (16 columns each, in order) combined within
+// the quad of lanes.  The planes are written whole tiles at a time from the
+// staged tile, 8 entries (16 bytes) per store; entries past Ne x Na are zero
+// in the tile, so the padding of the planes stays zero.
 template <bool SHADOW>
 __global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, int64_t Ne,
                                                  int64_t Na, int64_t ldw, int64_t Nep,
@@ -187,19 +190,26 @@ __global__ __launch_bounds__(kRT) void k_w_norms(const float* __restrict__ W, in
   }
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const int rr = ty + 4 * k;
-    const int64_t r = r0 + rr;
     const float v = vals[k];
-    if constexpr (SHADOW) tile[rr][tx] = v;
-    const double q = (double)v * (double)v;
-    cs += q;
-    double rs = q;  // this row's 64 entries sit in the 64 lanes of the wave
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) rs += __shfl_xor(rs, off);
-    if (tx == 0) rowpart[(int64_t)blockIdx.x * Nep + r] = rs;
+    tile[ty + 4 * k][tx] = v;
+    cs += (double)v * (double)v;
   }
   cred[ty][tx] = cs;
   __syncthreads();
+  {
+    // row rr, quarter q: entries 16 q .. 16 q + 15 (pitch 65: the 64 lanes of
+    // a read hit 64 distinct banks)
+    const int rr = threadIdx.x >> 2, q = threadIdx.x & 3;
+    double rs = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double v = tile[rr][16 * q + i];
+      rs += v * v;
+    }
+    rs += __shfl_xor(rs, 1);  // (q0 + q1) and (q2 + q3) ..
+    rs += __shfl_xor(rs, 2);  // .. then their sum, the same in all four lanes
+    if (q == 0) rowpart[(int64_t)blockIdx.x * Nep + r0 + rr] = rs;
+  }
   if (ty == 0)
     colpart[(int64_t)blockIdx.y * gridDim.x * 64 + c0 + tx] =
         ((cred[0][tx] + cred[1][tx]) + cred[2][tx]) + cred[3][tx];
