@@ -71,7 +71,7 @@ struct LayoutSpec {
   int64_t ppart_splits; // K splits of the W W^T partial products
   bool packed_c = false; // C as its upper tiles (packed_tile)
 };
-LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c = false);
+LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c, int32_t precision);
 
 }  // namespace panda
 

@@ -66,9 +66,10 @@ bool dims_ok(int64_t Ne, int64_t Na) {
 
 namespace panda {
 
-LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c) {
+LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c, int32_t precision) {
   const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
-  return LayoutSpec{false, rect_tiles(Nep, Nap), coop_splits(Nep, Nap), packed_c};
+  const int64_t blocks = precision == PANDA_PREC_BF16X3 ? 512 : 1024;
+  return LayoutSpec{false, rect_tiles(Nep, Nap), coop_splits(Nep, Nap, blocks), packed_c};
 }
 
 // Workspace layout shared by the size queries and the contexts.
@@ -639,7 +640,9 @@ size_t panda_workspace_bytes(int64_t Ne, int64_t Na, const panda_options* opt) {
   (void)opt;
   if (!dims_ok(Ne, Na)) return 0;
   return ctx_layout(Ne, Na, opt ? opt->precision : PANDA_PREC_FP32,
-                    single_spec(Ne, Na, opt && opt->packed_c), nullptr,
+                    single_spec(Ne, Na, opt && opt->packed_c,
+                                opt ? opt->precision : PANDA_PREC_FP32),
+                    nullptr,
                     nullptr);
 }
 
@@ -660,7 +663,8 @@ panda_status panda_ctx_create(int64_t Ne, int64_t Na, const panda_options* opt, 
     return fail(PANDA_ERR_WORKSPACE, "ctx_create: workspace too small or misaligned%s");
   panda_ctx* c = new (std::nothrow) panda_ctx();
   if (!c) return fail(PANDA_ERR_ARG, "ctx_create: out of host memory%s");
-  st = ctx_setup(c, Ne, Na, o, single_spec(Ne, Na, o.packed_c != 0), static_cast<char*>(workspace),
+  st = ctx_setup(c, Ne, Na, o, single_spec(Ne, Na, o.packed_c != 0, o.precision),
+                 static_cast<char*>(workspace),
                  stream);
   if (st != PANDA_OK) {
     delete c;

@@ -111,7 +111,10 @@ constexpr int kCoregGroup = PANDA_COREG_GROUP;
 // P update, split over K: partial products of W W^T on upper tiles.
 hipError_t launch_coop_partial(const float* W, int64_t ldw, int64_t Nep, int64_t Nap, int splits,
                                float* part, const int32_t* gate, hipStream_t s);
-int coop_splits(int64_t Nep, int64_t Nap);
+// K chunks of the partial products, for about `blocks` blocks in all (at
+// T=700, G=18000 the FP32 products run best at 1024, the split-BF16 ones at
+// 512: their partial sums then cost the finalise more than they save).
+int coop_splits(int64_t Nep, int64_t Nap, int64_t blocks);
 
 // Split-BF16 forms of the same products.  Operands are K-contiguous hi/lo
 // planes: P (diagonal zero), W row-major, W^T (gene-major); C stays FP32.

@@ -214,9 +214,9 @@ hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t 
                              rule, cstat, csq, order, gate, s, packed);
 }
 
-int coop_splits(int64_t Nep, int64_t Nap) {
+int coop_splits(int64_t Nep, int64_t Nap, int64_t blocks) {
   const int64_t nT = Nep / kPB, nU = nT * (nT + 1) / 2;
-  int64_t s = (512 + nU - 1) / nU;               // aim at a few hundred blocks
+  int64_t s = (blocks + nU - 1) / nU;
   const int64_t maxs = Nap / (4 * CoopF32::BK);  // at least 4 K-steps per block
   if (s > maxs) s = maxs;
   if (s < 1) s = 1;
