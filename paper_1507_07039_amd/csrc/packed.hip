@@ -41,26 +41,52 @@ __global__ __launch_bounds__(kNT) void k_pack_sym(const float* __restrict__ src,
 }
 
 // The tile is staged in LDS so that both its own rows and its mirror image
-// (the rows of block b, for an off-diagonal tile) are written along rows.
+// (the rows of block b, for an off-diagonal tile) are written along rows, 16
+// bytes per lane where the row allows (dst 16-byte aligned there and the four
+// columns inside n), entry by entry at the edges.
+typedef float fv4 __attribute__((ext_vector_type(4)));
+constexpr int kC4 = (int)kPT / 4;                 // 16-byte chunks per tile row
+constexpr int kPerThread4 = kTileF / 4 / kNT;     // chunks per thread and tile
+
+__device__ __forceinline__ void store4(float* __restrict__ dst, int64_t gi, int64_t gj, int64_t n,
+                                       int64_t ldd, const float (&v)[4]) {
+  if (gi >= n) return;
+  float* p = dst + gi * ldd + gj;
+  if (gj + 3 < n && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+    __builtin_nontemporal_store((fv4){v[0], v[1], v[2], v[3]}, reinterpret_cast<fv4*>(p));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (gj + e < n) p[e] = v[e];
+  }
+}
+
 __global__ __launch_bounds__(kNT) void k_unpack_sym(const float* __restrict__ src, int64_t n,
                                                     float* __restrict__ dst, int64_t ldd) {
   __shared__ float ts[kPT * kLdsLd];
   int64_t a, b;
   tile_of(blockIdx.x, a, b);
-  const float* t = src + (int64_t)blockIdx.x * kTileF;
-  for (int q = 0; q < kPerThread; ++q) {
-    const int e = threadIdx.x + q * kNT, r = e / (int)kPT, c = e % (int)kPT;
-    const float v = t[e];
-    ts[r * kLdsLd + c] = v;
-    const int64_t gi = a * kPT + r, gj = b * kPT + c;
-    if (gi < n && gj < n) dst[gi * ldd + gj] = v;
+  const fv4* t = reinterpret_cast<const fv4*>(src + (int64_t)blockIdx.x * kTileF);
+  fv4 v4[kPerThread4];
+#pragma unroll
+  for (int q = 0; q < kPerThread4; ++q) v4[q] = __builtin_nontemporal_load(t + threadIdx.x + q * kNT);
+#pragma unroll
+  for (int q = 0; q < kPerThread4; ++q) {
+    const int e = threadIdx.x + q * kNT, r = e / kC4, c = (e % kC4) * 4;
+    const float v[4] = {v4[q].x, v4[q].y, v4[q].z, v4[q].w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ts[r * kLdsLd + c + k] = v[k];
+    store4(dst, a * kPT + r, b * kPT + c, n, ldd, v);
   }
   if (a == b) return;  // a diagonal tile holds both of its triangles
   __syncthreads();
-  for (int q = 0; q < kPerThread; ++q) {
-    const int e = threadIdx.x + q * kNT, r = e / (int)kPT, c = e % (int)kPT;
-    const int64_t gi = b * kPT + r, gj = a * kPT + c;  // C[gi][gj] = tile entry (c, r)
-    if (gi < n && gj < n) dst[gi * ldd + gj] = ts[c * kLdsLd + r];
+#pragma unroll
+  for (int q = 0; q < kPerThread4; ++q) {
+    const int e = threadIdx.x + q * kNT, r = e / kC4, c = (e % kC4) * 4;
+    // C[b kPT + r][a kPT + c + k] = tile entry (c + k, r)
+    const float v[4] = {ts[c * kLdsLd + r], ts[(c + 1) * kLdsLd + r], ts[(c + 2) * kLdsLd + r],
+                        ts[(c + 3) * kLdsLd + r]};
+    store4(dst, b * kPT + r, a * kPT + c, n, ldd, v);
   }
 }
 
@@ -92,17 +118,38 @@ __global__ __launch_bounds__(kNT) void k_take_diag_packed(float* __restrict__ C,
 // slot value from each block of rows.
 __global__ __launch_bounds__(kNT) void k_packed_sq_part(const float* __restrict__ C,
                                                         int64_t Nap, double* __restrict__ slots) {
+  __shared__ float ts[kPT * kLdsLd];
   int64_t a, b;
   tile_of(blockIdx.x, a, b);
-  const float* t = C + (int64_t)blockIdx.x * kTileF;
+  const fv4* t = reinterpret_cast<const fv4*>(C + (int64_t)blockIdx.x * kTileF);
+  fv4 v4[kPerThread4];
+#pragma unroll
+  for (int q = 0; q < kPerThread4; ++q) v4[q] = t[threadIdx.x + q * kNT];
+#pragma unroll
+  for (int q = 0; q < kPerThread4; ++q) {
+    const int e = threadIdx.x + q * kNT, r = e / kC4, c = (e % kC4) * 4;
+    ts[r * kLdsLd + c] = v4[q].x;
+    ts[r * kLdsLd + c + 1] = v4[q].y;
+    ts[r * kLdsLd + c + 2] = v4[q].z;
+    ts[r * kLdsLd + c + 3] = v4[q].w;
+  }
+  __syncthreads();
+  // threads 0-127: column th of the tile (rows in order); 128-255: row th -
+  // 128 (columns in order), the mirror's column, for off-diagonal tiles
   const int th = threadIdx.x;
   double s = 0.0;
   if (th < (int)kPT) {
-    for (int r = 0; r < (int)kPT; ++r) s += (double)t[r * kPT + th] * (double)t[r * kPT + th];
+    for (int r = 0; r < (int)kPT; ++r) {
+      const double x = ts[r * kLdsLd + th];
+      s += x * x;
+    }
     slots[a * Nap + b * kPT + th] = s;
   } else if (a < b) {
     const int r = th - (int)kPT;
-    for (int c = 0; c < (int)kPT; ++c) s += (double)t[r * kPT + c] * (double)t[r * kPT + c];
+    for (int c = 0; c < (int)kPT; ++c) {
+      const double x = ts[r * kLdsLd + c];
+      s += x * x;
+    }
     slots[b * Nap + a * kPT + r] = s;
   }
 }
