@@ -315,6 +315,32 @@ def test_run_poll_every_and_determinism(torch, pd, oracle):
     assert torch.equal(a.W, b.W) and torch.equal(a.P, b.P) and torch.equal(a.C, b.C)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_run_one_iteration_ahead_equals_stepwise(torch, pd, oracle, precision):
+    # panda_run keeps the next iteration queued while it checks h of the last
+    # one; the iteration it queues after convergence runs gated.  The result
+    # must be that of a context stepped one synchronous iteration at a time,
+    # also when the cap falls on the converging iteration or just before it.
+    W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
+    Ne, Na = W.shape
+    opts = pd.default_options(precision=precision)
+    ctx = pd.Context(Ne, Na, opts)
+    ctx.load(cuda(torch, W), cuda(torch, P), cuda(torch, C))
+    for _ in range(200):
+        h, t = ctx.iterate()
+        if h < 1e-3:
+            break
+    Ws, Ps, Cs, hs, ts = ctx.state()
+    ctx.close()
+    for cap in (ts + 3, ts, ts - 1, 1):
+        r = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C), max_iter=cap, opts=opts)
+        if cap >= ts:
+            assert r.status == pd.OK and r.iters == ts and r.h == hs
+            assert torch.equal(r.W, Ws) and torch.equal(r.P, Ps) and torch.equal(r.C, Cs)
+        else:
+            assert r.status == pd.NOT_CONVERGED and r.iters == cap
+
+
 def test_resume_equals_straight_run(torch, pd, oracle):
     W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
     straight = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C))
