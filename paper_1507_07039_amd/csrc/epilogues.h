@@ -190,6 +190,61 @@ constexpr int kCB = 128;
 static_assert(kCB == kPT, "C-update tiles are the packed tiles");
 constexpr int kSymLD = kCB + 1;
 
+// EpiStoreT with X's diagonal term (xd set: R = T(P, W)) on a 128 x 128 tile
+// of a block GEMM of 256 threads: the tile's per-row values (xd, nx) and
+// per-column norms (ny) are staged in LDS once, then every entry takes the
+// arithmetic of EpiStoreT::block (the same results bit for bit), the W
+// entries of NB rows of a column loaded together.
+template <int NB, class G>
+__device__ __forceinline__ void store_t_tile_xd(const G& g, char* smem, const EpiStoreT& e,
+                                                int64_t m0, int64_t n0) {
+  static_assert(G::BM == kCB && G::BN == kCB && G::NT == 2 * kCB, "128 x 128 tiles, 256 threads");
+  static_assert(16 % NB == 0, "whole runs per accumulator column");
+  double* sxd = reinterpret_cast<double*>(smem);  // after the product's last LDS reads
+  double* snx = sxd + kCB;
+  double* sny = snx + kCB;
+  const int t = threadIdx.x;
+  __syncthreads();
+  if (t < kCB) {
+    const int64_t r = m0 + t < e.M ? m0 + t : e.M - 1;
+    sxd[t] = e.xd[r];
+    snx[t] = e.nx[r];
+  } else {
+    const int64_t c = n0 + (t - kCB) < e.N ? n0 + (t - kCB) : e.N - 1;
+    sny[t - kCB] = e.ny[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::TN; ++j) {
+      const int c = g.col_of(j);
+      const int64_t gc = n0 + c, cc = gc < e.N ? gc : e.N - 1;
+      const double ny = sny[c];
+#pragma unroll
+      for (int r0 = 0; r0 < 16; r0 += NB) {
+        float yv[NB], v[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int64_t gr = m0 + g.row_of(i, r0 + k), rr = gr < e.M ? gr : e.M - 1;
+          yv[k] = e.yv[rr * e.ldyv + cc];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int rl = g.row_of(i, r0 + k);
+          double dot = (double)g.acc[i][j][r0 + k];
+          dot += sxd[rl] * (double)yv[k];
+          v[k] = (float)tanimoto(dot, snx[rl], ny);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int64_t gr = m0 + g.row_of(i, r0 + k);
+          if (gr < e.M && gc < e.N) e.out[gr * e.ldo + gc] = v[k];
+        }
+      }
+    }
+}
+
 // Fresh similarity of one C-tile entry from its product and the squared
 // norms nr = |W_.gr|^2, nc = |W_.gc|^2 (FP32 math, see above); 0 outside the
 // strictly-upper real part.

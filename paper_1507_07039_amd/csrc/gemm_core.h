@@ -1128,6 +1128,29 @@ template <class G>
 struct block_epi<G, std::void_t<decltype(G::kBlockEpi)>>
     : std::integral_constant<bool, G::kBlockEpi> {};
 
+// The epilogue of a tile in runs of NB entries of one column (Epi::block):
+// all operands of a run are loaded before any of its results is stored.
+template <int NB, class G, class Epi>
+__device__ __forceinline__ void epi_tile_runs(const G& g, Epi& epi, int64_t m0, int64_t n0) {
+  static_assert(16 % NB == 0, "whole runs per accumulator column");
+#pragma unroll
+  for (int i = 0; i < G::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < G::TN; ++j)
+#pragma unroll
+      for (int r0 = 0; r0 < 16; r0 += NB) {
+        int64_t rs[NB], cs[NB];
+        float a[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          rs[r] = m0 + g.row_of(i, r0 + r);
+          cs[r] = n0 + g.col_of(j);
+          a[r] = g.acc[i][j][r0 + r];
+        }
+        epi.template block<NB>(rs, cs, a);
+      }
+}
+
 template <class G, class Epi>
 __device__ __forceinline__ void epi_tile(const G& g, Epi& epi, int64_t m0, int64_t n0) {
   if constexpr (has_fetch<Epi>::value && prefetch_epi<G>::value) {
@@ -1143,23 +1166,7 @@ __device__ __forceinline__ void epi_tile(const G& g, Epi& epi, int64_t m0, int64
         for (int r = 0; r < 16; ++r) epi.element_pre(m0 + g.row_of(i, r), c, g.acc[i][j][r], pre[r]);
       }
   } else if constexpr (has_block<Epi>::value && block_epi<G>::value) {
-    constexpr int NB = 8;
-#pragma unroll
-    for (int i = 0; i < G::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < G::TN; ++j)
-#pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += NB) {
-          int64_t rs[NB], cs[NB];
-          float a[NB];
-#pragma unroll
-          for (int r = 0; r < NB; ++r) {
-            rs[r] = m0 + g.row_of(i, r0 + r);
-            cs[r] = n0 + g.col_of(j);
-            a[r] = g.acc[i][j][r0 + r];
-          }
-          epi.template block<NB>(rs, cs, a);
-        }
+    epi_tile_runs<8>(g, epi, m0, n0);
   } else {
     g.for_each([&](int rr, int c, float v) { epi.element(m0 + rr, n0 + c, v); });
   }
@@ -1198,10 +1205,16 @@ void k_rect_streamk(typename G::Ops ops, int64_t nMT, int64_t nTiles, int64_t U,
 }
 
 // Tail tiles computed in S > 1 K-chunks: add the partial products in chunk
-// order (deterministic) and run the epilogue.  1024 threads per tile: the
+// order (deterministic) and run the epilogue.  1024 threads per block: the
 // epilogue's loads form a dependent chain per element, so the fix-up runs as
-// many waves per tile as a block holds.
+// many waves per tile as a block holds, and a tile of more than 8 entries per
+// thread is shared by kFixParts(G) blocks of 8 entries per thread each (one
+// round of loads per thread instead of several in a row).  Block part q > 0
+// of tile `tile` leaves its share of the h sum in slot q * nTiles + tile of
+// the epilogue's per-tile partials, part 0 in slot `tile`.
 constexpr int kFixThreads = 1024;
+template <class G>
+constexpr int kFixParts = (G::BM * G::BN) / kFixThreads > 8 ? (G::BM * G::BN) / kFixThreads / 8 : 1;
 template <class G, class Epi>
 __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t nTiles, int64_t nb,
                                                             int64_t S,
@@ -1209,17 +1222,21 @@ __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t
                                                             const int32_t* gate) {
   if (gate && *gate == 0) return;
   __shared__ double red[kFixThreads / 64];
+  constexpr int Q = kFixParts<G>;
   const int64_t nFull = (nTiles / nb) * nb, T = nTiles - nFull;
-  const int64_t t = blockIdx.x, tile = nFull + t;
+  const int64_t t = blockIdx.x / Q, tile = nFull + t;
+  const int qb = (int)(blockIdx.x % Q);
   const int64_t m0 = (tile % nMT) * G::BM, n0 = (tile / nMT) * G::BN;
   constexpr int E = G::BM * G::BN;
-  static_assert(E % kFixThreads == 0, "whole passes");
-  // entries e = threadIdx.x + q kFixThreads, taken GRP at a time: their
-  // partials (and the epilogue's own operands) are loaded together, then
-  // summed in chunk order and finished in the order of q
-  constexpr int PER = E / kFixThreads, GRP = PER < 8 ? PER : 8;
+  static_assert(E % (kFixThreads * Q) == 0, "whole passes");
+  // entries e = threadIdx.x + q kFixThreads, q in this block's share [q_lo,
+  // q_lo + PER), taken GRP at a time: their partials (and the epilogue's own
+  // operands) are loaded together, then summed in chunk order and finished
+  // in the order of q
+  constexpr int PER = E / kFixThreads / Q, GRP = PER < 8 ? PER : 8;
   static_assert(PER % GRP == 0, "whole groups");
-  for (int q0 = 0; q0 < PER; q0 += GRP) {
+  const int q_lo = qb * PER;
+  for (int q0 = q_lo; q0 < q_lo + PER; q0 += GRP) {
     float s[GRP];
 #pragma unroll
     for (int q = 0; q < GRP; ++q) s[q] = part[t * E + threadIdx.x + (q0 + q) * kFixThreads];
@@ -1255,7 +1272,7 @@ __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t
       }
     }
   }
-  epi.end_tile(tile, red);
+  epi.end_tile(qb * nTiles + tile, red);
 }
 
 // Blocks of kernel `fn` (nt threads each) the whole GPU runs at once.
@@ -1302,8 +1319,8 @@ hipError_t launch_rect(const typename G::Ops& ops, int64_t Mp, int64_t Np, int64
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (T == 0 || S == 1) return hipSuccess;
-  k_rect_fixup<G, Epi><<<dim3((unsigned)T), dim3(kFixThreads), 0, s>>>(nMT, nTiles, nb, S, part,
-                                                                       epi, gate);
+  k_rect_fixup<G, Epi><<<dim3((unsigned)(T * kFixParts<G>)), dim3(kFixThreads), 0, s>>>(
+      nMT, nTiles, nb, S, part, epi, gate);
   return hipGetLastError();
 }
 

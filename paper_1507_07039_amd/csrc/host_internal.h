@@ -99,6 +99,8 @@ struct panda_ctx {
   double* csq;
   double* zs;
   uint32_t* corder;  // launch order of the upper C tiles
+  uint32_t* corder_r;  // the same with the R tiles of the next iteration (split-BF16)
+  bool r_next;  // R holds T(P, W) of the current state (computed by the last C update)
   panda::DevState* st;
   bool b3;  // split-BF16 products
   bool packed;  // C stored as its upper tiles (packed_tile)

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -69,7 +70,8 @@ namespace panda {
 LayoutSpec single_spec(int64_t Ne, int64_t Na, bool packed_c, int32_t precision) {
   const int64_t Nep = round_up(Ne, kPadE), Nap = round_up(Na, kPadA);
   const int64_t blocks = precision == PANDA_PREC_BF16X3 ? 512 : 1024;
-  return LayoutSpec{false, rect_tiles(Nep, Nap), coop_splits(Nep, Nap, blocks), packed_c};
+  const int64_t nh = std::max(rect_tiles(Nep, Nap), rect_hpart_slots_b3(Nep, Nap));
+  return LayoutSpec{false, nh, coop_splits(Nep, Nap, blocks), packed_c};
 }
 
 // Workspace layout shared by the size queries and the contexts.
@@ -105,6 +107,9 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   DevState* st = cv.take<DevState>(1);
   // split-BF16 operand planes
   const bool b3 = precision == PANDA_PREC_BF16X3;
+  uint32_t* cor = (b3 && !spec.batched)
+                      ? cv.take<uint32_t>((size_t)(coreg_tiles(Nap) + next_r_tiles(Nep, Nap)))
+                      : nullptr;
   bf16_t* sh[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (b3) {
     sh[0] = cv.take<bf16_t>(nw);                   // W hi, row-major
@@ -134,11 +139,13 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
     c->colscr = scr;
     c->splits = splits;
     c->hpart = hp;
-    c->nh = b3 ? rect_tiles_b3(c->Nep, c->Nap) : nh;  // h partials the A + W tiling writes
+    c->nh = b3 ? rect_hpart_slots_b3(c->Nep, c->Nap) : rect_tiles(c->Nep, c->Nap);  // h partials the A + W tiling writes
     c->cstat = cs;
     c->csq = cq;
     c->zs = zs;
     c->corder = co;
+    c->corder_r = cor;
+    c->r_next = false;
     c->st = st;
     c->b3 = b3;
     c->packed = spec.packed_c;
@@ -172,6 +179,13 @@ panda_status ctx_fill_order(panda_ctx* c) {
   coreg_order_fill(c->Nap, kCoregGroup, order.data());
   HIP_TRY(hipMemcpyAsync(c->corder, order.data(), order.size() * sizeof(uint32_t),
                          hipMemcpyHostToDevice, c->stream));
+  std::vector<uint32_t> order_r;
+  if (c->corder_r) {
+    order_r.resize(order.size() + (size_t)next_r_tiles(c->Nep, c->Nap));
+    coreg_next_r_order_fill(c->Nep, c->Nap, order.data(), order_r.data());
+    HIP_TRY(hipMemcpyAsync(c->corder_r, order_r.data(), order_r.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   return PANDA_OK;
 }
@@ -291,8 +305,14 @@ panda_status enqueue_iteration(panda_ctx* c) {
   const int32_t* active = &c->st->active;
   const int32_t* run_pc = &c->st->run_pc;
   PANDA_TRY(mark(c, PANDA_PHASE_R));
-  // Eq. 3: R = T(P, W), K = N_e
-  if (c->b3)
+  // Eq. 3: R = T(P, W), K = N_e (split-BF16: computed by the last C update
+  // unless the state is new)
+  const bool next_r = c->b3 && c->corder_r;
+  if (next_r) {
+    if (!c->r_next)
+      HIP_TRY(launch_resp_tiles_b3(c->Ph, c->Pl, c->Nep, c->dP, c->Wth, c->Wtl, c->Nep, c->Nap,
+                                   c->Ne, c->Na, Wold, c->Nap, c->nP, c->nWc, c->R, active, s));
+  } else if (c->b3)
     HIP_TRY(launch_resp_b3(c->Ph, c->Pl, c->Nep, c->dP, c->Wth, c->Wtl, c->Nep, c->Nep, c->Nap,
                            c->Ne, c->Na, Wold, c->Nap, c->nP, c->nWc, c->R, c->skpart, active, s));
   else
@@ -324,9 +344,22 @@ panda_status enqueue_iteration(panda_ctx* c) {
   HIP_TRY(launch_coop_finalize(c->ppart, c->splits, c->Nep, c->nWr, c->P, c->Nep, c->Ne, c->rule,
                                c->rule.sigma_from_T ? c->Tside : nullptr, c->Ph, c->Pl, run_pc,
                                s));
+  // Eq. 6 for P, and |P_i.|^2, before the C update when it also computes
+  // the next R (which needs them)
+  if (next_r)
+    HIP_TRY(launch_diagonals(c->P, c->Nep, c->dP, c->Ne,
+                             c->rule.sigma_from_T ? c->Tside : nullptr, c->nP, c->dC, c->Nap,
+                             c->Na, c->cstat, c->rule.sigma_from_T ? c->csq : nullptr,
+                             coreg_slots(c->Nap), c->nC, c->rule, c->st, s, kDiagP));
   PANDA_TRY(mark(c, PANDA_PHASE_C));
-  // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored
-  if (c->b3)
+  // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored (and the
+  // next iteration's R = T(P, W) of the new P and W)
+  if (next_r)
+    HIP_TRY(launch_coreg_update_next_r_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Nap, c->Nap,
+                                          c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder_r,
+                                          run_pc, s, c->packed, c->Ph, c->Pl, c->dP, c->nP,
+                                          Wnew, c->Nap, c->Ne, c->R));
+  else if (c->b3)
     HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Nap,
                                    c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder,
                                    run_pc, s, c->packed));
@@ -338,7 +371,8 @@ panda_status enqueue_iteration(panda_ctx* c) {
   HIP_TRY(launch_diagonals(c->P, c->Nep, c->dP, c->Ne, c->rule.sigma_from_T ? c->Tside : nullptr,
                            c->nP, c->dC, c->Nap, c->Na, c->cstat,
                            c->rule.sigma_from_T ? c->csq : nullptr, coreg_slots(c->Nap), c->nC,
-                           c->rule, c->st, s));
+                           c->rule, c->st, s, next_r ? kDiagC : kDiagBoth));
+  c->r_next = next_r;
   PANDA_TRY(mark(c, PANDA_NPHASE));
   if (c->timing) c->npend += 1;
   c->enqueued += 1;
@@ -748,7 +782,10 @@ panda_status panda_ctx_load(panda_ctx* c, const float* W, const float* P, const 
   HIP_TRY(launch_w_norms(c->W[0], Ne, Na, Nap, Nep, c->nWr, c->nWc, c->colscr, c->Wh, c->Wl,
                          c->Wth, c->Wtl, Nep, nullptr, s));
   PANDA_TRY(ctx_fill_order(c));
+  // h partial slots the A + W product never writes add zeros
+  HIP_TRY(hipMemsetAsync(c->hpart, 0, (size_t)c->nh * sizeof(double), s));
   HIP_TRY(launch_state_init(c->st, t, s));
+  c->r_next = false;
   c->t0 = t;
   c->executed = 0;
   c->enqueued = 0;

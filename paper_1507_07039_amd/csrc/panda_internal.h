@@ -65,6 +65,9 @@ inline int64_t packed_floats(int64_t Nap) {
 // part: rect_partial_floats() floats of split-tile scratch.
 int64_t rect_tiles(int64_t Mp, int64_t Np);
 int64_t rect_tiles_b3(int64_t Mp, int64_t Np);  // tiles of the split-BF16 A + W product
+// h partial slots of the split-BF16 A + W product: one per tile and fix-up
+// block part (slots of tiles the fix-up never splits stay zero)
+int64_t rect_hpart_slots_b3(int64_t Mp, int64_t Np);
 size_t rect_partial_floats();
 
 // Out[i][j] = T(X, Y)_ij for i < M, j < N.  yd (optional): Y is square with
@@ -136,6 +139,28 @@ hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t 
                                   const double* nWcol, Rule rule, double2* cstat, double* csq,
                                   const uint32_t* order, const int32_t* gate, hipStream_t s,
                                   bool packed = false);
+// R = T(P, W) (Eq. 3) on 128 x 128 tiles (next_r_tiles of them), alone or
+// inside the C update's launch: that launch runs the C tiles and the R tiles
+// of the order coreg_next_r_order_fill builds, so the next iteration's R is
+// ready when the C update ends (P, its diagonal dP and norms nP, and W's
+// planes and column norms must be the new ones).  Both compute R the same
+// way, bit for bit.  W, R: leading dimension ldw; P's planes Nep x Nep.
+int64_t next_r_row_tiles(int64_t Nep);
+int64_t next_r_tiles(int64_t Nep, int64_t Nap);
+void coreg_next_r_order_fill(int64_t Nep, int64_t Nap, const uint32_t* corder, uint32_t* out);
+hipError_t launch_resp_tiles_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
+                                const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nap,
+                                int64_t Ne, int64_t Na, const float* W, int64_t ldw,
+                                const double* nP, const double* nWc, float* R,
+                                const int32_t* gate, hipStream_t s);
+hipError_t launch_coreg_update_next_r_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt,
+                                         int64_t Nep, float* C, int64_t ldc, int64_t Nap,
+                                         int64_t Na, const double* nWcol, Rule rule,
+                                         double2* cstat, double* csq, const uint32_t* order_r,
+                                         const int32_t* gate, hipStream_t s, bool packed,
+                                         const bf16_t* Ph, const bf16_t* Pl, const double* dP,
+                                         const double* nP, const float* W, int64_t ldw,
+                                         int64_t Ne, float* R);
 hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ldw, int64_t Nep,
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s);
@@ -167,10 +192,13 @@ hipError_t launch_finish_h(const double* hpart, int64_t n, int64_t count, DevSta
 hipError_t launch_coop_finalize(const float* part, int splits, int64_t Nep, const double* nWrow,
                                 float* P, int64_t ldp, int64_t Ne, Rule rule, float* Tside,
                                 bf16_t* Ph, bf16_t* Pl, const int32_t* gate, hipStream_t s);
+// part: kDiagBoth, or kDiagP / kDiagC for P's rows (dP, nP: they need only
+// the new P) or C's rows (dC, nC: they need the C update's row sums) alone.
+constexpr int kDiagBoth = 0, kDiagP = 1, kDiagC = 2;
 hipError_t launch_diagonals(const float* P, int64_t ldp, double* dP, int64_t Ne,
                             const float* Tside, double* nP, double* dC, int64_t ldc, int64_t Na,
                             const double2* cstat, const double* csq, int64_t nslots, double* nC,
-                            Rule rule, const DevState* st, hipStream_t s);
+                            Rule rule, const DevState* st, hipStream_t s, int part = kDiagBoth);
 // The same with the diagonal rule new = keep * old + f * N * sigma * g given
 // (closed form of several steps of Eq. 6).
 hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, int64_t Ne,

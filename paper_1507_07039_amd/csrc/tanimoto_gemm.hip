@@ -18,23 +18,64 @@ namespace {
 
 using namespace gemm;
 
+// R = T(P, W) (Eq. 3) on 128 x 128 tiles of the symmetric product's block:
+// X = P's planes (rows past N_e clamped, never stored), Y = W^T's planes, the
+// same K = N_e as the C update.  The split-BF16 form computes the next
+// iteration's R inside the C update's launch, as soon as P, its diagonal and
+// W's planes are new: its tiles fill the launch's last wave of C tiles.
+template <class G>
+struct NextR {
+  typename G::Ops ops;
+  EpiStoreT epi;
+};
+// An entry of the tile order with this bit set is R tile (entry & 0xffff,
+// (entry >> 16) & 0x7fff) (row tile of P, column tile of W); the others are
+// C tiles (I, J) = (entry & 0xffff, entry >> 16).
+constexpr uint32_t kNextRTile = 0x80000000u;
+// R's epilogue: W entries of runs of 8 rows of a column loaded together.
+constexpr int kNextRRun = 8;
+
 // The product of the tile, then the update in its epilogue (two blocks per
-// CU, so one block's epilogue overlaps the other's products).
-template <class G, bool SIGT, bool PK>
+// CU, so one block's epilogue overlaps the other's products).  With NR the
+// order also holds R tiles (kNextRTile).
+template <class G, bool SIGT, bool PK, bool NR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_coreg_update(
     typename G::Ops ops, int64_t Kp, float* __restrict__ C, int64_t ldc, int64_t Na,
     const double* __restrict__ ncol, double alpha, double2* __restrict__ cstat,
     double* __restrict__ csq, int64_t ldstat, const uint32_t* __restrict__ order,
-    const int32_t* gate) {
+    const int32_t* gate, NextR<G> nr) {
   if (gate && *gate == 0) return;
   __shared__ __align__(16) char smem[coreg_smem_bytes<G, SIGT>()];
   const uint32_t ij = order[xcd_tile(blockIdx.x, gridDim.x)];
+  if constexpr (NR) {
+    if (ij & kNextRTile) {
+      const int64_t m0 = (int64_t)(ij & 0xffff) * kCB, n0 = (int64_t)((ij >> 16) & 0x7fff) * kCB;
+      G g;
+      g.run(nr.ops, m0, n0, 0, Kp, smem);
+      store_t_tile_xd<kNextRRun>(g, smem, nr.epi, m0, n0);
+      return;
+    }
+  }
   const int64_t I = ij & 0xffff, J = ij >> 16;
   const int64_t m0 = I * kCB, n0 = J * kCB;
   const double nval = coreg_norm_load(ncol, I, J, Na);
   G g;
   g.run(ops, m0, n0, 0, Kp, smem);
   coreg_epilogue<SIGT, PK>(g, smem, I, J, C, ldc, Na, nval, alpha, cstat, csq, ldstat);
+}
+
+// R alone on the same tiles (same arithmetic, so R is the same bit for bit
+// whichever launch computed it): block b is tile (b % nRT, b / nRT).
+template <class G>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_resp_tiles(
+    NextR<G> nr, int64_t Kp, int64_t nRT, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  __shared__ __align__(16) char smem[G::MAIN_BYTES];
+  const int64_t b = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t m0 = (b % nRT) * kCB, n0 = (b / nRT) * kCB;
+  G g;
+  g.run(nr.ops, m0, n0, 0, Kp, smem);
+  store_t_tile_xd<kNextRRun>(g, smem, nr.epi, m0, n0);
 }
 
 // Pearson correlations: one upper 128 x 128 tile of Z Z^T per block, both
@@ -84,6 +125,10 @@ __global__ __launch_bounds__(kThreads) void k_coop_partial(typename G::Ops ops, 
 int64_t rect_tiles(int64_t Mp, int64_t Np) { return (Mp / RectF32::BM) * (Np / RectF32::BN); }
 int64_t rect_tiles_b3(int64_t Mp, int64_t Np) {
   return ((Mp + RectB3D::BM - 1) / RectB3D::BM) * (Np / RectB3D::BN);
+}
+static_assert(kFixParts<RectB3D> == kFixParts<RectB3DP>, "one slot layout for both C layouts");
+int64_t rect_hpart_slots_b3(int64_t Mp, int64_t Np) {
+  return rect_tiles_b3(Mp, Np) * kFixParts<RectB3D>;
 }
 size_t rect_partial_floats() {
   return (size_t)2 * (size_t)kMaxStreamKBlocks * RectF32::BM * RectF32::BN;
@@ -168,30 +213,32 @@ void coreg_order_fill(int64_t Nap, int group, uint32_t* out) {
           out[k++] = (uint32_t)(I | (J << 16));
 }
 
-template <class G, bool PK>
+template <class G, bool PK, bool NR>
 static hipError_t coreg_launch_pk(const typename G::Ops& ops, int64_t Nep, float* C, int64_t ldc,
                                   int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
                                   double2* cstat, double* csq, const uint32_t* order,
-                                  const int32_t* gate, hipStream_t s) {
-  const unsigned nb = (unsigned)coreg_tiles(Nap);
+                                  const int32_t* gate, hipStream_t s, const NextR<G>& nr,
+                                  int64_t extra) {
+  const unsigned nb = (unsigned)(coreg_tiles(Nap) + extra);
   if (rule.sigma_from_T)
-    k_coreg_update<G, true, PK><<<dim3(nb), dim3(kThreads), 0, s>>>(
-        ops, Nep, C, ldc, Na, nWcol, rule.alpha, cstat, csq, Nap, order, gate);
+    k_coreg_update<G, true, PK, NR><<<dim3(nb), dim3(kThreads), 0, s>>>(
+        ops, Nep, C, ldc, Na, nWcol, rule.alpha, cstat, csq, Nap, order, gate, nr);
   else
-    k_coreg_update<G, false, PK><<<dim3(nb), dim3(kThreads), 0, s>>>(
-        ops, Nep, C, ldc, Na, nWcol, rule.alpha, cstat, csq, Nap, order, gate);
+    k_coreg_update<G, false, PK, NR><<<dim3(nb), dim3(kThreads), 0, s>>>(
+        ops, Nep, C, ldc, Na, nWcol, rule.alpha, cstat, csq, Nap, order, gate, nr);
   return hipGetLastError();
 }
 
-template <class G>
+template <class G, bool NR = false>
 static hipError_t coreg_launch(const typename G::Ops& ops, int64_t Nep, float* C, int64_t ldc,
                                int64_t Nap, int64_t Na, const double* nWcol, Rule rule,
                                double2* cstat, double* csq, const uint32_t* order,
-                               const int32_t* gate, hipStream_t s, bool packed) {
-  return packed ? coreg_launch_pk<G, true>(ops, Nep, C, ldc, Nap, Na, nWcol, rule, cstat, csq,
-                                           order, gate, s)
-                : coreg_launch_pk<G, false>(ops, Nep, C, ldc, Nap, Na, nWcol, rule, cstat, csq,
-                                            order, gate, s);
+                               const int32_t* gate, hipStream_t s, bool packed,
+                               const NextR<G>& nr = NextR<G>{}, int64_t extra = 0) {
+  return packed ? coreg_launch_pk<G, true, NR>(ops, Nep, C, ldc, Nap, Na, nWcol, rule, cstat,
+                                               csq, order, gate, s, nr, extra)
+                : coreg_launch_pk<G, false, NR>(ops, Nep, C, ldc, Nap, Na, nWcol, rule, cstat,
+                                                csq, order, gate, s, nr, extra);
 }
 
 hipError_t launch_coreg_update(const float* W, int64_t ldw, int64_t Nep, float* C, int64_t ldc,
@@ -212,6 +259,64 @@ hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t 
   // FP32 C is written; the next A product splits it while staging.
   return coreg_launch<SymB3>(OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol,
                              rule, cstat, csq, order, gate, s, packed);
+}
+
+int64_t next_r_row_tiles(int64_t Nep) { return (Nep + kCB - 1) / kCB; }
+int64_t next_r_tiles(int64_t Nep, int64_t Nap) { return next_r_row_tiles(Nep) * (Nap / kCB); }
+
+void coreg_next_r_order_fill(int64_t Nep, int64_t Nap, const uint32_t* corder, uint32_t* out) {
+  // each XCD's share of the launch (the ranges xcd_tile maps block indices
+  // to) takes its share of the C tiles in their order, then its share of the
+  // R tiles, column tile by column tile (R tiles of one column share W's
+  // strip): the R tiles fill the end of every XCD's work
+  const int64_t nC = coreg_tiles(Nap), nRT = next_r_row_tiles(Nep), nR = next_r_tiles(Nep, Nap);
+  const int64_t n = nC + nR;
+  int64_t ci = 0, ri = 0, pos = 0;
+  for (int64_t x = 0; x < 8; ++x) {
+    const int64_t size = n / 8 + (x < n % 8 ? 1 : 0);
+    const int64_t nr = nR / 8 + (x < nR % 8 ? 1 : 0);
+    for (int64_t k = 0; k < size - nr; ++k) out[pos++] = corder[ci++];
+    for (int64_t k = 0; k < nr; ++k, ++ri)
+      out[pos++] = kNextRTile | (uint32_t)(ri % nRT) | ((uint32_t)(ri / nRT) << 16);
+  }
+}
+
+static NextR<SymB3> next_r_args(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
+                                const double* nP, const bf16_t* Wth, const bf16_t* Wtl,
+                                int64_t ldwt, const float* W, int64_t ldw, int64_t Ne, int64_t Na,
+                                const double* nWc, float* R) {
+  NextR<SymB3> nr;
+  nr.ops = OpsB3{Ph, Pl, ldp, Wth, Wtl, ldwt, ldp};  // P has ldp (= N_e padded) rows
+  nr.epi = EpiStoreT{R, ldw, Ne, Na, nP, nWc, dP, W, ldw};
+  return nr;
+}
+
+hipError_t launch_resp_tiles_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
+                                const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nap,
+                                int64_t Ne, int64_t Na, const float* W, int64_t ldw,
+                                const double* nP, const double* nWc, float* R,
+                                const int32_t* gate, hipStream_t s) {
+  if (ldp % SymB3::BK || Nap % kCB) return hipErrorInvalidValue;
+  const int64_t nRT = next_r_row_tiles(ldp);
+  k_resp_tiles<SymB3><<<dim3((unsigned)next_r_tiles(ldp, Nap)), dim3(kThreads), 0, s>>>(
+      next_r_args(Ph, Pl, ldp, dP, nP, Wth, Wtl, ldwt, W, ldw, Ne, Na, nWc, R), ldp, nRT, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_coreg_update_next_r_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt,
+                                         int64_t Nep, float* C, int64_t ldc, int64_t Nap,
+                                         int64_t Na, const double* nWcol, Rule rule,
+                                         double2* cstat, double* csq, const uint32_t* order_r,
+                                         const int32_t* gate, hipStream_t s, bool packed,
+                                         const bf16_t* Ph, const bf16_t* Pl, const double* dP,
+                                         const double* nP, const float* W, int64_t ldw,
+                                         int64_t Ne, float* R) {
+  if (Nep % SymB3::BK || Nap % kCB) return hipErrorInvalidValue;
+  return coreg_launch<SymB3, true>(
+      OpsB3{Wth, Wtl, ldwt, Wth, Wtl, ldwt}, Nep, C, ldc, Nap, Na, nWcol, rule, cstat, csq,
+      order_r, gate, s, packed,
+      next_r_args(Ph, Pl, Nep, dP, nP, Wth, Wtl, ldwt, W, ldw, Ne, Na, nWcol, R),
+      next_r_tiles(Nep, Nap));
 }
 
 int coop_splits(int64_t Nep, int64_t Nap, int64_t blocks) {

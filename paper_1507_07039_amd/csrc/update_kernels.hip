@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     const float* __restrict__ Tside, double* __restrict__ nP, double* __restrict__ dC,
     int64_t ldc, int64_t Na, const double2* __restrict__ cstat, const double* __restrict__ csq,
     int64_t nslots, double* __restrict__ nC, double alpha, int32_t diag_alpha, int32_t n_own,
-    int32_t ddof, const DevState* st, int32_t sched, double keep, double g) {
+    int32_t ddof, const DevState* st, int32_t sched, double keep, double g, int64_t b0) {
   __shared__ double red[4];
   if (st->run_pc == 0) return;
   upd::DiagRule dr = upd::diag_rule(alpha, diag_alpha, n_own, ddof, st->t);
@@ -43,15 +43,16 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
     dr.keep = keep;
     dr.g = g;
   }
-  if ((int64_t)blockIdx.x < Ne) {
-    upd::diag_p_row(blockIdx.x, P, ldp, dP, Ne, Na, Tside, nP, dr, red);
+  const int64_t blk = (int64_t)blockIdx.x + b0;  // launches of one part start at b0
+  if (blk < Ne) {
+    upd::diag_p_row(blk, P, ldp, dP, Ne, Na, Tside, nP, dr, red);
     return;
   }
   // C: 64 rows per block; wave w adds slots w, w + 4, ... and wave 0 adds
   // the four partial sums in wave order
   __shared__ double3 part[kRT / 64][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t r = ((int64_t)blockIdx.x - Ne) * 64 + lane;
+  const int64_t r = (blk - Ne) * 64 + lane;
   double s1 = 0.0, s2 = 0.0, c2 = 0.0;
   if (r < Na) {
     for (int64_t sl = w; sl < nslots; sl += kRT / 64) {
@@ -495,11 +496,13 @@ hipError_t launch_split_offdiag(const float* M, int64_t n, int64_t ld, bf16_t* M
 hipError_t launch_diagonals(const float* P, int64_t ldp, double* dP, int64_t Ne,
                             const float* Tside, double* nP, double* dC, int64_t ldc, int64_t Na,
                             const double2* cstat, const double* csq, int64_t nslots, double* nC,
-                            Rule rule, const DevState* st, hipStream_t s) {
-  const int64_t nb = Ne + (Na + 63) / 64;
+                            Rule rule, const DevState* st, hipStream_t s, int part) {
+  const int64_t b0 = part == kDiagC ? Ne : 0;
+  const int64_t nb = (part == kDiagC ? 0 : Ne) + (part == kDiagP ? 0 : (Na + 63) / 64);
+  if (nb == 0) return hipSuccess;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
-                                                 rule.n_own, rule.sigma_ddof, st, 0, 0.0, 0.0);
+                                                 rule.n_own, rule.sigma_ddof, st, 0, 0.0, 0.0, b0);
   return hipGetLastError();
 }
 
@@ -511,7 +514,7 @@ hipError_t launch_diagonals_schedule(const float* P, int64_t ldp, double* dP, in
   const int64_t nb = Ne + (Na + 63) / 64;
   k_diagonals<<<dim3((unsigned)nb), kRT, 0, s>>>(P, ldp, dP, Ne, Tside, nP, dC, ldc, Na, cstat,
                                                  csq, nslots, nC, rule.alpha, rule.diag_alpha,
-                                                 rule.n_own, rule.sigma_ddof, st, 1, keep, g);
+                                                 rule.n_own, rule.sigma_ddof, st, 1, keep, g, 0);
   return hipGetLastError();
 }
 

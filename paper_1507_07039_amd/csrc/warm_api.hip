@@ -68,6 +68,7 @@ panda_status panda_ws_features(panda_ctx* c, const float* omegaP, const float* o
   FeatLayout L;
   feat_layout(Ne, Na, static_cast<char*>(workspace), &L);
   hipStream_t s = c->stream;
+  c->r_next = false;  // R serves as scratch below
   const float* W0 = c->W[c->executed & 1];
   // one-step similarities R0 = T(P0, W0) (into R) and A0 = T(W0, C0) (into S)
   HIP_TRY(launch_resp(c->P, Nep, c->dP, W0, Nap, Nep, Nap, Ne, Na, c->nP, c->nWc, c->R,
@@ -225,6 +226,7 @@ panda_status panda_ws_init(panda_ctx* c, const float* Wpred, int32_t t0) {
   c->t0 = t0;
   c->executed = 0;
   c->enqueued = 0;
+  c->r_next = false;
   c->host->t = t0;
   c->host->active = 1;
   c->host->conv = 0;
