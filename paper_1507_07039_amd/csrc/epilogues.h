@@ -169,6 +169,10 @@ using SymF32 = BlockGemm<128, 128, 2, 2, false, false, 16>;
 using SymB3 = BlockGemmB3P<128, 128, 2, 2, false, 2>;  // direct-to-LDS, two stages (two blocks per CU)
 using CoopF32 = BlockGemm<64, 64, 2, 2, true, true, 32>;
 using CoopB3 = BlockGemmB3<64, 64, 2, 2>;
+// The single-network W W^T partials: each block's K chunk is ~70 K-tiles, long
+// enough for the direct-to-LDS pipeline with three stages (two K-tiles in
+// flight while one is multiplied); same products in the same order.
+using CoopB3P = BlockGemmB3P<64, 64, 2, 2, false, 3>;
 static_assert(CoopF32::BK == CoopB3::BK, "one K split");
 
 // ------------------------------------------------------------------------

@@ -344,7 +344,7 @@ hipError_t launch_coop_partial_b3(const bf16_t* Wh, const bf16_t* Wl, int64_t ld
                                   int64_t Nap, int splits, float* part, const int32_t* gate,
                                   hipStream_t s) {
   const int64_t nT = Nep / kPB, nU = nT * (nT + 1) / 2;
-  k_coop_partial<CoopB3><<<dim3((unsigned)(nU * splits)), dim3(kThreads), 0, s>>>(
+  k_coop_partial<CoopB3P><<<dim3((unsigned)(nU * splits)), dim3(kThreads), 0, s>>>(
       OpsB3{Wh, Wl, ldw, Wh, Wl, ldw}, Nep, nU, coop_chunk(Nap, splits), Nap, part, gate);
   return hipGetLastError();
 }

@@ -43,8 +43,18 @@ __device__ __forceinline__ void finish_h(const double* __restrict__ hpart, int64
     if (threadIdx.x == 0) st->run_pc = 0;
     return;
   }
+  // this thread's partials i, i + kUT, ... added in that order, eight loads
+  // in flight before the first of them is added
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kUT) s += hpart[i];
+  int64_t i = threadIdx.x;
+  for (; i + 7 * kUT < n; i += 8 * kUT) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = hpart[i + k * kUT];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  for (; i < n; i += kUT) s += hpart[i];
   const double tot = block_sum(s, red);
   if (threadIdx.x == 0) {
     const double h = tot / (double)count;
@@ -69,8 +79,20 @@ __device__ __forceinline__ void coop_finalize_entry(
   if (e >= Ne * Ne) return;
   const int64_t i = e / Ne, j = e % Ne;
   if (i >= j) return;
+  // the partials in split order, eight loads in flight before the first of
+  // them is added
   double dot = 0.0;
-  for (int s = 0; s < splits; ++s) dot += (double)part[(int64_t)s * Nep * Nep + i * Nep + j];
+  const float* pe = part + i * Nep + j;
+  const int64_t ps = Nep * Nep;
+  int s = 0;
+  for (; s + 8 <= splits; s += 8) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = pe[(int64_t)(s + k) * ps];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dot += (double)v[k];
+  }
+  for (; s < splits; ++s) dot += (double)pe[(int64_t)s * ps];
   const double den = nW[i] + nW[j] - fabs(dot);
   const double tv = den > 0.0 ? dot / sqrt(den) : 0.0;
   const float v = (float)((1.0 - alpha) * (double)P[i * ldp + j] + alpha * tv);

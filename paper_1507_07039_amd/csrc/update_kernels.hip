@@ -55,7 +55,26 @@ __global__ __launch_bounds__(kRT) void k_diagonals(
   const int64_t r = (blk - Ne) * 64 + lane;
   double s1 = 0.0, s2 = 0.0, c2 = 0.0;
   if (r < Na) {
-    for (int64_t sl = w; sl < nslots; sl += kRT / 64) {
+    // slots w, w + 4, ..., added in that order; eight slots' loads are in
+    // flight before the first of them is added
+    constexpr int64_t kStep = kRT / 64, kU = 8;
+    int64_t sl = w;
+    for (; sl + (kU - 1) * kStep < nslots; sl += kU * kStep) {
+      double2 v[kU];
+      double q[kU];
+#pragma unroll
+      for (int k = 0; k < kU; ++k) {
+        v[k] = cstat[(sl + k * kStep) * ldc + r];
+        q[k] = csq ? csq[(sl + k * kStep) * ldc + r] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kU; ++k) {
+        s1 += v[k].x;
+        s2 += v[k].y;
+        if (csq) c2 += q[k];
+      }
+    }
+    for (; sl < nslots; sl += kStep) {
       const double2 v = cstat[sl * ldc + r];
       s1 += v.x;
       s2 += v.y;
@@ -264,8 +283,17 @@ __global__ __launch_bounds__(kRT) void k_w_norms_sum(const double* __restrict__ 
   }
   const int64_t c = ((int64_t)blockIdx.x - Nep) * kRT + threadIdx.x;
   if (c >= Nap) return;
+  // blocks in order; eight blocks' loads in flight before the first is added
   double s = 0.0;
-  for (int64_t b = 0; b < nrb; ++b) s += colpart[b * Nap + c];
+  int64_t b = 0;
+  for (; b + 8 <= nrb; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = colpart[(b + k) * Nap + c];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  for (; b < nrb; ++b) s += colpart[b * Nap + c];
   nc[c] = s;
 }
 

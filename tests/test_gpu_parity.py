@@ -341,16 +341,21 @@ def test_run_one_iteration_ahead_equals_stepwise(torch, pd, oracle, precision):
             assert r.status == pd.NOT_CONVERGED and r.iters == cap
 
 
-def test_resume_equals_straight_run(torch, pd, oracle):
+@pytest.mark.parametrize("precision,packed", [(0, 0), (1, 0), (1, 1)])
+def test_resume_equals_straight_run(torch, pd, oracle, precision, packed):
+    """A state stored after 9 iterations and loaded into a new context runs to
+    the same result bit for bit (split-BF16: R after the load comes from its
+    own launch, later R from the C update's launch, with the same arithmetic)."""
     W, P, C = prep(oracle, *I.workload_priors(I.SMALL))
-    straight = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C))
-    ctx = pd.Context(*W.shape)
+    opts = pd.default_options(precision=precision, packed_c=packed)
+    straight = pd.run(cuda(torch, W), cuda(torch, P), cuda(torch, C), opts=opts)
+    ctx = pd.Context(*W.shape, opts)
     ctx.load(cuda(torch, W), cuda(torch, P), cuda(torch, C))
     for _ in range(9):
         ctx.iterate()
     Wk, Pk, Ck, hk, tk = ctx.state()
     assert tk == 9
-    ctx2 = pd.Context(*W.shape)
+    ctx2 = pd.Context(*W.shape, opts)
     ctx2.load(Wk, Pk, Ck, t=tk)
     t = tk
     while True:
