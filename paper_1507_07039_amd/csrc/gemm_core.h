@@ -1105,6 +1105,15 @@ template <class E, class = void>
 struct has_fetch : std::false_type {};
 template <class E>
 struct has_fetch<E, std::void_t<decltype(&E::fetch)>> : std::true_type {};
+// Epi::Pre where the epilogue fetches its operands ahead, else a placeholder.
+template <class E, class = void>
+struct fetch_t {
+  struct type {};
+};
+template <class E>
+struct fetch_t<E, std::void_t<typename E::Pre>> {
+  using type = typename E::Pre;
+};
 template <class G, class = void>
 struct prefetch_epi : std::false_type {};
 template <class G>
@@ -1237,12 +1246,33 @@ __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t
   static_assert(PER % GRP == 0, "whole groups");
   const int q_lo = qb * PER;
   for (int q0 = q_lo; q0 < q_lo + PER; q0 += GRP) {
+    // the epilogue's own operands first, then the partials of up to two
+    // chunks at a time, all in flight before they are added in chunk order
+    typename fetch_t<Epi>::type pre[GRP];
+    if constexpr (has_fetch<Epi>::value) {
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = threadIdx.x + (q0 + q) * kFixThreads;
+        pre[q] = epi.fetch(m0 + e / G::BN, n0 + e % G::BN);
+      }
+    }
     float s[GRP];
 #pragma unroll
     for (int q = 0; q < GRP; ++q) s[q] = part[t * E + threadIdx.x + (q0 + q) * kFixThreads];
-    for (int64_t c = 1; c < S; ++c)
+    for (int64_t c = 1; c < S; c += 2) {
+      float v[2][GRP];
 #pragma unroll
-      for (int q = 0; q < GRP; ++q) s[q] += part[(c * T + t) * E + threadIdx.x + (q0 + q) * kFixThreads];
+      for (int k = 0; k < 2; ++k)
+        if (c + k < S)
+#pragma unroll
+          for (int q = 0; q < GRP; ++q)
+            v[k][q] = part[((c + k) * T + t) * E + threadIdx.x + (q0 + q) * kFixThreads];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (c + k < S)
+#pragma unroll
+          for (int q = 0; q < GRP; ++q) s[q] += v[k][q];
+    }
     if constexpr (has_block<Epi>::value && !has_fetch<Epi>::value) {
       int64_t rs[GRP], cs[GRP];
 #pragma unroll
@@ -1253,12 +1283,6 @@ __global__ __launch_bounds__(kFixThreads) void k_rect_fixup(int64_t nMT, int64_t
       }
       epi.template block<GRP>(rs, cs, s);
     } else if constexpr (has_fetch<Epi>::value) {
-      typename Epi::Pre pre[GRP];
-#pragma unroll
-      for (int q = 0; q < GRP; ++q) {
-        const int e = threadIdx.x + (q0 + q) * kFixThreads;
-        pre[q] = epi.fetch(m0 + e / G::BN, n0 + e % G::BN);
-      }
 #pragma unroll
       for (int q = 0; q < GRP; ++q) {
         const int e = threadIdx.x + (q0 + q) * kFixThreads;
