@@ -83,7 +83,8 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   float* w0 = cv.take<float>(nw);
   float* w1 = cv.take<float>(nw);
   float* r = cv.take<float>(nw);
-  float* p = cv.take<float>((size_t)Nep * Nep);
+  // slack after P: the next-R tiles of the FP32 form read its last row past N_e
+  float* p = cv.take<float>((size_t)Nep * Nep + (size_t)next_r_p_slack(Nep));
   float* cc = cv.take<float>(spec.packed_c ? (size_t)packed_floats(Nap) : (size_t)Nap * Nap);
   float* ts = cv.take<float>((size_t)Nep * Nep);
   const int splits = (int)spec.ppart_splits;
@@ -107,7 +108,7 @@ size_t ctx_layout(int64_t Ne, int64_t Na, int32_t precision, const LayoutSpec& s
   DevState* st = cv.take<DevState>(1);
   // split-BF16 operand planes
   const bool b3 = precision == PANDA_PREC_BF16X3;
-  uint32_t* cor = (b3 && !spec.batched)
+  uint32_t* cor = !spec.batched
                       ? cv.take<uint32_t>((size_t)(coreg_tiles(Nap) + next_r_tiles(Nep, Nap)))
                       : nullptr;
   bf16_t* sh[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -305,13 +306,19 @@ panda_status enqueue_iteration(panda_ctx* c) {
   const int32_t* active = &c->st->active;
   const int32_t* run_pc = &c->st->run_pc;
   PANDA_TRY(mark(c, PANDA_PHASE_R));
-  // Eq. 3: R = T(P, W), K = N_e (split-BF16: computed by the last C update
-  // unless the state is new)
-  const bool next_r = c->b3 && c->corder_r;
+  // Eq. 3: R = T(P, W), K = N_e (computed by the last C update unless the
+  // state is new)
+  const bool next_r = c->corder_r != nullptr;
   if (next_r) {
-    if (!c->r_next)
-      HIP_TRY(launch_resp_tiles_b3(c->Ph, c->Pl, c->Nep, c->dP, c->Wth, c->Wtl, c->Nep, c->Nap,
-                                   c->Ne, c->Na, Wold, c->Nap, c->nP, c->nWc, c->R, active, s));
+    if (!c->r_next) {
+      if (c->b3)
+        HIP_TRY(launch_resp_tiles_b3(c->Ph, c->Pl, c->Nep, c->dP, c->Wth, c->Wtl, c->Nep,
+                                     c->Nap, c->Ne, c->Na, Wold, c->Nap, c->nP, c->nWc, c->R,
+                                     active, s));
+      else
+        HIP_TRY(launch_resp_tiles(c->P, c->Nep, c->dP, c->Nap, c->Ne, c->Na, Wold, c->Nap,
+                                  c->nP, c->nWc, c->R, active, s));
+    }
   } else if (c->b3)
     HIP_TRY(launch_resp_b3(c->Ph, c->Pl, c->Nep, c->dP, c->Wth, c->Wtl, c->Nep, c->Nep, c->Nap,
                            c->Ne, c->Na, Wold, c->Nap, c->nP, c->nWc, c->R, c->skpart, active, s));
@@ -354,11 +361,15 @@ panda_status enqueue_iteration(panda_ctx* c) {
   PANDA_TRY(mark(c, PANDA_PHASE_C));
   // Eq. 5, C: T(W_.k, W_.j) of the new W, upper tiles, mirrored (and the
   // next iteration's R = T(P, W) of the new P and W)
-  if (next_r)
+  if (next_r && c->b3)
     HIP_TRY(launch_coreg_update_next_r_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Nap, c->Nap,
                                           c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder_r,
                                           run_pc, s, c->packed, c->Ph, c->Pl, c->dP, c->nP,
                                           Wnew, c->Nap, c->Ne, c->R));
+  else if (next_r)
+    HIP_TRY(launch_coreg_update_next_r(Wnew, c->Nap, c->Nep, c->C, c->Nap, c->Nap, c->Na, c->nWc,
+                                       c->rule, c->cstat, c->csq, c->corder_r, run_pc, s,
+                                       c->packed, c->P, c->dP, c->nP, c->Ne, c->R));
   else if (c->b3)
     HIP_TRY(launch_coreg_update_b3(c->Wth, c->Wtl, c->Nep, c->Nep, c->C, c->Nap,
                                    c->Nap, c->Na, c->nWc, c->rule, c->cstat, c->csq, c->corder,

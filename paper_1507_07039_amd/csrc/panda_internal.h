@@ -148,6 +148,19 @@ hipError_t launch_coreg_update_b3(const bf16_t* Wth, const bf16_t* Wtl, int64_t 
 int64_t next_r_row_tiles(int64_t Nep);
 int64_t next_r_tiles(int64_t Nep, int64_t Nap);
 void coreg_next_r_order_fill(int64_t Nep, int64_t Nap, const uint32_t* corder, uint32_t* out);
+// FP32 form: P is read k-major and needs next_r_p_slack(Nep) floats of
+// readable memory after its Nep x Nep entries.
+int64_t next_r_p_slack(int64_t Nep);
+hipError_t launch_resp_tiles(const float* P, int64_t ldp, const double* dP, int64_t Nap,
+                             int64_t Ne, int64_t Na, const float* W, int64_t ldw,
+                             const double* nP, const double* nWc, float* R, const int32_t* gate,
+                             hipStream_t s);
+hipError_t launch_coreg_update_next_r(const float* W, int64_t ldw, int64_t Nep, float* C,
+                                      int64_t ldc, int64_t Nap, int64_t Na, const double* nWcol,
+                                      Rule rule, double2* cstat, double* csq,
+                                      const uint32_t* order_r, const int32_t* gate, hipStream_t s,
+                                      bool packed, const float* P, const double* dP,
+                                      const double* nP, int64_t Ne, float* R);
 hipError_t launch_resp_tiles_b3(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
                                 const bf16_t* Wth, const bf16_t* Wtl, int64_t ldwt, int64_t Nap,
                                 int64_t Ne, int64_t Na, const float* W, int64_t ldw,

@@ -281,6 +281,41 @@ void coreg_next_r_order_fill(int64_t Nep, int64_t Nap, const uint32_t* corder, u
   }
 }
 
+// FP32 form: X = P read k-major (P[k][i] = P[i][k]); the rows of the last
+// row tile past N_e read past row N_e - 1 into the slack P is allocated with
+// (next_r_p_slack floats), and their outputs are never stored.
+static NextR<SymF32> next_r_args_f32(const float* P, int64_t ldp, const double* dP,
+                                     const double* nP, const float* W, int64_t ldw, int64_t Ne,
+                                     int64_t Na, const double* nWc, float* R) {
+  NextR<SymF32> nr;
+  nr.ops = OpsF32{P, ldp, W, ldw};
+  nr.epi = EpiStoreT{R, ldw, Ne, Na, nP, nWc, dP, W, ldw};
+  return nr;
+}
+int64_t next_r_p_slack(int64_t Nep) { return next_r_row_tiles(Nep) * kCB - Nep; }
+
+hipError_t launch_resp_tiles(const float* P, int64_t ldp, const double* dP, int64_t Nap,
+                             int64_t Ne, int64_t Na, const float* W, int64_t ldw,
+                             const double* nP, const double* nWc, float* R, const int32_t* gate,
+                             hipStream_t s) {
+  if (ldp % SymF32::BK || Nap % kCB) return hipErrorInvalidValue;
+  k_resp_tiles<SymF32><<<dim3((unsigned)next_r_tiles(ldp, Nap)), dim3(kThreads), 0, s>>>(
+      next_r_args_f32(P, ldp, dP, nP, W, ldw, Ne, Na, nWc, R), ldp, next_r_row_tiles(ldp), gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_coreg_update_next_r(const float* W, int64_t ldw, int64_t Nep, float* C,
+                                      int64_t ldc, int64_t Nap, int64_t Na, const double* nWcol,
+                                      Rule rule, double2* cstat, double* csq,
+                                      const uint32_t* order_r, const int32_t* gate, hipStream_t s,
+                                      bool packed, const float* P, const double* dP,
+                                      const double* nP, int64_t Ne, float* R) {
+  if (Nep % SymF32::BK || Nap % kCB) return hipErrorInvalidValue;
+  return coreg_launch<SymF32, true>(
+      OpsF32{W, ldw, W, ldw}, Nep, C, ldc, Nap, Na, nWcol, rule, cstat, csq, order_r, gate, s,
+      packed, next_r_args_f32(P, Nep, dP, nP, W, ldw, Ne, Na, nWcol, R), next_r_tiles(Nep, Nap));
+}
+
 static NextR<SymB3> next_r_args(const bf16_t* Ph, const bf16_t* Pl, int64_t ldp, const double* dP,
                                 const double* nP, const bf16_t* Wth, const bf16_t* Wtl,
                                 int64_t ldwt, const float* W, int64_t ldw, int64_t Ne, int64_t Na,

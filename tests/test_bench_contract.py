@@ -20,8 +20,9 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_only_for_the_profiled_sources(monkeypatch):
     vals = bench.recorded_traffic()
-    if vals:  # the summary matches the sources: every kernel's bytes are there
-        assert {"fp32_aw_traffic_bytes", "b3_aw_traffic_bytes"} <= set(vals)
+    if vals:  # the summary matches the sources: both forms' A + W bytes are there
+        chosen = "b3p" if bench.CHOSEN_OPTS.get("packed_c") else "b3"
+        assert {"fp32_aw_traffic_bytes", chosen + "_aw_traffic_bytes"} <= set(vals)
         assert all(v > 0 for v in vals.values())
     monkeypatch.setattr(bench, "csrc_digest", lambda: "0" * 64)
     assert bench.recorded_traffic() == {}
