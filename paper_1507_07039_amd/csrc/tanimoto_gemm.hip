@@ -33,7 +33,7 @@ struct NextR {
 // C tiles (I, J) = (entry & 0xffff, entry >> 16).
 constexpr uint32_t kNextRTile = 0x80000000u;
 // R's epilogue: W entries of runs of 8 rows of a column loaded together.
-constexpr int kNextRRun = 8;
+constexpr int kNextRRun = 16;
 
 // The product of the tile, then the update in its epilogue (two blocks per
 // CU, so one block's epilogue overlaps the other's products).  With NR the
