@@ -32,7 +32,7 @@ struct NextR {
 // (entry >> 16) & 0x7fff) (row tile of P, column tile of W); the others are
 // C tiles (I, J) = (entry & 0xffff, entry >> 16).
 constexpr uint32_t kNextRTile = 0x80000000u;
-// R's epilogue: W entries of runs of 8 rows of a column loaded together.
+// R's epilogue: W entries of runs of 16 rows of a column loaded together.
 constexpr int kNextRRun = 16;
 
 // The product of the tile, then the update in its epilogue (two blocks per
