@@ -18,11 +18,13 @@ namespace {
 
 using namespace gemm;
 
-// R = T(P, W) (Eq. 3) on 128 x 128 tiles of the symmetric product's block:
-// X = P's planes (rows past N_e clamped, never stored), Y = W^T's planes, the
-// same K = N_e as the C update.  The split-BF16 form computes the next
-// iteration's R inside the C update's launch, as soon as P, its diagonal and
-// W's planes are new: its tiles fill the launch's last wave of C tiles.
+// R = T(P, W) (Eq. 3) on 128 x 128 tiles of the symmetric product's block,
+// the same K = N_e as the C update: X = P (split-BF16: P's planes with rows
+// past N_e clamped; FP32: P read k-major, rows past N_e read into slack),
+// Y = W^T (its planes) or W; rows past N_e are never stored.  Both forms
+// compute the next iteration's R inside the C update's launch, as soon as P,
+// its diagonal and W's norms (and planes) are new: its tiles fill the
+// launch's last wave of C tiles.
 template <class G>
 struct NextR {
   typename G::Ops ops;
