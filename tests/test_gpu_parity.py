@@ -341,7 +341,7 @@ def test_run_one_iteration_ahead_equals_stepwise(torch, pd, oracle, precision):
             assert r.status == pd.NOT_CONVERGED and r.iters == cap
 
 
-@pytest.mark.parametrize("precision,packed", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("precision,packed", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_resume_equals_straight_run(torch, pd, oracle, precision, packed):
     """A state stored after 9 iterations and loaded into a new context runs to
     the same result bit for bit (split-BF16: R after the load comes from its
